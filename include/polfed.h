@@ -1,0 +1,296 @@
+/*
+ * polfed.h -- C ABI of the MI355X POLFED library (polynomially filtered exact
+ * diagonalization of sparse many-body Hamiltonians).
+ *
+ * Problem statement (paper, Sec. 4.6): given a sparse Hamiltonian H, a target
+ * energy lambda and a number of eigenpairs N_ev, return the N_ev eigenpairs
+ * of H nearest lambda.  The method (Secs. 3.2, 4.1-4.4) rescales H to
+ * H~ = (H - E_c)/dE (eq. rescaledMatrix), builds the Chebyshev delta filter
+ * P(H~) = (1/chi) sum_{n=0}^{K} c_n T_n(H~) (eqs. transformation and
+ * transformationCoefficients), and runs Lanczos on P(H~) with full
+ * reorthogonalization, applying P(H~) by the Clenshaw recurrence
+ * (eq. clenshaw_chebyshev_prod): K sparse mat-vecs per Lanczos step.
+ *
+ * Conventions shared by every call
+ *  - Every function returns a polfed_status: 0 = OK, > 0 warning, < 0 error.
+ *    No function throws or aborts.  After an error, polfed_last_error()
+ *    returns a message for the calling thread (owned by the library, valid
+ *    until the next call on that thread).
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory on the context's device (e.g. torch tensor data_ptr()).
+ *  - Vectors are contiguous; blocks of vectors are column-major with leading
+ *    dimension D (column j starts at j*D).
+ *  - Work is ordered on the context's HIP stream.  Calls that return results
+ *    in host memory synchronize that stream; calls that only write device
+ *    buffers are asynchronous unless stated otherwise.
+ *  - Ownership: the library owns contexts, operators and requests and frees
+ *    them in the matching destroy call.  Arrays passed in are borrowed: input
+ *    arrays are copied before the call returns, caller-owned output buffers
+ *    must stay alive until the call (or, for serving, the request) finishes.
+ *  - Many-body bit convention: site j = 1..L is bit j-1 of a state integer;
+ *    an up spin / occupied site is a set bit.
+ */
+#ifndef POLFED_H
+#define POLFED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  POLFED_OK = 0,
+  POLFED_NOT_CONVERGED = 1,  /* partial result: *n_found pairs are valid */
+  POLFED_ERR_INVALID = -1,   /* bad argument (message says which) */
+  POLFED_ERR_OOM = -2,       /* device allocation failed */
+  POLFED_ERR_HIP = -3,       /* HIP runtime error (message has the code) */
+  POLFED_ERR_BOUNDS = -4,    /* filter blow-up: spectral bounds too tight */
+  POLFED_ERR_BREAKDOWN = -5, /* Lanczos breakdown that could not be resumed */
+  POLFED_ERR_BUSY = -6,      /* serving not started / already running */
+  POLFED_ERR_NODEVICE = -7,  /* no HIP device visible */
+  POLFED_ERR_REJECTED = -8   /* serving: request larger than the HBM budget */
+} polfed_status;
+
+enum { POLFED_FP64 = 0, POLFED_FP32 = 1 };        /* Clenshaw precision */
+enum { POLFED_MATRIX_FREE = 0, POLFED_CSR = 1 };  /* operator storage */
+enum {
+  POLFED_TARGET_ABSOLUTE = 0,   /* target is lambda itself */
+  POLFED_TARGET_RESCALED = 1,   /* target is lambda~ in [-1, 1] of [E_min, E_max] */
+  POLFED_TARGET_NORMALIZED = 2  /* target is (lambda - E_min)/(E_max - E_min) */
+};
+
+typedef struct polfed_ctx polfed_ctx;
+typedef struct polfed_op polfed_op;
+typedef struct polfed_req polfed_req;
+
+/* ---------------------------------------------------------------- context */
+
+int polfed_version(void);
+const char* polfed_last_error(void);
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * that the context borrows (NULL: the library creates its own stream, at the
+ * default priority).  Fails with POLFED_ERR_NODEVICE when no GPU is visible. */
+polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out);
+polfed_status polfed_destroy(polfed_ctx* ctx);
+/* Waits for all work queued on the context's stream. */
+polfed_status polfed_sync(polfed_ctx* ctx);
+
+/* ------------------------------------------------------------------ basis
+ * Sector of L-bit strings with N set bits (the U(1) sector of App. A), in
+ * ascending integer order; the rank of a state is its position.  The library
+ * computes ranks with the combinadic rank(s) = sum_k binom(p_k, k) over the
+ * set-bit positions p_1 < ... < p_N, which equals that position.
+ * 1 <= L <= 32, 0 <= N <= L. */
+
+/* Host only: D = binom(L, N). */
+polfed_status polfed_basis_dim(int L, int N, int64_t* D);
+/* Writes all D states, ascending, to device array states[D]. */
+polfed_status polfed_basis_enumerate(polfed_ctx* ctx, int L, int N,
+                                     uint32_t* states);
+/* ranks[i] = rank of states[i] (device arrays, n entries); a state that is
+ * not in the sector (wrong popcount or bits >= L) gets rank -1. */
+polfed_status polfed_basis_rank(polfed_ctx* ctx, int L, int N,
+                                const uint32_t* states, int64_t n,
+                                int64_t* ranks);
+/* states[i] = state of rank ranks[i] (device arrays); ranks outside [0, D)
+ * give 0xFFFFFFFF. */
+polfed_status polfed_basis_unrank(polfed_ctx* ctx, int L, int N,
+                                  const int64_t* ranks, int64_t n,
+                                  uint32_t* states);
+
+/* -------------------------------------------------------------- operators
+ * All parameter arrays are host arrays, copied at creation.  Matrix-free
+ * operators generate matrix elements from the state bits on the fly; a CSR
+ * copy can be built on the device with polfed_op_materialize_csr. */
+
+/* Random-field XXZ chain, App. A eq. (xxz):
+ *   H = J sum_i (S^x_i S^x_{i+1} + S^y_i S^y_{i+1} + Delta S^z_i S^z_{i+1})
+ *       + sum_i h_i S^z_i,   S = sigma/2,
+ * in the sector with n_up up spins; h[L]; periodic != 0 adds bond (L, 1).
+ * 3 <= L <= 32 for periodic chains, 2 <= L <= 32 otherwise. */
+polfed_status polfed_op_xxz(polfed_ctx* ctx, int L, int n_up, double J,
+                            double Delta, const double* h, int periodic,
+                            polfed_op** out);
+/* Spinless fermions (not a model of the paper):
+ *   H = -t sum_i (c^dag_i c_{i+1} + h.c.) + V sum_i n_i n_{i+1}
+ *       + sum_i eps_i n_i
+ * with Jordan-Wigner ordering by site; the periodic bond carries the string
+ * sign (-1)^(n_part - 1).  eps[L]. */
+polfed_status polfed_op_tv(polfed_ctx* ctx, int L, int n_part, double t,
+                           double V, const double* eps, int periodic,
+                           polfed_op** out);
+/* Quantum sun, App. A eq. (qsun), full 2^(N_dot+L) space:
+ *   H = H_dot (x) I + g0 sum_j alpha^{u_j} S^x_{n(j)} S^x_j + sum_j h_j S^z_j,
+ *   H_dot = gamma (A + A^T) / sqrt(2 (2^N_dot + 1))   (App. A normalization).
+ * A: 2^N_dot x 2^N_dot row-major host matrix of the raw normal draws;
+ * u[L], n_of_j[L] (dot spin 0..N_dot-1 coupled to outer spin j), h[L].
+ * Dot spin k is bit L+k of the state index, outer spin j is bit j-1.
+ * 1 <= N_dot <= 6, 1 <= L, N_dot + L <= 31. */
+polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L,
+                             const double* A, double gamma, double g0,
+                             double alpha, const double* u,
+                             const int32_t* n_of_j, const double* h,
+                             polfed_op** out);
+/* Generic symmetric sparse matrix in CSR (host arrays, copied): rowptr[D+1]
+ * (int64), col[nnz] (int32, any order within a row), val[nnz].  Diagonal
+ * entries may appear; they are split off internally.  Symmetry is the
+ * caller's promise (not checked).  D < 2^31. */
+polfed_status polfed_op_csr(polfed_ctx* ctx, int64_t D, const int64_t* rowptr,
+                            const int32_t* col, const double* val,
+                            polfed_op** out);
+/* Builds the device CSR copy of a matrix-free operator (off-diagonal part in
+ * CSR, diagonal separate).  No-op for CSR operators. */
+polfed_status polfed_op_materialize_csr(polfed_ctx* ctx, polfed_op* op);
+/* Chooses which representation the filter uses (POLFED_MATRIX_FREE needs a
+ * model operator; POLFED_CSR needs a CSR copy). */
+polfed_status polfed_op_set_storage(polfed_op* op, int storage);
+polfed_status polfed_op_dim(const polfed_op* op, int64_t* D);
+/* Off-diagonal nnz of the CSR copy (-1 if there is none). */
+polfed_status polfed_op_nnz(const polfed_op* op, int64_t* nnz_offdiag);
+/* Copies the CSR copy to caller device buffers: rowptr[D+1], col[nnz],
+ * val[nnz] (off-diagonal part, rows sorted by column) and diag[D]. */
+polfed_status polfed_op_export_csr(polfed_ctx* ctx, const polfed_op* op,
+                                   int64_t* rowptr, int32_t* col, double* val,
+                                   double* diag);
+polfed_status polfed_op_destroy(polfed_op* op);
+/* y = H x (device vectors of length D, FP64). */
+polfed_status polfed_op_apply(polfed_ctx* ctx, const polfed_op* op,
+                              const double* x, double* y);
+/* Exact trace moments Tr H / D and Tr H^2 / D (host results; synchronizes).
+ * They fix the mean and width of the Gaussian DOS, eq. (dos_gaussian). */
+polfed_status polfed_op_moments(polfed_ctx* ctx, const polfed_op* op,
+                                double* tr1, double* tr2);
+
+/* ------------------------------------------------------ filter (host side) */
+
+/* Plan of the filter (Secs. 4.1-4.2), computed on the host from the bounds,
+ * the trace moments and the target. */
+typedef struct {
+  double E_c, dE;      /* eq. rescaledMatrix, from the padded bounds */
+  double lambda_t;     /* rescaled target */
+  double mu_t, Gamma_t;/* Gaussian DOS mean and width, rescaled */
+  double rho;          /* DOS at the target, eq. dos_gaussian */
+  double delta;        /* window half-width, eq. Nev */
+  double K_approx;     /* eq. K_approx */
+  int K;               /* order from eq. condition_for_K */
+} polfed_plan;
+
+/* n_window eigenvalues in the window; omega <= 0 selects the default cutoff
+ * sin(2.655)/2.655; K_override > 0 skips the bisection.  D is the matrix
+ * dimension; pad widens [E_min, E_max] by pad*(E_max-E_min) on each side. */
+polfed_status polfed_make_plan(int64_t D, double E_min, double E_max,
+                               double pad, double lambda, double tr1,
+                               double tr2, int n_window, double omega,
+                               int K_override, polfed_plan* out);
+/* a[0..K] = c_n / chi (eqs. transformation, transformationCoefficients). */
+polfed_status polfed_filter_coefficients(double lambda_t, int K, double* a);
+/* out[i] = P^K_{lambda~}(x[i]) by its closed form (host arrays). */
+polfed_status polfed_filter_value(double lambda_t, int K, const double* x,
+                                  int64_t n, double* out);
+
+/* ------------------------------------------------------- filter (device) */
+
+/* w = P(H~) v by the Clenshaw recurrence, eq. clenshaw_chebyshev_prod, with
+ * H~ = (H - E_c)/dE; a[0..K] host coefficients.  v, w: device vectors of
+ * length D in the chosen precision (double for POLFED_FP64, float for
+ * POLFED_FP32); v and w must not overlap.  K >= 0. */
+polfed_status polfed_filter_apply(polfed_ctx* ctx, const polfed_op* op,
+                                  double E_c, double dE, const double* a,
+                                  int K, const void* v, void* w,
+                                  int precision);
+/* One fused Clenshaw step (the hot kernel), in place on b2:
+ *   b2 <- a_i v + 2 H~ b1 - b2            (final == 0)
+ *   b2 <- a_i v +   H~ b1 - b2            (final != 0, the closing step)
+ * Device vectors of length D in the chosen precision; b1 must not overlap
+ * v or b2. */
+polfed_status polfed_clenshaw_step(polfed_ctx* ctx, const polfed_op* op,
+                                   double E_c, double dE, double a_i,
+                                   const void* v, const void* b1, void* b2,
+                                   int precision, int final);
+
+/* --------------------------------------------------------------- Lanczos */
+
+/* Spectral extremes by plain Lanczos on H with full reorthogonalization
+ * (Sec. 3.2), started from device vector x0[D] (need not be normalized).
+ * Stops when both extreme Ritz residuals are below tol*(E_max-E_min) or
+ * after max_iter steps.  Host results; synchronizes. */
+polfed_status polfed_bounds(polfed_ctx* ctx, const polfed_op* op,
+                            const double* x0, double tol, int max_iter,
+                            double* E_min, double* E_max);
+
+typedef struct {
+  int target_kind;     /* POLFED_TARGET_* */
+  double target;
+  int n_ev;            /* N_ev >= 1 */
+  int precision;       /* POLFED_FP64, or POLFED_FP32 for the bulk filter */
+  int K_override;      /* 0: plan K */
+  double omega;        /* 0: default cutoff */
+  double eta;          /* 0: 1.5, over-allocation of the Krylov basis */
+  double tol_resid;    /* 0: 1e-8, accepted ||H u - E u|| */
+  double bound_pad;    /* 0: 1e-3 */
+  int max_iter;        /* 0: 4 * expectedkrylovdim */
+  double E_min, E_max; /* both 0: compute the bounds */
+} polfed_params;
+
+typedef struct {
+  double E_min, E_max, lambda, lambda_t, E_c, dE, delta, rho;
+  int K, M_alloc, iters, n_want, n_converged, checks, restarts, refine_sweeps;
+  double t_bounds, t_plan, t_filter, t_reorth, t_check, t_extract, t_refine,
+      t_total;           /* seconds */
+  double filter_steps;   /* Clenshaw steps executed */
+  double filter_bytes;   /* algorithmic HBM bytes of those steps */
+  double filter_GBps;    /* filter_bytes / t_filter / 1e9 */
+} polfed_report;
+
+polfed_status polfed_params_default(polfed_params* p);
+
+/* Synchronous solve.  x0: device start vector [D].  Outputs are caller
+ * device buffers: evals[n_ev], evecs[D * n_ev] (column-major, unit norm),
+ * resid[n_ev] = ||H u - E u||, ordered by (|E - lambda|, E).  *n_found gets
+ * the number of valid pairs (n_ev on POLFED_OK, fewer with
+ * POLFED_NOT_CONVERGED).  rep may be NULL. */
+polfed_status polfed_solve(polfed_ctx* ctx, const polfed_op* op,
+                           const polfed_params* params, const double* x0,
+                           double* evals, double* evecs, double* resid,
+                           int* n_found, polfed_report* rep);
+
+/* Batched solve of B realizations that share the off-diagonal pattern (same
+ * model, L, N and couplings, different diagonal fields): the filter runs as
+ * one multi-column recurrence.  Arrays of B pointers; each entry as in
+ * polfed_solve.  n_found[B], rep[B] (rep may be NULL). */
+polfed_status polfed_solve_batch(polfed_ctx* ctx, int B,
+                                 const polfed_op* const* ops,
+                                 const polfed_params* params,
+                                 const double* const* x0,
+                                 double* const* evals, double* const* evecs,
+                                 double* const* resid, int* n_found,
+                                 polfed_report* rep);
+
+/* --------------------------------------------------------------- serving
+ * Continuous batching: requests are admitted while the HBM their Krylov
+ * bases need fits the budget and a column slot is free; admitted requests of
+ * the same operator class (same chain pattern) share one multi-column
+ * filter recurrence, and each leaves the batch as soon as it converges. */
+polfed_status polfed_serve_start(polfed_ctx* ctx, size_t hbm_budget_bytes,
+                                 int max_cols);
+/* Queues a solve; op, x0 and the output buffers must stay alive until
+ * polfed_wait returns.  Requests whose footprint exceeds the budget are
+ * rejected (POLFED_ERR_REJECTED). */
+polfed_status polfed_submit(polfed_ctx* ctx, const polfed_op* op,
+                            const polfed_params* params, const double* x0,
+                            double* evals, double* evecs, double* resid,
+                            polfed_req** out);
+polfed_status polfed_poll(polfed_req* req, int* done);
+/* Blocks until the request finished; returns its solve status. */
+polfed_status polfed_wait(polfed_req* req, int* n_found, polfed_report* rep);
+polfed_status polfed_req_destroy(polfed_req* req);
+polfed_status polfed_serve_stop(polfed_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLFED_H */

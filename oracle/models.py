@@ -155,6 +155,26 @@ def qsun(N: int, L: int, A, gamma: float, g0: float, alpha: float, u, n_of_j,
     return H
 
 
+def xxz_rows_apply(L: int, N: int, J: float, Delta: float, h, periodic: bool,
+                   states: np.ndarray, rows: np.ndarray, x: np.ndarray):
+    """(H x)[r] for the listed rows only, straight from eq. (xxz), for checks
+    at sizes where the whole matrix is not built.  `states` is the full
+    ascending sector list (basis.sector_states)."""
+    h = np.asarray(h, dtype=np.float64)
+    s = states[rows]
+    diag = np.zeros(len(rows))
+    for i in range(L):
+        diag += h[i] * (_bit(s, i) - 0.5)
+    out = np.zeros(len(rows))
+    for (i, j) in _bonds(L, periodic):
+        bi, bj = _bit(s, i), _bit(s, j)
+        diag += J * Delta * (bi - 0.5) * (bj - 0.5)
+        flip = bi != bj
+        partner = s[flip] ^ ((1 << i) | (1 << j))
+        out[flip] += 0.5 * J * x[basis.rank(states, partner)]
+    return out + diag * x[rows]
+
+
 def is_symmetric(H, tol: float = 0.0) -> bool:
     diff = (H - H.T).tocsr()
     if diff.nnz == 0:

@@ -1,0 +1,312 @@
+// Dense vector and tall-skinny kernels of the Lanczos iteration: reductions,
+// the two products of classical Gram-Schmidt (c = V^T w, w -= V c), scaling,
+// conversions, and the small GEMMs of the eigenpair extraction.  All FP64;
+// every reduction has a fixed order (block partials, then one block), so
+// results do not depend on timing.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace polfed {
+
+constexpr int kTB = 256;  // threads per block of these kernels
+
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// Sums x over the block; the result is valid in thread 0.
+__device__ __forceinline__ double block_reduce(double x, double* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  return t;
+}
+
+int64_t red_blocks(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>(1024, (n + kTB * 4 - 1) / (kTB * 4)));
+}
+
+__global__ __launch_bounds__(kTB) void k_dot_partial(int64_t n, const double* x,
+                                                     const double* y, double* part) {
+  __shared__ double red[kTB / 64];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += x[i] * y[i];
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kTB) void k_sum_partials(const double* part, int64_t n,
+                                                      double* out, int sqrt_out) {
+  __shared__ double red[kTB / 64];
+  double acc = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) out[0] = sqrt_out ? sqrt(t) : t;
+}
+
+void dev_dot(hipStream_t s, int64_t n, const double* x, const double* y,
+             double* partial, int64_t npart, double* out, int sqrt_out) {
+  const int64_t g = std::min(npart, red_blocks(n));
+  hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)g), dim3(kTB), 0, s, n, x, y, partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kTB), 0, s, partial, g, out, sqrt_out);
+  HIPC(hipGetLastError());
+}
+
+// ---- c = V^T w over k columns: grid (column groups of 8, row segments) ----
+constexpr int kCols = 8;
+
+__global__ __launch_bounds__(kTB) void k_gemv_t(int64_t D, int k, const double* V,
+                                                int64_t ld, const double* w,
+                                                int64_t seg_len, int64_t nseg,
+                                                double* part) {
+  __shared__ double red[kCols][kTB / 64];
+  const int j0 = blockIdx.x * kCols;
+  const int64_t seg = blockIdx.y;
+  const int64_t r0 = seg * seg_len, r1 = std::min<int64_t>(D, r0 + seg_len);
+  double acc[kCols];
+#pragma unroll
+  for (int q = 0; q < kCols; ++q) acc[q] = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const double wr = w[r];
+#pragma unroll
+    for (int q = 0; q < kCols; ++q)
+      if (j0 + q < k) acc[q] += V[r + (int64_t)(j0 + q) * ld] * wr;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kCols; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) red[q][wid] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kCols && j0 + (int)threadIdx.x < k) {
+    double t = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[threadIdx.x][i];
+    part[(int64_t)(j0 + threadIdx.x) * nseg + seg] = t;
+  }
+}
+
+// c[j] = sum of the partials of column j; the last column's value is also
+// stored to (or added to) *tail, which carries the Lanczos alpha_k.
+__global__ void k_reduce_cols(const double* part, int64_t nseg, int k, double* c,
+                              double* tail, int tail_add) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double t = 0;
+  for (int64_t s = 0; s < nseg; ++s) t += part[(int64_t)j * nseg + s];
+  c[j] = t;
+  if (tail && j == k - 1) tail[0] = tail_add ? tail[0] + t : t;
+}
+
+static int64_t seg_len_for(int64_t D, int64_t nseg) {
+  int64_t len = (D + nseg - 1) / nseg;
+  return std::max<int64_t>(kTB, ((len + kTB - 1) / kTB) * kTB);
+}
+
+void dev_gemv_t(hipStream_t s, int64_t D, int k, const double* V, int64_t ld,
+                const double* w, double* partial, int64_t nseg, double* c,
+                double* tail, int tail_add) {
+  if (k <= 0) return;
+  const int64_t len = seg_len_for(D, nseg);
+  const int64_t ns = std::max<int64_t>(1, (D + len - 1) / len);
+  dim3 grid((unsigned)((k + kCols - 1) / kCols), (unsigned)ns);
+  hipLaunchKernelGGL(k_gemv_t, grid, dim3(kTB), 0, s, D, k, V, ld, w, len, ns, partial);
+  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, s,
+                     partial, ns, k, c, tail, tail_add);
+  HIPC(hipGetLastError());
+}
+
+// ---- w -= V c ----
+__global__ __launch_bounds__(kTB) void k_gemv_n_sub(int64_t D, int k, const double* V,
+                                                    int64_t ld, const double* c,
+                                                    double* w) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  double acc = 0;
+  for (int j = 0; j < k; ++j) acc += V[r + (int64_t)j * ld] * c[j];
+  w[r] -= acc;
+}
+
+void dev_gemv_n_sub(hipStream_t s, int64_t D, int k, const double* V, int64_t ld,
+                    const double* c, double* w) {
+  if (k <= 0 || D == 0) return;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)((D + kTB - 1) / kTB)), dim3(kTB), 0,
+                     s, D, k, V, ld, c, w);
+  HIPC(hipGetLastError());
+}
+
+// ---- out = w / beta; a vanishing beta (breakdown) leaves zeros and raises flag ----
+__global__ void k_scale_into(int64_t D, const double* w, const double* beta,
+                             double* out, int* flag) {
+  const double b = beta[0];
+  const bool ok = b > 1e-300 && isfinite(b);
+  const double inv = ok ? 1.0 / b : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = w[i] * inv;
+  if (!ok && flag && blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 1;
+}
+
+static unsigned stream_grid(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kTB - 1) / kTB));
+}
+
+void dev_scale_into(hipStream_t s, int64_t D, const double* w, const double* beta,
+                    double* out, int* flag) {
+  hipLaunchKernelGGL(k_scale_into, dim3(stream_grid(D)), dim3(kTB), 0, s, D, w, beta,
+                     out, flag);
+  HIPC(hipGetLastError());
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* x, double b, double* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+void dev_axpby(hipStream_t s, int64_t n, double a, const double* x, double b,
+               double* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(kTB), 0, s, n, a, x, b, y);
+  HIPC(hipGetLastError());
+}
+
+__global__ void k_cvt_d2f(int64_t n, const double* x, float* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void k_cvt_f2d(int64_t n, const float* x, double* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+void dev_copy_d2f(hipStream_t s, int64_t n, const double* x, float* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cvt_d2f, dim3(stream_grid(n)), dim3(kTB), 0, s, n, x, y);
+  HIPC(hipGetLastError());
+}
+void dev_copy_f2d(hipStream_t s, int64_t n, const float* x, double* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cvt_f2d, dim3(stream_grid(n)), dim3(kTB), 0, s, n, x, y);
+  HIPC(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+void dev_fill(hipStream_t s, int64_t n, double v, double* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill<double>, dim3(stream_grid(n)), dim3(kTB), 0, s, n, v, y);
+  HIPC(hipGetLastError());
+}
+void dev_fillf(hipStream_t s, int64_t n, float v, float* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill<float>, dim3(stream_grid(n)), dim3(kTB), 0, s, n, v, y);
+  HIPC(hipGetLastError());
+}
+
+// Counter-based uniform draws in [-1, 1): splitmix64 of (seed, index).
+__global__ void k_random(int64_t n, uint64_t seed, double* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    y[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+void dev_random(hipStream_t s, int64_t n, uint64_t seed, double* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_random, dim3(stream_grid(n)), dim3(kTB), 0, s, n, seed, y);
+  HIPC(hipGetLastError());
+}
+
+// ---- C (D x n) = A (D x m) B (m x n) ----
+__global__ __launch_bounds__(kTB) void k_gemm_nn(int64_t D, int m, int n, const double* A,
+                                                 int64_t lda, const double* B,
+                                                 double* C, int64_t ldc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * kCols;
+  if (r >= D) return;
+  double acc[kCols];
+#pragma unroll
+  for (int q = 0; q < kCols; ++q) acc[q] = 0;
+  for (int i = 0; i < m; ++i) {
+    const double a = A[r + (int64_t)i * lda];
+#pragma unroll
+    for (int q = 0; q < kCols; ++q)
+      if (j0 + q < n) acc[q] += a * B[i + (int64_t)(j0 + q) * m];
+  }
+#pragma unroll
+  for (int q = 0; q < kCols; ++q)
+    if (j0 + q < n) C[r + (int64_t)(j0 + q) * ldc] = acc[q];
+}
+
+void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A, int64_t lda,
+                 const double* B, double* C, int64_t ldc) {
+  if (!D || !n) return;
+  dim3 grid((unsigned)((D + kTB - 1) / kTB), (unsigned)((n + kCols - 1) / kCols));
+  hipLaunchKernelGGL(k_gemm_nn, grid, dim3(kTB), 0, s, D, m, n, A, lda, B, C, ldc);
+  HIPC(hipGetLastError());
+}
+
+void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A, const double* B,
+                 double* partial, int64_t nseg, double* G) {
+  for (int j = 0; j < n; ++j)
+    dev_gemv_t(s, D, n, A, D, B + (int64_t)j * D, partial, nseg, G + (int64_t)j * n,
+               nullptr, 0);
+}
+
+// ---- residual norms ----
+__global__ __launch_bounds__(kTB) void k_resid(int64_t D, int n, const double* U,
+                                               const double* HU, const double* E,
+                                               int64_t seg_len, int64_t nseg,
+                                               double* part) {
+  __shared__ double red[kTB / 64];
+  const int j = blockIdx.x;
+  const int64_t seg = blockIdx.y;
+  const int64_t r0 = seg * seg_len, r1 = std::min<int64_t>(D, r0 + seg_len);
+  const double e = E[j];
+  double acc = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const double d = HU[r + (int64_t)j * D] - e * U[r + (int64_t)j * D];
+    acc += d * d;
+  }
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)j * nseg + seg] = t;
+}
+
+__global__ void k_reduce_cols_sqrt(const double* part, int64_t nseg, int n, double* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double t = 0;
+  for (int64_t s = 0; s < nseg; ++s) t += part[(int64_t)j * nseg + s];
+  out[j] = sqrt(t);
+}
+
+void dev_resid(hipStream_t s, int64_t D, int n, const double* U, const double* HU,
+               const double* E, double* partial, int64_t nseg, double* res) {
+  if (!n) return;
+  const int64_t len = seg_len_for(D, nseg);
+  const int64_t ns = std::max<int64_t>(1, (D + len - 1) / len);
+  hipLaunchKernelGGL(k_resid, dim3((unsigned)n, (unsigned)ns), dim3(kTB), 0, s, D, n, U,
+                     HU, E, len, ns, partial);
+  hipLaunchKernelGGL(k_reduce_cols_sqrt, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s,
+                     partial, ns, n, res);
+  HIPC(hipGetLastError());
+}
+
+}  // namespace polfed

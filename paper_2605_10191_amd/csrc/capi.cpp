@@ -1,0 +1,573 @@
+// extern "C" entry points of polfed.h: argument checks, error capture and
+// dispatch to the library internals.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace polfed {
+
+polfed_op* make_xxz(polfed_ctx*, int, int, double, double, const double*, int);
+polfed_op* make_tv(polfed_ctx*, int, int, double, double, const double*, int);
+polfed_op* make_qsun(polfed_ctx*, int, int, const double*, double, double, double,
+                     const double*, const int32_t*, const double*);
+polfed_op* make_csr(polfed_ctx*, int64_t, const int64_t*, const int32_t*, const double*);
+polfed_status serve_start(polfed_ctx*, size_t, int);
+polfed_status serve_submit(polfed_ctx*, const polfed_op*, const polfed_params*,
+                           const double*, double*, double*, double*, polfed_req**);
+polfed_status req_poll(polfed_req*, int*);
+polfed_status req_wait(polfed_req*, int*, polfed_report*);
+polfed_status req_destroy(polfed_req*);
+polfed_status serve_stop(polfed_ctx*);
+
+namespace {
+thread_local std::string g_err;
+}
+
+[[noreturn]] void fail(polfed_status code, const std::string& msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  const char* base = std::strrchr(file, '/');
+  std::string m = std::string(what) + " failed: " + hipGetErrorString(e) + " (" +
+                  (base ? base + 1 : file) + ":" + std::to_string(line) + ")";
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    throw Error(POLFED_ERR_OOM, m);
+  throw Error(POLFED_ERR_HIP, m);
+}
+
+void DevBuf::alloc(size_t bytes) {
+  release();
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(POLFED_ERR_OOM, "device allocation of " + std::to_string(bytes) +
+                                    " bytes failed: " + hipGetErrorString(e));
+  }
+  p_ = p;
+  n_ = bytes;
+}
+
+void DevBuf::release() {
+  if (p_) (void)hipFree(p_);
+  p_ = nullptr;
+  n_ = 0;
+}
+
+template <class F>
+polfed_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return POLFED_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return POLFED_ERR_INVALID;
+  } catch (...) {
+    g_err = "unknown error";
+    return POLFED_ERR_INVALID;
+  }
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) HIPC(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace polfed
+
+using namespace polfed;
+
+#define CTX_OK(ctx) REQUIRE((ctx) != nullptr, "null context")
+
+extern "C" {
+
+int polfed_version(void) { return 10000; }
+
+const char* polfed_last_error(void) { return g_err.c_str(); }
+
+polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(out != nullptr, "null output handle");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+      (void)hipGetLastError();
+      fail(POLFED_ERR_NODEVICE, "no HIP device visible");
+    }
+    REQUIRE(device >= 0 && device < n, "device index out of range");
+    DeviceGuard g(device);
+    auto ctx = std::make_unique<polfed_ctx>();
+    ctx->device = device;
+    if (hip_stream) {
+      ctx->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      HIPC(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+      ctx->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, device));
+    ctx->n_cu = prop.multiProcessorCount;
+    *out = ctx.release();
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_destroy(polfed_ctx* ctx) {
+  return guarded([&]() -> polfed_status {
+    if (!ctx) return POLFED_OK;
+    if (ctx->server) (void)serve_stop(ctx);
+    {
+      DeviceGuard g(ctx->device);
+      (void)hipStreamSynchronize(ctx->stream);
+      ctx->scratch_red.release();
+      ctx->scratch_scalar.release();
+      ctx->binom.release();
+      if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_sync(polfed_ctx* ctx) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    DeviceGuard g(ctx->device);
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return POLFED_OK;
+  });
+}
+
+// ---------------------------------------------------------------- basis
+
+polfed_status polfed_basis_dim(int L, int N, int64_t* D) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(D != nullptr, "null output");
+    REQUIRE(L >= 1 && L <= 32 && N >= 0 && N <= L, "need 1 <= L <= 32, 0 <= N <= L");
+    *D = binom64(L, N);
+    return POLFED_OK;
+  });
+}
+
+namespace {
+const uint32_t* ctx_binom(polfed_ctx* ctx) {
+  if (!ctx->binom.get()) {
+    upload(ctx->binom, host_binom(), (size_t)kBinomN * kBinomN, ctx->stream);
+    HIPC(hipStreamSynchronize(ctx->stream));
+  }
+  return ctx->binom.as<uint32_t>();
+}
+}  // namespace
+
+polfed_status polfed_basis_enumerate(polfed_ctx* ctx, int L, int N, uint32_t* states) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(L >= 1 && L <= 32 && N >= 0 && N <= L, "need 1 <= L <= 32, 0 <= N <= L");
+    const int64_t D = binom64(L, N);
+    REQUIRE(D < (int64_t(1) << 31), "sector too large");
+    REQUIRE(states != nullptr || D == 0, "null states");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    basis_enumerate(ctx->stream, L, N, D, states, ctx_binom(ctx));
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_basis_rank(polfed_ctx* ctx, int L, int N, const uint32_t* states,
+                                int64_t n, int64_t* ranks) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(L >= 1 && L <= 32 && N >= 0 && N <= L, "need 1 <= L <= 32, 0 <= N <= L");
+    REQUIRE(n >= 0, "negative count");
+    REQUIRE(n == 0 || (states && ranks), "null array");
+    REQUIRE(binom64(L, N) < (int64_t(1) << 31), "sector too large");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    basis_rank(ctx->stream, L, N, states, n, ranks, ctx_binom(ctx));
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_basis_unrank(polfed_ctx* ctx, int L, int N, const int64_t* ranks,
+                                  int64_t n, uint32_t* states) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(L >= 1 && L <= 32 && N >= 0 && N <= L, "need 1 <= L <= 32, 0 <= N <= L");
+    REQUIRE(n >= 0, "negative count");
+    REQUIRE(n == 0 || (states && ranks), "null array");
+    const int64_t D = binom64(L, N);
+    REQUIRE(D < (int64_t(1) << 31), "sector too large");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    basis_unrank(ctx->stream, L, N, D, ranks, n, states, ctx_binom(ctx));
+    return POLFED_OK;
+  });
+}
+
+// ------------------------------------------------------------ operators
+
+polfed_status polfed_op_xxz(polfed_ctx* ctx, int L, int n_up, double J, double Delta,
+                            const double* h, int periodic, polfed_op** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(out, "null output handle");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = make_xxz(ctx, L, n_up, J, Delta, h, periodic);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_tv(polfed_ctx* ctx, int L, int n_part, double t, double V,
+                           const double* eps, int periodic, polfed_op** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(out, "null output handle");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = make_tv(ctx, L, n_part, t, V, eps, periodic);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L, const double* A,
+                             double gamma, double g0, double alpha, const double* u,
+                             const int32_t* n_of_j, const double* h, polfed_op** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(out, "null output handle");
+    *out = nullptr;
+    REQUIRE(std::isfinite(gamma) && std::isfinite(g0) && std::isfinite(alpha) && alpha > 0,
+            "qsun: need finite gamma, g0 and alpha > 0");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = make_qsun(ctx, N_dot, L, A, gamma, g0, alpha, u, n_of_j, h);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_csr(polfed_ctx* ctx, int64_t D, const int64_t* rowptr,
+                            const int32_t* col, const double* val, polfed_op** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(out, "null output handle");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = make_csr(ctx, D, rowptr, col, val);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_materialize_csr(polfed_ctx* ctx, polfed_op* op) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    materialize_csr(ctx, op);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_set_storage(polfed_op* op, int storage) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(op, "null operator");
+    if (storage == POLFED_CSR) {
+      REQUIRE(op->has_csr, "operator has no CSR copy (call polfed_op_materialize_csr)");
+    } else {
+      REQUIRE(storage == POLFED_MATRIX_FREE, "unknown storage");
+      REQUIRE(op->model != Model::Csr, "CSR operator has no matrix-free form");
+    }
+    op->storage = storage;
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_dim(const polfed_op* op, int64_t* D) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(op && D, "null argument");
+    *D = op->D;
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_nnz(const polfed_op* op, int64_t* nnz) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(op && nnz, "null argument");
+    *nnz = op->has_csr ? op->nnz : -1;
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_export_csr(polfed_ctx* ctx, const polfed_op* op, int64_t* rowptr,
+                                   int32_t* col, double* val, double* diag) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(op->has_csr, "operator has no CSR copy");
+    REQUIRE(rowptr && diag && (op->nnz == 0 || (col && val)), "null buffer");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    HIPC(hipMemcpyAsync(rowptr, op->d_rowptr.get(), (op->D + 1) * sizeof(int64_t),
+                        hipMemcpyDeviceToDevice, s));
+    if (op->nnz) {
+      HIPC(hipMemcpyAsync(col, op->d_col.get(), op->nnz * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+      HIPC(hipMemcpyAsync(val, op->d_val.get(), op->nnz * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    }
+    if (op->D)
+      HIPC(hipMemcpyAsync(diag, op->d_diag.get(), op->D * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_destroy(polfed_op* op) {
+  return guarded([&]() -> polfed_status {
+    if (!op) return POLFED_OK;
+    DeviceGuard g(op->ctx->device);
+    (void)hipStreamSynchronize(op->ctx->stream);
+    delete op;
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_apply(polfed_ctx* ctx, const polfed_op* op, const double* x,
+                              double* y) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(op->D == 0 || (x && y), "null vector");
+    REQUIRE(x != y, "x and y must not overlap");
+    DeviceGuard g(ctx->device);
+    op_step<double>(ctx->stream, op, 1.0, 0.0, 0.0, nullptr, x, nullptr, y);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_moments(polfed_ctx* ctx, const polfed_op* op, double* tr1,
+                                double* tr2) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(tr1 && tr2, "null output");
+    REQUIRE(op->D >= 1, "empty operator");
+    DeviceGuard g(ctx->device);
+    DevBuf two(2 * sizeof(double)), part(2 * 4096 * sizeof(double));
+    op_moments(ctx->stream, op, two.as<double>(), part.as<double>(), 4096);
+    double t[2];
+    HIPC(hipMemcpyAsync(t, two.get(), sizeof t, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    *tr1 = t[0] / (double)op->D;
+    *tr2 = t[1] / (double)op->D;
+    return POLFED_OK;
+  });
+}
+
+// ------------------------------------------------------------- filter
+
+polfed_status polfed_make_plan(int64_t D, double E_min, double E_max, double pad,
+                               double lambda, double tr1, double tr2, int n_window,
+                               double omega, int K_override, polfed_plan* out) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(out, "null output");
+    *out = make_plan(D, E_min, E_max, pad, lambda, tr1, tr2, n_window, omega, K_override);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_filter_coefficients(double lambda_t, int K, double* a) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(a, "null output");
+    REQUIRE(K >= 0, "K must be >= 0");
+    REQUIRE(lambda_t >= -1.0 && lambda_t <= 1.0, "lambda~ must lie in [-1, 1]");
+    filter_coefficients(lambda_t, K, a);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_filter_value(double lambda_t, int K, const double* x, int64_t n,
+                                  double* out) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(n >= 0 && (n == 0 || (x && out)), "null array");
+    REQUIRE(K >= 0, "K must be >= 0");
+    REQUIRE(lambda_t >= -1.0 && lambda_t <= 1.0, "lambda~ must lie in [-1, 1]");
+    for (int64_t i = 0; i < n; ++i) out[i] = filter_value_closed(lambda_t, K, x[i]);
+    return POLFED_OK;
+  });
+}
+
+static void check_step_args(polfed_ctx* ctx, const polfed_op* op, double dE, int precision) {
+  CTX_OK(ctx);
+  REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+  REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
+  REQUIRE(std::isfinite(dE) && dE > 0, "dE must be finite and positive");
+}
+
+polfed_status polfed_filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c,
+                                  double dE, const double* a, int K, const void* v, void* w,
+                                  int precision) {
+  return guarded([&]() -> polfed_status {
+    check_step_args(ctx, op, dE, precision);
+    REQUIRE(std::isfinite(E_c), "E_c must be finite");
+    REQUIRE(K >= 0 && a, "need K >= 0 and coefficients a[K+1]");
+    REQUIRE(op->D == 0 || (v && w), "null vector");
+    REQUIRE(v != w, "v and w must not overlap");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int64_t D = op->D;
+    if (precision == POLFED_FP64) {
+      DevBuf A(std::max<int64_t>(D, 1) * sizeof(double)), Bb(std::max<int64_t>(D, 1) * sizeof(double));
+      filter_apply<double>(ctx, op, E_c, dE, a, K, static_cast<const double*>(v),
+                           static_cast<double*>(w), A.as<double>(), Bb.as<double>());
+      HIPC(hipStreamSynchronize(ctx->stream));
+    } else {
+      DevBuf A(std::max<int64_t>(D, 1) * sizeof(float)), Bb(std::max<int64_t>(D, 1) * sizeof(float));
+      filter_apply<float>(ctx, op, E_c, dE, a, K, static_cast<const float*>(v),
+                          static_cast<float*>(w), A.as<float>(), Bb.as<float>());
+      HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_clenshaw_step(polfed_ctx* ctx, const polfed_op* op, double E_c,
+                                   double dE, double a_i, const void* v, const void* b1,
+                                   void* b2, int precision, int final) {
+  return guarded([&]() -> polfed_status {
+    check_step_args(ctx, op, dE, precision);
+    REQUIRE(std::isfinite(E_c) && std::isfinite(a_i), "non-finite scalar");
+    REQUIRE(op->D == 0 || (v && b1 && b2), "null vector");
+    REQUIRE(b1 != b2 && b1 != v, "b1 must not overlap v or b2");
+    DeviceGuard g(ctx->device);
+    const double f = final ? 0.5 : 1.0;
+    const double sigma = f * 2.0 / dE, tau = -f * 2.0 * E_c / dE;
+    if (precision == POLFED_FP64)
+      op_step<double>(ctx->stream, op, sigma, tau, a_i, static_cast<const double*>(v),
+                      static_cast<const double*>(b1), static_cast<const double*>(b2),
+                      static_cast<double*>(b2));
+    else
+      op_step<float>(ctx->stream, op, (float)sigma, (float)tau, (float)a_i,
+                     static_cast<const float*>(v), static_cast<const float*>(b1),
+                     static_cast<const float*>(b2), static_cast<float*>(b2));
+    return POLFED_OK;
+  });
+}
+
+// ------------------------------------------------------------- Lanczos
+
+polfed_status polfed_bounds(polfed_ctx* ctx, const polfed_op* op, const double* x0,
+                            double tol, int max_iter, double* E_min, double* E_max) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(x0 && E_min && E_max, "null argument");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    bounds(ctx, op, x0, tol, max_iter, E_min, E_max, nullptr);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_params_default(polfed_params* p) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(p, "null params");
+    std::memset(p, 0, sizeof *p);
+    p->target_kind = POLFED_TARGET_NORMALIZED;
+    p->target = 0.5;
+    p->n_ev = 20;
+    p->precision = POLFED_FP64;
+    p->eta = 1.5;
+    p->tol_resid = 1e-8;
+    p->bound_pad = 1e-3;
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params* params,
+                           const double* x0, double* evals, double* evecs, double* resid,
+                           int* n_found, polfed_report* rep) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(params, "null params");
+    if (n_found) *n_found = 0;
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return solve(ctx, op, *params, x0, evals, evecs, resid, n_found, rep);
+  });
+}
+
+polfed_status polfed_solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
+                                 const polfed_params* params, const double* const* x0,
+                                 double* const* evals, double* const* evecs,
+                                 double* const* resid, int* n_found, polfed_report* rep) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(B >= 1 && ops && params && x0 && evals && evecs && resid && n_found,
+            "null argument");
+    for (int i = 0; i < B; ++i) REQUIRE(ops[i] && ops[i]->ctx == ctx, "bad operator");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return solve_batch(ctx, B, ops, *params, x0, evals, evecs, resid, n_found, rep);
+  });
+}
+
+// ------------------------------------------------------------- serving
+
+polfed_status polfed_serve_start(polfed_ctx* ctx, size_t hbm_budget_bytes, int max_cols) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    return serve_start(ctx, hbm_budget_bytes, max_cols);
+  });
+}
+
+polfed_status polfed_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_params* params,
+                            const double* x0, double* evals, double* evecs, double* resid,
+                            polfed_req** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    return serve_submit(ctx, op, params, x0, evals, evecs, resid, out);
+  });
+}
+
+polfed_status polfed_poll(polfed_req* req, int* done) {
+  return guarded([&]() -> polfed_status { return req_poll(req, done); });
+}
+
+polfed_status polfed_wait(polfed_req* req, int* n_found, polfed_report* rep) {
+  return guarded([&]() -> polfed_status { return req_wait(req, n_found, rep); });
+}
+
+polfed_status polfed_req_destroy(polfed_req* req) {
+  return guarded([&]() -> polfed_status { return req_destroy(req); });
+}
+
+polfed_status polfed_serve_stop(polfed_ctx* ctx) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    return serve_stop(ctx);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Small host eigensolvers for the Lanczos matrix and the Rayleigh-Ritz
+// projection.  Symmetric tridiagonal: implicit QL with Wilkinson-type shifts
+// (Bowdler, Martin, Reinsch and Wilkinson, 1968).  Dense symmetric:
+// Householder reduction to tridiagonal form (Golub and Van Loan, Sec. 8.3)
+// followed by the tridiagonal solver.  Sizes here are a few hundred at most.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace polfed {
+
+void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
+                 std::vector<double>& Z, int nz) {
+  if (n <= 0) return;
+  e.resize(n, 0.0);
+  e[n - 1] = 0.0;
+  const double eps = 2.220446049250313e-16;
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    for (;;) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
+      }
+      if (m == l) break;
+      if (++iter > 200) fail(POLFED_ERR_INVALID, "tridiagonal QL did not converge");
+      // shift from the leading 2x2 block
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      bool deflated = false;
+      for (; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // underflow: split and restart
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        for (int k = 0; k < nz; ++k) {
+          double* zk = &Z[(size_t)k * n];
+          const double zf = zk[i + 1];
+          zk[i + 1] = s * zk[i] + c * zf;
+          zk[i] = c * zk[i] - s * zf;
+        }
+      }
+      if (deflated) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  // ascending order, columns of Z alike
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  std::vector<double> d2(n), Z2((size_t)nz * n);
+  for (int j = 0; j < n; ++j) {
+    d2[j] = d[idx[j]];
+    for (int k = 0; k < nz; ++k) Z2[(size_t)k * n + j] = Z[(size_t)k * n + idx[j]];
+  }
+  d.swap(d2);
+  Z.swap(Z2);
+}
+
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
+             std::vector<double>& Zout) {
+  // Work row-major on a symmetric copy (A is col-major; symmetric anyway).
+  std::vector<double> a((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      a[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), q(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // length of the column below the diagonal
+    double xn = 0;
+    for (int i = 0; i < m; ++i) xn += a[(size_t)(k + 1 + i) * n + k] * a[(size_t)(k + 1 + i) * n + k];
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double x0 = a[(size_t)(k + 1) * n + k];
+    const double alpha = x0 >= 0 ? -xn : xn;
+    for (int i = 0; i < m; ++i) v[i] = a[(size_t)(k + 1 + i) * n + k];
+    v[0] -= alpha;
+    double vv = 0;
+    for (int i = 0; i < m; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // p = beta * A_sub v
+    for (int i = 0; i < m; ++i) {
+      double t = 0;
+      const double* row = &a[(size_t)(k + 1 + i) * n + (k + 1)];
+      for (int j = 0; j < m; ++j) t += row[j] * v[j];
+      p[i] = beta * t;
+    }
+    double vp = 0;
+    for (int i = 0; i < m; ++i) vp += v[i] * p[i];
+    const double Kc = 0.5 * beta * vp;
+    for (int i = 0; i < m; ++i) q[i] = p[i] - Kc * v[i];
+    for (int i = 0; i < m; ++i) {
+      double* row = &a[(size_t)(k + 1 + i) * n + (k + 1)];
+      for (int j = 0; j < m; ++j) row[j] -= v[i] * q[j] + q[i] * v[j];
+    }
+    a[(size_t)(k + 1) * n + k] = alpha;
+    a[(size_t)k * n + (k + 1)] = alpha;
+    for (int i = 1; i < m; ++i) {
+      a[(size_t)(k + 1 + i) * n + k] = 0.0;
+      a[(size_t)k * n + (k + 1 + i)] = 0.0;
+    }
+    // Q <- Q H on columns k+1..n-1
+    for (int r = 0; r < n; ++r) {
+      double* qr = &Q[(size_t)r * n + (k + 1)];
+      double t = 0;
+      for (int j = 0; j < m; ++j) t += qr[j] * v[j];
+      t *= beta;
+      for (int j = 0; j < m; ++j) qr[j] -= t * v[j];
+    }
+  }
+  std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
+  for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)(i + 1) * n + i];
+  tridiag_eig(n, d, e, Q, n);  // Q rows: components, columns: eigenvectors
+  w = d;
+  Zout.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Zout[(size_t)j * n + i] = Q[(size_t)i * n + j];
+}
+
+}  // namespace polfed

@@ -1,0 +1,250 @@
+// Internal declarations of the POLFED HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/polfed.h"
+
+namespace polfed {
+
+// ------------------------------------------------------------ errors ----
+
+struct Error : std::runtime_error {
+  polfed_status code;
+  Error(polfed_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(polfed_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPC(x) ::polfed::hip_check((x), #x, __FILE__, __LINE__)
+#define REQUIRE(cond, msg)                                        \
+  do {                                                            \
+    if (!(cond)) ::polfed::fail(POLFED_ERR_INVALID, (msg));       \
+  } while (0)
+
+// --------------------------------------------------- device buffers ----
+
+// Owning device allocation (library-internal workspaces and tables).
+class DevBuf {
+ public:
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) { alloc(bytes); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    return *this;
+  }
+  void alloc(size_t bytes);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p_); }
+  void* get() const { return p_; }
+  size_t bytes() const { return n_; }
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+template <class T>
+void upload(DevBuf& b, const T* host, size_t n, hipStream_t s) {
+  b.alloc(n * sizeof(T) > 0 ? n * sizeof(T) : 16);
+  if (n) HIPC(hipMemcpyAsync(b.get(), host, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------- model structs ----
+
+constexpr int kBinomN = 33;  // binomial table C(n, k), 0 <= n, k <= 32
+
+// Random-field / t-V chain in a fixed particle-number sector, matrix-free.
+// Diagonal: vzz * #(occupied nearest-neighbour pairs) + c0 + sum_i f_i n_i,
+// with the site sum read from four byte-indexed tables.  Hopping on an
+// internal bond has amplitude t_in, on the periodic bond t_pb.
+struct ChainDev {
+  int L, N, periodic, Lb;
+  int64_t D;
+  double t_in, t_pb, vzz, c0;
+  const double* ftab;      // [4][256] partial field sums (FP64)
+  const float* ftab32;     // same in FP32
+  const uint32_t* binom;   // [kBinomN][kBinomN]
+  const int32_t* hi_off;   // ranks of the first state of each high part
+  const int32_t* lo_rank;  // rank of a low part among equal-popcount ones
+};
+
+constexpr int kQsunMaxL = 31;
+// Quantum sun in the full space: index = dot_state << L | outer_bits.
+struct QsunDev {
+  int N, L;
+  int64_t D;
+  double c0;
+  const double* hdot;     // [2^N][2^N]
+  const double* ftab;     // [4][256] outer field sums (FP64)
+  const float* ftab32;
+  uint32_t ray_mask[kQsunMaxL];
+  double ray_amp[kQsunMaxL];
+};
+
+// CSR with the diagonal split off.  Rows are grouped in blocks whose
+// off-diagonal entries fit the LDS stage of the CSR kernel.
+struct CsrDev {
+  int64_t D;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const float* val32;
+  const double* diag;
+  const float* diag32;
+  const int64_t* blk_row;  // [nblk + 1]
+  int64_t nblk;
+};
+
+enum class Model { Chain, Qsun, Csr };
+
+}  // namespace polfed
+
+// Opaque handles of the C ABI.
+struct polfed_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n_cu = 256;
+  std::mutex mu;  // serializes calls that use the shared workspaces
+  // reusable workspaces
+  polfed::DevBuf scratch_red;  // reduction partials
+  polfed::DevBuf scratch_scalar;
+  polfed::DevBuf binom;  // binomial table for the basis calls
+  struct Server* server = nullptr;
+};
+
+struct polfed_op {
+  polfed_ctx* ctx = nullptr;
+  polfed::Model model = polfed::Model::Chain;
+  int storage = POLFED_MATRIX_FREE;
+  int64_t D = 0;
+  // chain parameters (host copy) and tables
+  int L = 0, N = 0, periodic = 0;
+  double t_in = 0, t_pb = 0, vzz = 0, c0 = 0;
+  std::vector<double> site_f;  // f_i
+  // quantum sun (host copy)
+  int N_dot = 0;
+  std::vector<double> hdot;
+  std::vector<uint32_t> ray_mask;
+  std::vector<double> ray_amp;
+  // pattern key: operators with equal keys share the off-diagonal pattern
+  std::string pattern_key;
+  polfed::DevBuf d_ftab, d_ftab32, d_binom, d_hi_off, d_lo_rank, d_hdot;
+  // CSR copy
+  bool has_csr = false;
+  int64_t nnz = -1;
+  polfed::DevBuf d_rowptr, d_col, d_val, d_val32, d_diag, d_diag32, d_blk;
+  int64_t nblk = 0;
+  polfed::ChainDev chain() const;
+  polfed::QsunDev qsun() const;
+  polfed::CsrDev csr() const;
+};
+
+namespace polfed {
+
+// ------------------------------------------------------------ basis ----
+const uint32_t* host_binom();  // host table [kBinomN][kBinomN]
+int64_t binom64(int n, int k);
+void basis_enumerate(hipStream_t s, int L, int N, int64_t D, uint32_t* states,
+                     const uint32_t* d_binom);
+void basis_rank(hipStream_t s, int L, int N, const uint32_t* states, int64_t n,
+                int64_t* ranks, const uint32_t* d_binom);
+void basis_unrank(hipStream_t s, int L, int N, int64_t D, const int64_t* ranks,
+                  int64_t n, uint32_t* states, const uint32_t* d_binom);
+// Tables for ranking through the split state = hi << Lb | lo.
+void build_split_rank_tables(int L, int N, int Lb, std::vector<int32_t>& hi_off,
+                             std::vector<int32_t>& lo_rank);
+
+// ----------------------------------------------------------- operators ----
+// Fused Clenshaw step for every operator kind and precision:
+//   out = a * v + sigma * (H b1) + tau * b1 - (b2 ? b2 : 0)
+// v may be null (a ignored); out may alias b2.
+template <typename T>
+void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
+             const T* v, const T* b1, const T* b2, T* out);
+// Multi-column step for B columns stored row-interleaved (element (r, c) at
+// r * B + c); per-column scalars and diagonal tables.
+void op_moments(hipStream_t s, const polfed_op* op, double* d_two, double* partial,
+                int64_t npart);
+void materialize_csr(polfed_ctx* ctx, polfed_op* op);
+
+// ---------------------------------------------------------------- blas ----
+int64_t red_blocks(int64_t n);
+void dev_dot(hipStream_t s, int64_t n, const double* x, const double* y,
+             double* partial, int64_t npart, double* out, int sqrt_out);
+void dev_gemv_t(hipStream_t s, int64_t D, int k, const double* V, int64_t ld,
+                const double* w, double* partial, int64_t nseg, double* c,
+                double* tail, int tail_add);
+void dev_gemv_n_sub(hipStream_t s, int64_t D, int k, const double* V, int64_t ld,
+                    const double* c, double* w);
+void dev_scale_into(hipStream_t s, int64_t D, const double* w,
+                    const double* beta, double* out, int* flag);
+void dev_axpby(hipStream_t s, int64_t n, double a, const double* x, double b,
+               double* y);
+void dev_copy_d2f(hipStream_t s, int64_t n, const double* x, float* y);
+void dev_copy_f2d(hipStream_t s, int64_t n, const float* x, double* y);
+void dev_fill(hipStream_t s, int64_t n, double v, double* y);
+void dev_fillf(hipStream_t s, int64_t n, float v, float* y);
+void dev_random(hipStream_t s, int64_t n, uint64_t seed, double* y);
+// C (D x n) = A (D x m, ld lda) * B (m x n, host-uploaded, col-major, ld m)
+void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A,
+                 int64_t lda, const double* B, double* C, int64_t ldc);
+// G (n x n) = A^T B for A, B of D x n (ld D); G on device, col-major.
+void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A,
+                 const double* B, double* partial, int64_t nseg, double* G);
+// res[j] = || HU[:, j] - E[j] U[:, j] ||
+void dev_resid(hipStream_t s, int64_t D, int n, const double* U,
+               const double* HU, const double* E, double* partial, int64_t nseg,
+               double* res);
+
+// ------------------------------------------------------- host eigen ----
+// Symmetric tridiagonal eigenproblem by implicit QL.  d[n] diagonal, e[n-1]
+// off-diagonal.  Accumulates the rotations into the rows of Z (nz x n,
+// row-major) that the caller initializes (identity rows for eigenvectors,
+// the last unit row for last components only).  Eigenvalues ascending, Z
+// columns permuted alike.
+void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
+                 std::vector<double>& Z, int nz);
+// Dense symmetric eigenproblem (n x n col-major A, overwritten): eigenvalues
+// ascending in w, eigenvectors in the columns of Z (col-major).
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
+             std::vector<double>& Z);
+
+// ---------------------------------------------------------------- plan ----
+double filter_value_closed(double lambda_t, int K, double x);
+void filter_coefficients(double lambda_t, int K, double* a);
+polfed_plan make_plan(int64_t D, double E_min, double E_max, double pad,
+                      double lambda, double tr1, double tr2, int n_window,
+                      double omega, int K_override);
+constexpr double kOmegaDefault = 0.17612720216036546;  // sin(2.655)/2.655
+int expected_krylov_dim(int howmany, int blocksize, double eta);
+
+// ---------------------------------------------------------------- solve ----
+template <typename T>
+void filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                  const double* a, int K, const T* v, T* w, T* bufA, T* bufB);
+void bounds(polfed_ctx* ctx, const polfed_op* op, const double* x0, double tol,
+            int max_iter, double* E_min, double* E_max, int* iters);
+polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p,
+                    const double* x0, double* evals, double* evecs,
+                    double* resid, int* n_found, polfed_report* rep);
+polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
+                          const polfed_params& p, const double* const* x0,
+                          double* const* evals, double* const* evecs,
+                          double* const* resid, int* n_found,
+                          polfed_report* rep);
+double now_seconds();
+
+}  // namespace polfed

@@ -1,0 +1,539 @@
+// POLFED driver on one GPU (Sec. 4.6 of the paper): spectral bounds by
+// Lanczos, the filter plan, Lanczos on P(H~) with the Clenshaw filter and
+// full reorthogonalization (classical Gram-Schmidt, two passes), periodic
+// convergence checks on the tridiagonal Lanczos matrix, and the extraction
+// u = V t refined by Rayleigh-Ritz with H.
+//
+// Everything of size D stays on the device.  The host sees only the Lanczos
+// coefficients (copied at the periodic checks) and the small projected
+// matrices of the extraction.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace polfed {
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------- filter apply ----
+
+template <typename T>
+__global__ void k_scale_t(int64_t n, T a, const T* x, T* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+template <typename T>
+static void scale_t(hipStream_t s, int64_t n, T a, const T* x, T* y) {
+  if (!n) return;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256));
+  hipLaunchKernelGGL((k_scale_t<T>), dim3(g), dim3(256), 0, s, n, a, x, y);
+  HIPC(hipGetLastError());
+}
+
+// w = P(H~) v, eq. clenshaw_chebyshev_prod: b_{K+1} = b_{K+2} = 0,
+// b_i = a_i v + 2 H~ b_{i+1} - b_{i+2} for i = K..1, then
+// w = a_0 v + H~ b_1 - b_2.  b_i overwrites b_{i+2} in place, so two buffers
+// carry the recurrence.
+template <typename T>
+void filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                  const double* a, int K, const T* v, T* w, T* bufA, T* bufB) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  const T sigma = (T)(2.0 / dE), tau = (T)(-2.0 * E_c / dE);
+  if (K == 0) {
+    scale_t<T>(s, D, (T)a[0], v, w);
+    return;
+  }
+  scale_t<T>(s, D, (T)a[K], v, bufA);  // b_K
+  const T* cur = bufA;                  // b_{i+1}
+  T* prev = nullptr;                    // b_{i+2}
+  for (int i = K - 1; i >= 1; --i) {
+    T* out = prev ? prev : bufB;
+    op_step<T>(s, op, sigma, tau, (T)a[i], v, cur, prev, out);
+    prev = const_cast<T*>(cur);
+    cur = out;
+  }
+  op_step<T>(s, op, (T)(0.5 * sigma), (T)(0.5 * tau), (T)a[0], v, cur, prev, w);
+}
+
+template void filter_apply<double>(polfed_ctx*, const polfed_op*, double, double,
+                                   const double*, int, const double*, double*,
+                                   double*, double*);
+template void filter_apply<float>(polfed_ctx*, const polfed_op*, double, double,
+                                  const double*, int, const float*, float*, float*,
+                                  float*);
+
+// ------------------------------------------------------------ Lanczos ----
+
+namespace {
+
+struct Basis {
+  int64_t D = 0;
+  int cap = 0;  // columns available beyond v_0: V holds cap + 1 vectors
+  DevBuf V;
+  void ensure(hipStream_t s, int64_t D_, int need_cap, int keep_cols) {
+    if (need_cap <= cap && D_ == D) return;
+    DevBuf nv((size_t)D_ * (need_cap + 1) * sizeof(double));
+    if (keep_cols > 0)
+      HIPC(hipMemcpyAsync(nv.get(), V.get(), (size_t)D_ * keep_cols * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    V = std::move(nv);
+    D = D_;
+    cap = need_cap;
+  }
+  double* col(int j) const { return V.as<double>() + (size_t)j * D; }
+};
+
+struct Ws {
+  DevBuf w, c, partial, scal, flag, alpha, beta, bA, bB, v32, w32;
+  int64_t nseg = 0;
+  int coef_cap = 0;
+  void init(hipStream_t s, int64_t D, int max_cols, bool fp32) {
+    w.alloc(std::max<int64_t>(D, 1) * sizeof(double));
+    nseg = std::max<int64_t>(1, std::min<int64_t>(256, (D + 8191) / 8192));
+    grow(s, max_cols);
+    scal.alloc(64 * sizeof(double));
+    flag.alloc(sizeof(int));
+    HIPC(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+    const size_t tb = fp32 ? sizeof(float) : sizeof(double);
+    bA.alloc(std::max<int64_t>(D, 1) * tb);
+    bB.alloc(std::max<int64_t>(D, 1) * tb);
+    if (fp32) {
+      v32.alloc(std::max<int64_t>(D, 1) * sizeof(float));
+      w32.alloc(std::max<int64_t>(D, 1) * sizeof(float));
+    }
+  }
+  void grow(hipStream_t s, int max_cols) {
+    if (max_cols <= coef_cap) return;
+    DevBuf na((size_t)(max_cols + 1) * sizeof(double)), nb((size_t)(max_cols + 2) * sizeof(double));
+    if (coef_cap > 0) {
+      HIPC(hipMemcpyAsync(na.get(), alpha.get(), (size_t)(coef_cap + 1) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+      HIPC(hipMemcpyAsync(nb.get(), beta.get(), (size_t)(coef_cap + 2) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+      HIPC(hipStreamSynchronize(s));
+    }
+    alpha = std::move(na);
+    beta = std::move(nb);
+    c.alloc((size_t)(max_cols + 1) * sizeof(double));
+    partial.alloc((size_t)nseg * (max_cols + 1) * sizeof(double) + 8192 * sizeof(double));
+    coef_cap = max_cols;
+  }
+};
+
+// w <- w - V V^T w twice over the first k1 basis vectors; the first column
+// projection of each pass adds up alpha[k]; then beta_next = ||w|| and
+// v_next = w / beta_next.
+void cgs2_normalize(hipStream_t s, int64_t D, int k1, const Basis& B, Ws& ws,
+                    double* alpha_k, double* beta_next, double* v_next) {
+  double* w = ws.w.as<double>();
+  for (int pass = 0; pass < 2; ++pass) {
+    dev_gemv_t(s, D, k1, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
+               ws.c.as<double>(), alpha_k, pass);
+    dev_gemv_n_sub(s, D, k1, B.V.as<double>(), D, ws.c.as<double>(), w);
+  }
+  dev_dot(s, D, w, w, ws.partial.as<double>(), 1024, beta_next, 1);
+  dev_scale_into(s, D, w, beta_next, v_next, ws.flag.as<int>());
+}
+
+void normalize_into(hipStream_t s, int64_t D, const double* x, Ws& ws, double* out) {
+  double* nrm = ws.scal.as<double>();
+  dev_dot(s, D, x, x, ws.partial.as<double>(), 1024, nrm, 1);
+  dev_scale_into(s, D, x, nrm, out, ws.flag.as<int>());
+}
+
+void apply_H(hipStream_t s, const polfed_op* op, const double* x, double* y) {
+  op_step<double>(s, op, 1.0, 0.0, 0.0, nullptr, x, nullptr, y);
+}
+
+// Tridiagonal Lanczos matrix from alpha[0..m) and beta[1..m).
+void ritz_last(int m, const std::vector<double>& al, const std::vector<double>& be,
+               std::vector<double>& theta, std::vector<double>& zlast) {
+  theta.assign(al.begin(), al.begin() + m);
+  std::vector<double> e(m > 1 ? m - 1 : 0);
+  for (int i = 0; i + 1 < m; ++i) e[i] = be[i + 1];
+  std::vector<double> Z((size_t)m, 0.0);
+  Z[m - 1] = 1.0;  // track the last component only
+  tridiag_eig(m, theta, e, Z, 1);
+  zlast = Z;
+}
+
+void ritz_full(int m, const std::vector<double>& al, const std::vector<double>& be,
+               std::vector<double>& theta, std::vector<double>& Y /* m x m row-major */) {
+  theta.assign(al.begin(), al.begin() + m);
+  std::vector<double> e(m > 1 ? m - 1 : 0);
+  for (int i = 0; i + 1 < m; ++i) e[i] = be[i + 1];
+  Y.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Y[(size_t)i * m + i] = 1.0;
+  tridiag_eig(m, theta, e, Y, m);
+}
+
+template <typename T>
+void dcopy_async(hipStream_t s, T* dst, const T* src, size_t n, hipMemcpyKind k) {
+  if (n) HIPC(hipMemcpyAsync(dst, src, n * sizeof(T), k, s));
+}
+
+}  // namespace
+
+void bounds(polfed_ctx* ctx, const polfed_op* op, const double* x0, double tol,
+            int max_iter, double* E_min, double* E_max, int* iters) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  REQUIRE(D >= 1, "bounds: empty operator");
+  if (!(tol > 0)) tol = 1e-10;
+  if (max_iter <= 0) max_iter = 300;
+  const int cap = (int)std::min<int64_t>(max_iter, D);
+  Basis B;
+  B.ensure(s, D, cap, 0);
+  Ws ws;
+  ws.init(s, D, cap + 1, false);
+  normalize_into(s, D, x0, ws, B.col(0));
+  std::vector<double> al(cap + 1), be(cap + 2);
+  double lo = 0, hi = 0;
+  int k = 0;
+  for (;;) {
+    apply_H(s, op, B.col(k), ws.w.as<double>());
+    cgs2_normalize(s, D, k + 1, B, ws, ws.alpha.as<double>() + k,
+                   ws.beta.as<double>() + k + 1, B.col(k + 1));
+    ++k;
+    const bool last = k >= cap;
+    if (k % 10 == 0 || last) {
+      HIPC(hipMemcpyAsync(al.data(), ws.alpha.get(), k * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(be.data(), ws.beta.get(), (k + 1) * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      for (int i = 0; i < k; ++i)
+        if (!std::isfinite(al[i])) fail(POLFED_ERR_INVALID, "bounds: non-finite Lanczos coefficient");
+      std::vector<double> th, zl;
+      ritz_last(k, al, be, th, zl);
+      lo = th.front();
+      hi = th.back();
+      const double r_lo = std::fabs(be[k] * zl.front()), r_hi = std::fabs(be[k] * zl.back());
+      const double width = std::max(hi - lo, 1e-300);
+      const bool brk = be[k] <= 1e-13 * std::max(std::fabs(lo), std::fabs(hi));
+      if ((r_lo <= tol * width && r_hi <= tol * width) || last || brk) break;
+    }
+  }
+  *E_min = lo;
+  *E_max = hi;
+  if (iters) *iters = k;
+}
+
+// ------------------------------------------------------------- solve ----
+
+namespace {
+
+int buffer_size(int n_ev) { return std::max(10, (int)std::ceil(0.2 * n_ev)); }
+
+double target_energy(int kind, double target, double E_min, double E_max) {
+  switch (kind) {
+    case POLFED_TARGET_ABSOLUTE: return target;
+    case POLFED_TARGET_RESCALED: return 0.5 * (E_max + E_min) + target * 0.5 * (E_max - E_min);
+    case POLFED_TARGET_NORMALIZED: return E_min + target * (E_max - E_min);
+  }
+  fail(POLFED_ERR_INVALID, "unknown target kind");
+}
+
+struct Extracted {
+  std::vector<double> E, res;
+  std::vector<int> sel;  // chosen columns of U2, ordered by (|E - lam|, E)
+  bool complete = false;
+  DevBuf U2;             // D x n
+};
+
+// u = V t for the selected Ritz vectors, Rayleigh-Ritz with H on their span,
+// residual norms, choice of the n_ev nearest accepted pairs and the check
+// that no nearer eigenvalue can be missing.
+Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, int m,
+                  const std::vector<double>& Ysel /* m x n col-major */, int n,
+                  double theta_min, double lam, int n_ev, double tol_resid,
+                  const polfed_plan& pl) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  Extracted ex;
+  DevBuf dY((size_t)m * n * sizeof(double));
+  dcopy_async(s, dY.as<double>(), Ysel.data(), (size_t)m * n, hipMemcpyHostToDevice);
+  DevBuf U((size_t)D * n * sizeof(double)), HU((size_t)D * n * sizeof(double));
+  dev_gemm_nn(s, D, m, n, B.V.as<double>(), D, dY.as<double>(), U.as<double>(), D);
+  for (int j = 0; j < n; ++j) apply_H(s, op, U.as<double>() + (size_t)j * D, HU.as<double>() + (size_t)j * D);
+  DevBuf dG((size_t)n * n * sizeof(double));
+  DevBuf part((size_t)ws.nseg * n * sizeof(double) + 8192 * sizeof(double));
+  dev_gemm_tn(s, D, n, U.as<double>(), HU.as<double>(), part.as<double>(), ws.nseg,
+              dG.as<double>());
+  std::vector<double> G((size_t)n * n);
+  dcopy_async(s, G.data(), dG.as<double>(), G.size(), hipMemcpyDeviceToHost);
+  HIPC(hipStreamSynchronize(s));
+  std::vector<double> w, Z;
+  sym_eig(n, G, w, Z);
+  DevBuf dZ((size_t)n * n * sizeof(double)), dE((size_t)n * sizeof(double)),
+      dR((size_t)n * sizeof(double));
+  dcopy_async(s, dZ.as<double>(), Z.data(), Z.size(), hipMemcpyHostToDevice);
+  dcopy_async(s, dE.as<double>(), w.data(), w.size(), hipMemcpyHostToDevice);
+  ex.U2.alloc((size_t)D * n * sizeof(double));
+  DevBuf HU2((size_t)D * n * sizeof(double));
+  dev_gemm_nn(s, D, n, n, U.as<double>(), D, dZ.as<double>(), ex.U2.as<double>(), D);
+  dev_gemm_nn(s, D, n, n, HU.as<double>(), D, dZ.as<double>(), HU2.as<double>(), D);
+  dev_resid(s, D, n, ex.U2.as<double>(), HU2.as<double>(), dE.as<double>(), part.as<double>(),
+            ws.nseg, dR.as<double>());
+  ex.res.resize(n);
+  dcopy_async(s, ex.res.data(), dR.as<double>(), (size_t)n, hipMemcpyDeviceToHost);
+  HIPC(hipStreamSynchronize(s));
+  ex.E = w;
+  std::vector<int> ok;
+  for (int j = 0; j < n; ++j)
+    if (ex.res[j] <= tol_resid) ok.push_back(j);
+  std::stable_sort(ok.begin(), ok.end(), [&](int a, int b) {
+    const double da = std::fabs(ex.E[a] - lam), db = std::fabs(ex.E[b] - lam);
+    if (da != db) return da < db;
+    return ex.E[a] < ex.E[b];
+  });
+  if ((int)ok.size() > n_ev) ok.resize(n_ev);
+  ex.sel = ok;
+  if ((int)ok.size() == n_ev && n_ev > 0) {
+    double d = 0;
+    for (int j : ok) d = std::max(d, std::fabs(ex.E[j] - lam));
+    d /= pl.dE;
+    const double pm = filter_value_closed(pl.lambda_t, pl.K, pl.lambda_t - d);
+    const double pp = filter_value_closed(pl.lambda_t, pl.K, pl.lambda_t + d);
+    ex.complete = std::min(pm, pp) >= theta_min;
+  }
+  return ex;
+}
+
+double step_bytes(const polfed_op* op, int precision) {
+  const double w = precision == POLFED_FP32 ? 4.0 : 8.0;
+  double b = 4.0 * w * (double)op->D;
+  if (op->storage == POLFED_CSR)
+    b += (double)op->nnz * (w + 4.0) + 8.0 * (double)(op->D + 1) + w * (double)op->D;
+  return b;
+}
+
+}  // namespace
+
+polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p,
+                    const double* x0, double* evals, double* evecs, double* resid,
+                    int* n_found, polfed_report* rep) {
+  hipStream_t s = ctx->stream;
+  const double t_start = now_seconds();
+  const int64_t D = op->D;
+  REQUIRE(D >= 1, "solve: empty operator");
+  REQUIRE(p.n_ev >= 1 && p.n_ev <= D, "solve: need 1 <= n_ev <= D");
+  REQUIRE(p.precision == POLFED_FP64 || p.precision == POLFED_FP32, "solve: bad precision");
+  REQUIRE(x0 && evals && evecs && resid && n_found, "solve: null buffer");
+  const bool fp32 = p.precision == POLFED_FP32;
+  const double tol_resid = p.tol_resid > 0 ? p.tol_resid : 1e-8;
+  const double pad = p.bound_pad > 0 ? p.bound_pad : 1e-3;
+  const double eta = p.eta > 0 ? p.eta : 1.5;
+  polfed_report R{};
+  *n_found = 0;
+
+  // 1. spectral bounds
+  double E_min = p.E_min, E_max = p.E_max;
+  double t0 = now_seconds();
+  if (!(E_max > E_min)) {
+    int it = 0;
+    bounds(ctx, op, x0, 1e-10, 300, &E_min, &E_max, &it);
+  }
+  R.t_bounds = now_seconds() - t0;
+  R.E_min = E_min;
+  R.E_max = E_max;
+
+  // 2-3. trace moments, DOS, window, K, coefficients
+  t0 = now_seconds();
+  DevBuf two(2 * sizeof(double)), mpart(2 * 4096 * sizeof(double));
+  op_moments(s, op, two.as<double>(), mpart.as<double>(), 4096);
+  double tr[2];
+  HIPC(hipMemcpyAsync(tr, two.get(), sizeof tr, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  const double tr1 = tr[0] / (double)D, tr2 = tr[1] / (double)D;
+  const double lam = target_energy(p.target_kind, p.target, E_min, E_max);
+  int n_want = (int)std::min<int64_t>(D, p.n_ev + buffer_size(p.n_ev));
+  const polfed_plan pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega,
+                                   p.K_override);
+  std::vector<double> a(pl.K + 1);
+  filter_coefficients(pl.lambda_t, pl.K, a.data());
+  R.t_plan = now_seconds() - t0;
+  R.lambda = lam;
+  R.lambda_t = pl.lambda_t;
+  R.E_c = pl.E_c;
+  R.dE = pl.dE;
+  R.delta = pl.delta;
+  R.rho = pl.rho;
+  R.K = pl.K;
+
+  // 4. filtered Lanczos
+  const int M_alloc = expected_krylov_dim(n_want, 1, eta);
+  const int M_max = (int)std::min<int64_t>(D, p.max_iter > 0 ? p.max_iter : 4 * M_alloc);
+  int cap = std::min(M_alloc, M_max);
+  R.M_alloc = M_alloc;
+  Basis B;
+  B.ensure(s, D, cap, 0);
+  Ws ws;
+  ws.init(s, D, cap + 1, fp32);
+  normalize_into(s, D, x0, ws, B.col(0));
+  const int check_every = std::max(10, (int)std::ceil(0.05 * M_alloc));
+  int next_check = std::min(n_want, M_max);
+  std::vector<double> al, be;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> fev, rev;
+  auto ev_pair = [&]() {
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    return std::make_pair(e0, e1);
+  };
+  auto drain = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& acc) {
+    for (auto& pr : v) {
+      float ms = 0;
+      HIPC(hipEventElapsedTime(&ms, pr.first, pr.second));
+      acc += 1e-3 * ms;
+      HIPC(hipEventDestroy(pr.first));
+      HIPC(hipEventDestroy(pr.second));
+    }
+    v.clear();
+  };
+  const double sbytes = step_bytes(op, p.precision);
+  int k = 0;
+  polfed_status status = POLFED_NOT_CONVERGED;
+  uint64_t restart_seed = 0x5EEDULL;
+  for (;;) {
+    auto fe = ev_pair();
+    HIPC(hipEventRecord(fe.first, s));
+    if (fp32) {
+      dev_copy_d2f(s, D, B.col(k), ws.v32.as<float>());
+      filter_apply<float>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, ws.v32.as<float>(),
+                          ws.w32.as<float>(), ws.bA.as<float>(), ws.bB.as<float>());
+      dev_copy_f2d(s, D, ws.w32.as<float>(), ws.w.as<double>());
+    } else {
+      filter_apply<double>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, B.col(k),
+                           ws.w.as<double>(), ws.bA.as<double>(), ws.bB.as<double>());
+    }
+    HIPC(hipEventRecord(fe.second, s));
+    fev.push_back(fe);
+    R.filter_steps += pl.K;
+    auto re = ev_pair();
+    HIPC(hipEventRecord(re.first, s));
+    cgs2_normalize(s, D, k + 1, B, ws, ws.alpha.as<double>() + k,
+                   ws.beta.as<double>() + k + 1, B.col(k + 1));
+    HIPC(hipEventRecord(re.second, s));
+    rev.push_back(re);
+    ++k;
+    if (k >= cap && cap < M_max) {
+      const int ncap = std::min(M_max, (int)std::ceil(1.25 * cap) + 1);
+      B.ensure(s, D, ncap, k + 1);
+      ws.grow(s, ncap + 1);
+      cap = ncap;
+    }
+    if (k < next_check && k < M_max) continue;
+
+    // periodic check (eq. lan_criterion)
+    const double tc = now_seconds();
+    al.resize(k);
+    be.resize(k + 1);
+    int flag = 0;
+    HIPC(hipMemcpyAsync(al.data(), ws.alpha.get(), k * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(be.data(), ws.beta.get(), (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(&flag, ws.flag.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    drain(fev, R.t_filter);
+    drain(rev, R.t_reorth);
+    for (int i = 0; i < k; ++i)
+      if (!std::isfinite(al[i]) || std::fabs(al[i]) > 4.0 || !std::isfinite(be[i + 1]))
+        fail(POLFED_ERR_BOUNDS,
+             "filter blow-up: Lanczos coefficient " + std::to_string(al[i]) +
+                 " at step " + std::to_string(i) + " (spectral bounds too tight?)");
+    // breakdown: restart from the first vanishing beta with a random vector
+    int kb = -1;
+    for (int i = 1; i <= k; ++i)
+      if (be[i] <= 1e-13) { kb = i; break; }
+    if (kb > 0 && kb < M_max) {
+      if (R.restarts >= 8) fail(POLFED_ERR_BREAKDOWN, "Lanczos breakdown: too many restarts");
+      ++R.restarts;
+      k = kb;
+      double* w = ws.w.as<double>();
+      dev_random(s, D, restart_seed++, w);
+      double* junk = ws.scal.as<double>() + 8;
+      for (int pass = 0; pass < 2; ++pass) {
+        dev_gemv_t(s, D, k, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
+                   ws.c.as<double>(), junk, 0);
+        dev_gemv_n_sub(s, D, k, B.V.as<double>(), D, ws.c.as<double>(), w);
+      }
+      double zero = 0.0;
+      HIPC(hipMemcpyAsync(ws.beta.as<double>() + k, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+      normalize_into(s, D, w, ws, B.col(k));
+      HIPC(hipMemsetAsync(ws.flag.get(), 0, sizeof(int), s));
+      HIPC(hipStreamSynchronize(s));
+      next_check = k + 1;
+      R.t_check += now_seconds() - tc;
+      continue;
+    }
+    ++R.checks;
+    std::vector<double> th, zl;
+    ritz_last(k, al, be, th, zl);
+    std::vector<int> order(k);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return th[x] > th[y]; });
+    const int nw = std::min(n_want, k);
+    double thmax = 0;
+    for (double t : th) thmax = std::max(thmax, std::fabs(t));
+    bool conv = true;
+    for (int j = 0; j < nw; ++j)
+      if (std::fabs(be[k] * zl[order[j]]) > 1e-10 * std::max(1.0, thmax)) conv = false;
+    R.t_check += now_seconds() - tc;
+    if (conv || k >= M_max) {
+      const double tx = now_seconds();
+      std::vector<double> thf, Y;
+      ritz_full(k, al, be, thf, Y);
+      // the full solve orders eigenvalues alike; pick the n_want largest
+      std::vector<int> ord(k);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return thf[x] > thf[y]; });
+      std::vector<double> Ysel((size_t)k * nw);
+      for (int j = 0; j < nw; ++j)
+        for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
+      const double theta_min = thf[ord[nw - 1]];
+      Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw, theta_min, lam, p.n_ev, tol_resid, pl);
+      R.t_extract += now_seconds() - tx;
+      const bool done = (int)ex.sel.size() == p.n_ev && ex.complete;
+      if (done || k >= M_max) {
+        const int nf = (int)ex.sel.size();
+        std::vector<double> Eo(nf), Ro(nf);
+        for (int j = 0; j < nf; ++j) {
+          Eo[j] = ex.E[ex.sel[j]];
+          Ro[j] = ex.res[ex.sel[j]];
+          dcopy_async(s, evecs + (size_t)j * D, ex.U2.as<double>() + (size_t)ex.sel[j] * D,
+                      (size_t)D, hipMemcpyDeviceToDevice);
+        }
+        dcopy_async(s, evals, Eo.data(), (size_t)nf, hipMemcpyHostToDevice);
+        dcopy_async(s, resid, Ro.data(), (size_t)nf, hipMemcpyHostToDevice);
+        HIPC(hipStreamSynchronize(s));
+        *n_found = nf;
+        R.n_converged = nf;
+        status = done ? POLFED_OK : POLFED_NOT_CONVERGED;
+        break;
+      }
+      if ((int)ex.sel.size() == p.n_ev && !ex.complete)
+        n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
+    }
+    next_check = k + check_every;
+  }
+  drain(fev, R.t_filter);
+  drain(rev, R.t_reorth);
+  R.iters = k;
+  R.n_want = n_want;
+  R.filter_bytes = R.filter_steps * sbytes;
+  R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
+  R.t_total = now_seconds() - t_start;
+  if (rep) *rep = R;
+  return status;
+}
+
+}  // namespace polfed
