@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the POLFED hot path on one MI355X.
+
+Workload (the headline metric's configuration): random-field XXZ chain,
+L = 24, periodic, J = Delta = 1, h_i ~ U[-3, 3] (seed 0), Sz = 0 sector
+(D = 2,704,156), N_ev = 100 eigenpairs nearest normalized energy 0.5, FP64,
+matrix-free operator.  The plan (bounds, trace moments, order K) is the
+solve's own.
+
+One timed step is one filtered Lanczos iteration of that solve: the filter
+P(H~) v by K fused Clenshaw steps (K is the plan's order) and the full
+reorthogonalization of the result against a Krylov basis of half the
+expected Krylov dimension.  value = filtered-SpMV GB/s = algorithmic filter
+bytes of one step (K * 4 * 8 * D: read v, b_{i+1}, b_{i+2}, write b_i per
+Clenshaw step) / measured time per step.
+
+Beside it the JSON line carries
+  roofline      the fused step kernel's algorithmic bytes per launch over its
+                mean duration (HIP events around each launch), against the
+                8 TB/s HBM peak; traffic = HBM bytes per launch from the
+                rocprofv3 counters recorded in profiles/, when they were taken
+                on the current kernel source;
+  eigenpairs_per_s  a complete solve of the XXZ L=20 workload (100 pairs);
+  cpu_baseline  the CPU oracle's Clenshaw steps at L=24 on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_step_xxz_L24_fp64.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_10191_amd", "csrc", "ops.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counters, or None when
+    they were taken on another version of the kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != kernel_source_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def xxz_setup(pk, wl, ctx, L, W, seed, n_ev):
+    h = wl.xxz_fields(L, W, seed)
+    op = pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, h, True)
+    import torch
+    x0 = torch.tensor(wl.start_vector(op.D, seed), device=ctx.torch_device)
+    E_min, E_max = pk.bounds(op, x0)
+    tr1, tr2 = op.moments()
+    lam = E_min + 0.5 * (E_max - E_min)
+    n_want = n_ev + max(10, math.ceil(0.2 * n_ev))
+    plan = pk.make_plan(op.D, E_min, E_max, 1e-3, lam, tr1, tr2, n_want)
+    return op, x0, (E_min, E_max, lam, n_want, plan)
+
+
+def cpu_baseline(L: int, W: float, seed: int, steps: int):
+    """The oracle (plain FP64 SciPy CSR Clenshaw) on the same workload: a
+    sample of `steps` Clenshaw steps, converted to the same algorithmic
+    bytes per step as the GPU figure."""
+    import numpy as np
+    import workloads as wl
+    from oracle import filter as flt
+    from oracle import models
+    h = wl.xxz_fields(L, W, seed)
+    H, _ = models.xxz(L, L // 2, 1.0, 1.0, h)
+    D = H.shape[0]
+    a = flt.coefficients(0.0, steps)
+    v = wl.start_vector(D, seed)
+    t0 = time.perf_counter()
+    flt.apply_filter(H, 0.0, 22.0, a, v)
+    dt = time.perf_counter() - t0
+    gbs = steps * 4 * 8 * D / dt / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} Clenshaw steps (K={steps} filter application) of the "
+                      f"oracle's SciPy CSR recurrence, XXZ L={L} D={D}, "
+                      f"{dt:.1f} s; host has {os.cpu_count()} CPUs, "
+                      "SciPy sparse mat-vec runs on one thread",
+            "ms_per_clenshaw_step": round(1e3 * dt / steps, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=24)
+    ap.add_argument("--W", type=float, default=3.0)
+    ap.add_argument("--n-ev", type=int, default=100)
+    ap.add_argument("--solve-L", type=int, default=20)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--profile-iters", type=int, default=300)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the step kernel and a plain copy (counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_10191_amd as pk
+    import workloads as wl
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    ctx = pk.Context(0)
+    if args.profile_only:
+        # counter runs: the step kernel alone, then a plain copy of known size
+        h = wl.xxz_fields(args.L, args.W, 0)
+        op = pk.Operator.xxz(ctx, args.L, args.L // 2, 1.0, 1.0, h, True)
+        avg_ms, _ = pk.profile_step(op, pk.FP64, args.profile_iters)
+        n = 64 * 1024 * 1024  # 512 MiB of FP64
+        x = torch.ones(n, dtype=torch.float64, device=ctx.torch_device)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"profile-only: step kernel {avg_ms * 1e3:.2f} us; copied {n * 8} bytes x3")
+        return
+    t0 = time.time()
+    op, x0, (E_min, E_max, lam, n_want, plan) = xxz_setup(
+        pk, wl, ctx, args.L, args.W, 0, args.n_ev)
+    D, K = op.D, plan.K
+    a = pk.filter_coefficients(plan.lambda_t, K)
+    log(f"setup L={args.L} D={D} bounds=[{E_min:.6f},{E_max:.6f}] K={K} "
+        f"({time.time() - t0:.1f}s)")
+
+    # Krylov basis at half the expected depth, built with cheap unfiltered
+    # Lanczos steps (its content only sets the reorthogonalization cost).
+    M = math.ceil((20.427 + 1.696 * n_want) * 1.5)
+    depth = M // 2
+    ncols = depth + args.warmup + args.steps + 1
+    V = torch.empty((ncols + 1, D), dtype=torch.float64, device=ctx.torch_device)
+    V[0] = x0 / torch.linalg.vector_norm(x0)
+    alpha = torch.zeros(ncols + 1, dtype=torch.float64, device=ctx.torch_device)
+    beta = torch.zeros(ncols + 2, dtype=torch.float64, device=ctx.torch_device)
+    a_lin = np.array([0.0, 1.0])  # P(H~) = H~: one mat-vec per step
+    for k in range(depth):
+        pk.lanczos_step(op, plan.E_c, plan.dE, a_lin, V, k, alpha[k:k + 1],
+                        beta[k + 1:k + 2])
+    ctx.sync()
+    log(f"basis depth {depth} ready ({time.time() - t0:.1f}s)")
+
+    k = depth
+    for _ in range(args.warmup):
+        pk.lanczos_step(op, plan.E_c, plan.dE, a, V, k, alpha[k:k + 1],
+                        beta[k + 1:k + 2])
+        k += 1
+    ctx.sync()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        pk.lanczos_step(op, plan.E_c, plan.dE, a, V, k, alpha[k:k + 1],
+                        beta[k + 1:k + 2])
+        k += 1
+        ctx.sync()
+        log(f"step {i + 1}/{args.steps} done ({time.perf_counter() - t_start:.1f}s)")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    al = alpha[depth:k].cpu().numpy()
+    be = beta[depth + 1:k + 1].cpu().numpy()
+    assert np.all(np.isfinite(al)) and np.all(np.abs(al) <= 1.5), al
+    assert np.all(np.isfinite(be)) and np.all(be > 0), be
+    step_bytes = 4 * 8 * D
+    value = K * step_bytes / (ms_per_step / 1e3) / 1e9
+
+    # roofline of the fused Clenshaw step kernel
+    avg_ms, min_ms = pk.profile_step(op, pk.FP64, args.profile_iters)
+    achieved = step_bytes / (avg_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "k_chain_step<double,4>",
+                "kernel_ms_avg": round(avg_ms, 5), "kernel_ms_min": round(min_ms, 5),
+                "bytes_per_launch": step_bytes}
+    log(f"step kernel {avg_ms * 1e3:.2f} us avg -> {achieved:.0f} GB/s")
+
+    out = {"metric": "filtered-SpMV GB/s (% HBM peak) + eigenpairs/s, XXZ L=24; "
+                     "p50/p99 batched solve ms",
+           "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded random fields)",
+           "config": {"workload": f"random-field XXZ chain L={args.L} periodic "
+                                  f"J=1 Delta=1 W={args.W} seed 0, Sz=0 (D={D}), "
+                                  f"N_ev={args.n_ev} at normalized energy 0.5, "
+                                  "matrix-free FP64; step = one filtered Lanczos "
+                                  f"iteration (K={K} Clenshaw steps + CGS2 at "
+                                  f"depth {depth})",
+                      "K": K, "D": D, "hbm_frac": round(value / HBM_PEAK_GBS, 4)},
+           "roofline": roofline}
+
+    if not args.no_solve:
+        opS, x0S, (_, _, lamS, _, _) = xxz_setup(pk, wl, ctx, args.solve_L, 3.0, 0,
+                                                 args.n_ev)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ev, U, res, rep, status = pk.solve(opS, x0S, args.n_ev, lamS, "absolute")
+        torch.cuda.synchronize()
+        tsolve = time.perf_counter() - ts
+        out["eigenpairs_per_s"] = {
+            "value": round(args.n_ev / tsolve, 3) if status == "OK" else None,
+            "unit": "eigenpairs/s",
+            "workload": f"XXZ L={args.solve_L} W=3 seed 0 (D={opS.D}), "
+                        f"{args.n_ev} pairs at normalized energy 0.5, FP64, full solve",
+            "solve_s": round(tsolve, 2), "status": status, "K": rep["K"],
+            "iters": rep["iters"], "max_resid": float(res.max().item()),
+            "filter_GBps": round(rep["filter_GBps"], 1),
+            "t_filter": round(rep["t_filter"], 2), "t_reorth": round(rep["t_reorth"], 2)}
+        log(f"solve L={args.solve_L}: {tsolve:.1f}s status={status}")
+    out["p50_p99_batched_solve_ms"] = None
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.L, args.W, 0, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

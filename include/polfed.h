@@ -221,6 +221,25 @@ polfed_status polfed_bounds(polfed_ctx* ctx, const polfed_op* op,
                             const double* x0, double tol, int max_iter,
                             double* E_min, double* E_max);
 
+/* One Lanczos step on the filtered operator (Sec. 4.3 with block size 1):
+ * w = P(H~) v_k by the Clenshaw filter (a[0..K], host), full
+ * reorthogonalization of w against v_0..v_k by classical Gram-Schmidt
+ * applied twice, *alpha = v_k^T P(H~) v_k, *beta = ||w||, v_{k+1} = w / beta.
+ * V: device basis, column-major D x (k+2), columns 0..k orthonormal; column
+ * k+1 is written.  alpha, beta: device scalars.  precision selects the
+ * Clenshaw arithmetic (the basis is FP64 either way).  Asynchronous. */
+polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
+                                  double E_c, double dE, const double* a,
+                                  int K, double* V, int k, double* alpha,
+                                  double* beta, int precision);
+/* Measurement helper: runs `iters` back-to-back launches of the fused
+ * Clenshaw step kernel on scratch vectors with HIP events around each
+ * launch, and returns the mean and minimum kernel time in milliseconds
+ * (host results; synchronizes). */
+polfed_status polfed_profile_step(polfed_ctx* ctx, const polfed_op* op,
+                                  int precision, int iters, double* avg_ms,
+                                  double* min_ms);
+
 typedef struct {
   int target_kind;     /* POLFED_TARGET_* */
   double target;

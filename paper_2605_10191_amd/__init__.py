@@ -104,6 +104,8 @@ SIGNATURES = {
     "polfed_filter_apply": [_P, _P, _D, _D, _DP, _I, _P, _P, _I],
     "polfed_clenshaw_step": [_P, _P, _D, _D, _D, _P, _P, _P, _I, _I],
     "polfed_bounds": [_P, _P, _P, _D, _I, _DP, _DP],
+    "polfed_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _P, _P, _I],
+    "polfed_profile_step": [_P, _P, _I, _I, _DP, _DP],
     "polfed_params_default": [ctypes.POINTER(Params)],
     "polfed_solve": [_P, _P, ctypes.POINTER(Params), _P, _P, _P, _P,
                      ctypes.POINTER(_I), ctypes.POINTER(Report)],
@@ -132,6 +134,9 @@ def load_library(path: str = LIB_PATH):
         raise ImportError(
             f"{path} is missing: build it with "
             "`python -m paper_2605_10191_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch loaded
+    # (same soname), so one runtime serves both in the process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, args in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -390,6 +395,24 @@ def bounds(op: Operator, x0, tol=1e-10, max_iter=300):
     _check(_lib.polfed_bounds(op.ctx.handle, op.handle, _ptr(x0), tol,
                               max_iter, ctypes.byref(lo), ctypes.byref(hi)))
     return lo.value, hi.value
+
+
+def lanczos_step(op: Operator, E_c, dE, a, V, k, alpha, beta, precision=FP64):
+    """One filtered Lanczos step on the device basis V (a (k+2, D) tensor,
+    rows = basis vectors); alpha and beta are one-element device tensors."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    _check(_lib.polfed_lanczos_step(op.ctx.handle, op.handle, E_c, dE, _dptr(a),
+                                    len(a) - 1, _ptr(V), int(k), _ptr(alpha),
+                                    _ptr(beta), precision))
+
+
+def profile_step(op: Operator, precision=FP64, iters=200):
+    """(mean, min) milliseconds of the fused Clenshaw step kernel."""
+    avg, mn = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.polfed_profile_step(op.ctx.handle, op.handle, precision,
+                                    int(iters), ctypes.byref(avg),
+                                    ctypes.byref(mn)))
+    return avg.value, mn.value
 
 
 def make_params(n_ev, target, target_kind="normalized", precision=FP64,

@@ -489,6 +489,35 @@ polfed_status polfed_bounds(polfed_ctx* ctx, const polfed_op* op, const double* 
   });
 }
 
+polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c,
+                                  double dE, const double* a, int K, double* V, int k,
+                                  double* alpha, double* beta, int precision) {
+  return guarded([&]() -> polfed_status {
+    check_step_args(ctx, op, dE, precision);
+    REQUIRE(std::isfinite(E_c), "E_c must be finite");
+    REQUIRE(K >= 0 && a, "need K >= 0 and coefficients a[K+1]");
+    REQUIRE(k >= 0 && k + 1 < op->D + 1, "need 0 <= k and k + 1 <= D");
+    REQUIRE(V && alpha && beta, "null buffer");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    lanczos_step(ctx, op, E_c, dE, a, K, V, k, alpha, beta, precision);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_profile_step(polfed_ctx* ctx, const polfed_op* op, int precision,
+                                  int iters, double* avg_ms, double* min_ms) {
+  return guarded([&]() -> polfed_status {
+    check_step_args(ctx, op, 1.0, precision);
+    REQUIRE(iters >= 1 && iters <= 100000, "need 1 <= iters <= 100000");
+    REQUIRE(avg_ms && min_ms, "null output");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    profile_step(ctx, op, precision, iters, avg_ms, min_ms);
+    return POLFED_OK;
+  });
+}
+
 polfed_status polfed_params_default(polfed_params* p) {
   return guarded([&]() -> polfed_status {
     REQUIRE(p, "null params");

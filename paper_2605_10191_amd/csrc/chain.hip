@@ -1,0 +1,384 @@
+// Fused Clenshaw step for the chain models (XXZ, t-V) in a particle-number
+// sector, laid out for wave64 execution.
+//
+// A state is split as s = hi << Lb | lo.  States in ascending order are
+// grouped by hi, and the rows of one hi form a contiguous block of
+// binom(Lb, N - popcount(hi)) rows (at most 252 for Lb = 10) whose low parts
+// run through the Lb-bit strings of that popcount in ascending order, so
+//     rank(s) = hi_off[hi] + lo_rank[lo]
+// and the position of a row inside its block is lo_rank[lo].
+//
+// Each wavefront processes a segment of one block (up to 128 rows, lanes on
+// consecutive rows).  Within a wavefront hi is uniform, hence:
+//   - a hop inside the low part stays in the block.  The wavefront stages
+//     the block's b_{i+1} entries in LDS once (coalesced) and reads those
+//     neighbours from LDS at position lo_rank[lo'];
+//   - a hop across a bond inside the high part moves to row r + d with a
+//     wave-uniform d = hi_off[hi'] - hi_off[hi]: fully coalesced gathers;
+//   - the bond joining the two parts and the periodic bond land in another
+//     block at r + d + lo_rank[lo'] - lo_rank[lo] (d uniform);
+//   - the diagonal is DLO[lo] (LDS) + a uniform high part + two cross terms.
+// All wave-uniform data of a segment (offsets, flags, diagonal part) is
+// precomputed into a 128-byte record read with scalar loads, prefetched one
+// segment ahead.  Every gather is issued unconditionally (a bond that cannot
+// hop reads the row's own entry, which is subtracted again), so the gathers
+// of a lane's rows are in flight together.
+//
+// Locality: the eight XCDs each sweep a contiguous eighth of the segments
+// (workgroups are dispatched to the XCDs round robin), so most high-part
+// gathers of an XCD stay in its own L2; the streamed vectors v, b2 and the
+// output use non-temporal accesses so they do not evict the gathered one.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace polfed {
+
+void build_chain_split(polfed_op* op) {
+  const int L = op->L, N = op->N;
+  const int Lb = std::min(kChainLoBits, L / 2), Lh = L - Lb;
+  REQUIRE(Lh - 1 <= kChainMaxHighBonds, "chain: too many high bonds");
+  const int nlo = 1 << Lb;
+  // low parts: ranks within their popcount class, list grouped by popcount
+  std::vector<int32_t> lo_rank(nlo), cnt(Lb + 1, 0), lo_base(Lb + 2, 0);
+  for (int lo = 0; lo < nlo; ++lo) lo_rank[lo] = cnt[__builtin_popcount(lo)]++;
+  for (int p = 0; p <= Lb; ++p) lo_base[p + 1] = lo_base[p] + cnt[p];
+  std::vector<uint16_t> lolist(nlo);
+  for (int lo = 0; lo < nlo; ++lo)
+    lolist[lo_base[__builtin_popcount(lo)] + lo_rank[lo]] = (uint16_t)lo;
+  // block positions of the low-bond neighbours (own position if no hop), then
+  // the ranks of lo with its top bit and with bit 0 flipped (all < 256)
+  std::vector<uint8_t> npos((size_t)nlo * 16, 0);
+  for (int lo = 0; lo < nlo; ++lo) {
+    uint8_t* q = &npos[(size_t)lo * 16];
+    for (int b = 0; b + 1 < Lb; ++b) {
+      const bool act = ((lo >> b) & 1) != ((lo >> (b + 1)) & 1);
+      q[b] = (uint8_t)(act ? lo_rank[lo ^ (3 << b)] : lo_rank[lo]);
+    }
+    q[9] = (uint8_t)lo_rank[lo ^ (1 << (Lb - 1))];
+    q[10] = (uint8_t)lo_rank[lo ^ 1];
+  }
+  std::vector<double> dlo(nlo);
+  for (int lo = 0; lo < nlo; ++lo) {
+    double f = op->vzz * __builtin_popcount(lo & (lo >> 1));
+    for (int i = 0; i < Lb; ++i)
+      if ((lo >> i) & 1) f += op->site_f[i];
+    dlo[lo] = f;
+  }
+  // high parts: first row of each block
+  const int64_t nhi = (int64_t)1 << Lh;
+  std::vector<int32_t> hi_off(nhi + 1, 0);
+  int64_t acc = 0;
+  for (int64_t hi = 0; hi < nhi; ++hi) {
+    hi_off[hi] = (int32_t)acc;
+    const int need = N - __builtin_popcountll(hi);
+    if (need >= 0 && need <= Lb) acc += cnt[need];
+  }
+  hi_off[nhi] = (int32_t)acc;
+  // one record per segment
+  std::vector<int32_t> rec;
+  for (int64_t hi = 0; hi < nhi; ++hi) {
+    const int need = N - __builtin_popcountll(hi);
+    if (need < 0 || need > Lb) continue;
+    const int bs = cnt[need];
+    const int hoff = hi_off[hi];
+    double dhi = op->vzz * __builtin_popcountll(hi & (hi >> 1)) + op->c0;
+    for (int i = 0; i < Lh; ++i)
+      if ((hi >> i) & 1) dhi += op->site_f[Lb + i];
+    int32_t w[kChainRecWords] = {0};
+    int idle = 0;
+    for (int b = 0; b + 1 < Lh; ++b) {
+      const bool act = ((hi >> b) & 1) != ((hi >> (b + 1)) & 1);
+      w[10 + b] = act ? hi_off[hi ^ (3LL << b)] - hoff : 0;
+      idle += act ? 0 : 1;
+    }
+    w[4] = idle;
+    w[5] = hi_off[hi ^ 1] - hoff;
+    w[6] = hi_off[hi ^ (1LL << (Lh - 1))] - hoff;
+    std::memcpy(&w[8], &dhi, sizeof(double));
+    for (int st = 0; st < bs; st += kChainSegRows) {
+      w[0] = hoff + st;
+      w[1] = std::min(kChainSegRows, bs - st);
+      w[2] = lo_base[need] + st;
+      w[3] = (int32_t)((hi & 1) | (((hi >> (Lh - 1)) & 1) << 1) | (bs << 2) | (st << 12));
+      rec.insert(rec.end(), w, w + kChainRecWords);
+    }
+  }
+  hipStream_t s = op->ctx->stream;
+  op->split_Lb = Lb;
+  op->split_nseg = (int64_t)(rec.size() / kChainRecWords);
+  // packed LDS images: [neighbour positions | diagonal of the low part (T) |
+  // low-part list]
+  for (int w = 0; w < 2; ++w) {
+    const int tb = w == 0 ? 8 : 4;
+    std::vector<unsigned char> blob(chain_blob_bytes(nlo, tb), 0);
+    unsigned char* p = blob.data();
+    std::memcpy(p, npos.data(), npos.size());
+    p += npos.size();
+    for (int lo = 0; lo < nlo; ++lo) {
+      if (tb == 8) {
+        std::memcpy(p + 8 * lo, &dlo[lo], 8);
+      } else {
+        const float f = (float)dlo[lo];
+        std::memcpy(p + 4 * lo, &f, 4);
+      }
+    }
+    std::memcpy(p + (size_t)tb * nlo, lolist.data(), 2 * (size_t)nlo);
+    upload(w == 0 ? op->d_blob64 : op->d_blob32, blob.data(), blob.size(), s);
+  }
+  upload(op->d_rec, rec.data(), rec.size(), s);
+  HIPC(hipStreamSynchronize(s));
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Orders the LDS accesses of a wavefront around a staging step.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave-uniform data of one segment (see the record layout).
+template <int NH>
+struct SegRec {
+  int row0, len, lidx, flags, n_idle_h, d_join, d_pbc;
+  double dhi;
+  int dh[NH > 0 ? NH : 1];
+};
+
+template <int NH>
+__device__ __forceinline__ SegRec<NH> load_rec(const int32_t* rec) {
+  SegRec<NH> r;
+  r.row0 = uniform(rec[0]);
+  r.len = uniform(rec[1]);
+  r.lidx = uniform(rec[2]);
+  r.flags = uniform(rec[3]);
+  r.n_idle_h = uniform(rec[4]);
+  r.d_join = uniform(rec[5]);
+  r.d_pbc = uniform(rec[6]);
+  int dw[2] = {uniform(rec[8]), uniform(rec[9])};
+  __builtin_memcpy(&r.dhi, dw, sizeof(double));
+#pragma unroll
+  for (int b = 0; b < NH; ++b) r.dh[b] = uniform(rec[10 + b]);
+  return r;
+}
+
+// Buffer accesses: a 128-bit resource for each vector, a per-lane 32-bit
+// byte offset (VGPR) and a wave-uniform byte offset (SGPR), so gathers at
+// uniform row offsets need no per-lane address arithmetic.  Accesses beyond
+// the resource's size return 0 / are dropped by the hardware.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kAuxNT = 2;  // non-temporal cache policy
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t vo, uint32_t so) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, AUX));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, AUX));
+}
+template <int AUX, typename T>
+__device__ __forceinline__ void bstore(T x, rsrc_t r, uint32_t vo, uint32_t so) {
+  using u2 = __attribute__((ext_vector_type(2))) unsigned int;
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, vo, so, AUX);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, vo, so, AUX);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_chain_split(
+    ChainSplitDev c, T sigma, T tau, T a, const T* __restrict__ v,
+    const T* __restrict__ b1, const T* b2, T* out, int nxcd,
+    const int32_t* __restrict__ recs) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;  // bonds inside the high part
+  constexpr int NL = Lb - 1;  // bonds inside the low part
+  constexpr int RPL = kChainSegRows / 64;  // rows per lane
+  constexpr int SPL = kChainStageRows / 64;  // staged rows per lane
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  {  // one vectorized, unrolled copy of the packed tables into LDS
+    const u4* src = reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blob64 : c.blob32);
+    u4* dst = reinterpret_cast<u4*>(smem);
+    constexpr int PER = (CHUNKS + 255) / 256;
+    u4 tmp[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CHUNKS) tmp[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CHUNKS) dst[i] = tmp[k];
+    }
+  }
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const T* s_dlo = reinterpret_cast<const T*>(smem + 16 * NLO);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(s_dlo + NLO);
+  T* stage = reinterpret_cast<T*>(smem + BLOB) + (threadIdx.x >> 6) * kChainStageRows;
+  __syncthreads();
+
+  // this XCD's contiguous share of the segments
+  const int xcd = blockIdx.x % nxcd;
+  const int blocks_x = gridDim.x / nxcd;
+  const int64_t s_begin = c.nseg * xcd / nxcd, s_end = c.nseg * (xcd + 1) / nxcd;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wstride = (int64_t)blocks_x * wpb;
+  const int lane = threadIdx.x & 63;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t vbytes = (uint32_t)(c.D * TB);
+  const rsrc_t rb1 = make_rsrc(b1, vbytes), rv = make_rsrc(v, v ? vbytes : 0),
+               rb2 = make_rsrc(b2, b2 ? vbytes : 0), rout = make_rsrc(out, vbytes);
+  int64_t si = s_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
+  if (si >= s_end) return;
+  for (; si < s_end; si += wstride) {
+    const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform((int)si) * kChainRecWords);
+    const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+    const int bs = (cur.flags >> 2) & 1023, st = (cur.flags >> 12) & 1023;
+    const int blk0 = cur.row0 - st;
+    const uint32_t so_blk = (uint32_t)blk0 * TB, so_row = (uint32_t)cur.row0 * TB;
+    // the block of b_{i+1} for the low-part hops: loads now, LDS later
+    T stg[SPL];
+#pragma unroll
+    for (int m = 0; m < SPL; ++m)
+      stg[m] = bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk);
+    // rows of this lane, clamped into the segment (a clamped lane repeats the
+    // last row and stores the same value)
+    int jj[RPL], lo[RPL];
+    u4 np[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      jj[i] = min(lane + 64 * i, cur.len - 1);
+      lo[i] = s_lo[cur.lidx + jj[i]];
+      np[i] = s_np[lo[i]];
+    }
+    // global gathers: high-part hops at uniform offsets, joining and periodic
+    // bonds, and the streamed v and b_{i+2}
+    T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
+    bool act_j[RPL], act_p[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const uint32_t off = (uint32_t)jj[i] * TB;
+#pragma unroll
+      for (int b = 0; b < NH; ++b)
+        g_hi[i][b] = bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB);
+      const int l = lo[i];
+      act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
+      act_p[i] = c.periodic && ((l & 1) != hitop);
+      const int rj = (int)((np[i][2] >> 8) & 255u);   // byte 9
+      const int rp = (int)((np[i][2] >> 16) & 255u);  // byte 10
+      g_j[i] = bload<T>(rb1, (uint32_t)(act_j[i] ? blk0 + cur.d_join + rj : cur.row0 + jj[i]) * TB, 0);
+      g_p[i] = bload<T>(rb1, (uint32_t)(act_p[i] ? blk0 + cur.d_pbc + rp : cur.row0 + jj[i]) * TB, 0);
+      vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
+      bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
+    }
+    wave_sync();  // the previous segment's LDS reads are done
+#pragma unroll
+    for (int m = 0; m < SPL; ++m) stage[min(lane + 64 * m, bs - 1)] = stg[m];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int l = lo[i];
+      const int pos = st + jj[i];
+      const T bo = stage[pos];
+      T hop = 0;
+#pragma unroll
+      for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+#pragma unroll
+      for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
+      const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+      const int n_idle = (NL - __popc(xlo)) + cur.n_idle_h;
+      hop -= (T)n_idle * bo;
+      hop += act_j[i] ? g_j[i] : T(0);
+      const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
+      const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
+      const T dg = s_dlo[l] + (T)cur.dhi + vzz * (T)n11x;
+      const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+      T o = sigma * acc + tau * bo - bt[i];
+      if (v) o += a * vv[i];
+      bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+    }
+  }
+}
+
+// Launch shape: persistent blocks per CU and the XCD-contiguous mapping can
+// be overridden through POLFED_CHAIN_BPC and POLFED_CHAIN_XCD (0 = off).
+static int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  return (s && *s) ? std::atoi(s) : dflt;
+}
+
+template <typename T, int L>
+static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
+                         const T* v, const T* b1, const T* b2, T* out) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int NLO = 1 << Lb;
+  static const int bpc = std::max(1, env_int("POLFED_CHAIN_BPC", kChainBlocksPerCU));
+  static const int xcd_map = env_int("POLFED_CHAIN_XCD", 1);
+  const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) + 4 * kChainStageRows * sizeof(T);
+  ChainSplitDev c = op->chain_split();
+  const int64_t blocks_needed = (c.nseg + 3) / 4;
+  int64_t grid = std::min<int64_t>(blocks_needed, (int64_t)op->ctx->n_cu * bpc);
+  int nxcd = 1;
+  if (xcd_map && grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  hipLaunchKernelGGL((k_chain_split<T, L>), dim3((unsigned)grid), dim3(256), shm, s, c,
+                     sigma, tau, a, v, b1, b2, out, nxcd, c.rec);
+  HIPC(hipGetLastError());
+}
+
+template <typename T>
+bool chain_split_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
+                      const T* v, const T* b1, const T* b2, T* out) {
+  if (op->split_nseg <= 0) return false;
+  switch (op->L) {
+#define POLFED_CASE(LL) \
+  case LL: launch_split<T, LL>(s, op, sigma, tau, a, v, b1, b2, out); return true;
+    POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
+    POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
+    POLFED_CASE(14) POLFED_CASE(15) POLFED_CASE(16) POLFED_CASE(17) POLFED_CASE(18)
+    POLFED_CASE(19) POLFED_CASE(20) POLFED_CASE(21) POLFED_CASE(22) POLFED_CASE(23)
+    POLFED_CASE(24) POLFED_CASE(25) POLFED_CASE(26) POLFED_CASE(27) POLFED_CASE(28)
+#undef POLFED_CASE
+    default: return false;
+  }
+}
+
+template bool chain_split_step<double>(hipStream_t, const polfed_op*, double, double, double,
+                                       const double*, const double*, const double*, double*);
+template bool chain_split_step<float>(hipStream_t, const polfed_op*, float, float, float,
+                                      const float*, const float*, const float*, float*);
+
+}  // namespace polfed
+
+polfed::ChainSplitDev polfed_op::chain_split() const {
+  polfed::ChainSplitDev c{};
+  c.D = D;
+  c.N = N;
+  c.periodic = periodic;
+  c.t_in = t_in;
+  c.t_pb = t_pb;
+  c.vzz = vzz;
+  c.blob64 = d_blob64.get();
+  c.blob32 = d_blob32.get();
+  c.rec = d_rec.as<int32_t>();
+  c.nseg = split_nseg;
+  return c;
+}

@@ -80,6 +80,39 @@ struct ChainDev {
   const int32_t* lo_rank;  // rank of a low part among equal-popcount ones
 };
 
+// Split layout of the chain kernel (state = hi << Lb | lo, rows of one hi
+// contiguous): one wavefront per segment of a block, described by a
+// 128-byte record of wave-uniform data:
+//   [0] first row  [1] rows  [2] index of its first low part  [3] flags
+//   (bit 0: lowest high bit, bit 1: top high bit, bits 2-11: rows of the
+//   block, bits 12-21: position of the segment in its block)  [4] high bonds
+//   that cannot hop  [5] row offset of the joining bond  [6] of the periodic
+//   bond  [8..9] high-part diagonal (double)  [10..31] row offsets of the
+//   hops inside the high part (0 where no hop).
+constexpr int kChainLoBits = 10;      // Lb = min(10, L / 2); blocks <= 252 rows
+constexpr int kChainSegRows = 128;    // rows per wavefront segment
+constexpr int kChainStageRows = 256;  // LDS rows staged per wavefront
+constexpr int kChainBlocksPerCU = 6;  // persistent blocks per compute unit
+constexpr int kChainRecWords = 32;
+constexpr int kChainMaxHighBonds = kChainRecWords - 10;
+// bytes of the packed LDS image of the low-part tables, per low part lo:
+// 16 bytes of block positions (the Lb-1 low-bond neighbours, own position
+// where a bond cannot hop; then lo_rank of lo with its top bit flipped and of
+// lo with bit 0 flipped), the low-part diagonal (T) and the low-part list
+// (uint16).  16-byte multiple.
+constexpr int chain_blob_bytes(int nlo, int tbytes) {
+  return ((nlo * (16 + tbytes + 2)) + 15) / 16 * 16;
+}
+struct ChainSplitDev {
+  int64_t D;
+  int N, periodic;
+  double t_in, t_pb, vzz;
+  const void* blob64;  // packed LDS image, FP64 diagonal
+  const void* blob32;  // same with FP32 diagonal
+  const int32_t* rec;
+  int64_t nseg;
+};
+
 constexpr int kQsunMaxL = 31;
 // Quantum sun in the full space: index = dot_state << L | outer_bits.
 struct QsunDev {
@@ -122,6 +155,7 @@ struct polfed_ctx {
   polfed::DevBuf scratch_red;  // reduction partials
   polfed::DevBuf scratch_scalar;
   polfed::DevBuf binom;  // binomial table for the basis calls
+  polfed::DevBuf ws[8];  // scratch of the single-step entry points
   struct Server* server = nullptr;
 };
 
@@ -142,6 +176,11 @@ struct polfed_op {
   // pattern key: operators with equal keys share the off-diagonal pattern
   std::string pattern_key;
   polfed::DevBuf d_ftab, d_ftab32, d_binom, d_hi_off, d_lo_rank, d_hdot;
+  // split layout of the chain kernel
+  int split_Lb = 0;
+  int64_t split_nseg = 0;
+  polfed::DevBuf d_blob64, d_blob32, d_rec;
+  polfed::ChainSplitDev chain_split() const;
   // CSR copy
   bool has_csr = false;
   int64_t nnz = -1;
@@ -178,6 +217,11 @@ void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
 // r * B + c); per-column scalars and diagonal tables.
 void op_moments(hipStream_t s, const polfed_op* op, double* d_two, double* partial,
                 int64_t npart);
+// Split-layout chain step; false when no instantiation covers op->L.
+template <typename T>
+bool chain_split_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
+                      const T* v, const T* b1, const T* b2, T* out);
+void build_chain_split(polfed_op* op);
 void materialize_csr(polfed_ctx* ctx, polfed_op* op);
 
 // ---------------------------------------------------------------- blas ----
@@ -246,5 +290,11 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
                           double* const* resid, int* n_found,
                           polfed_report* rep);
 double now_seconds();
+void* ctx_scratch(polfed_ctx* ctx, int slot, size_t bytes);
+void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                  const double* a, int K, double* V, int k, double* alpha,
+                  double* beta, int precision);
+void profile_step(polfed_ctx* ctx, const polfed_op* op, int precision, int iters,
+                  double* avg_ms, double* min_ms);
 
 }  // namespace polfed

@@ -336,6 +336,7 @@ void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
   const int64_t tiles = (op->D + 256 * ROWS - 1) / (256 * ROWS);
   const unsigned grid = (unsigned)std::min<int64_t>(tiles, grid_cap(op));
   if (op->model == Model::Chain) {
+    if (chain_split_step<T>(s, op, sigma, tau, a, v, b1, b2, out)) return;
     hipLaunchKernelGGL((k_chain_step<T, ROWS>), dim3(grid), dim3(256), 0, s,
                        op->chain(), sigma, tau, a, v, b1, b2, out, vec_ok);
   } else if (op->model == Model::Qsun) {
@@ -704,6 +705,7 @@ static polfed_op* make_chain(polfed_ctx* ctx, int L, int N, int periodic,
   upload(op->d_hi_off, hi.data(), hi.size(), s);
   upload(op->d_lo_rank, lo.data(), lo.size(), s);
   HIPC(hipStreamSynchronize(s));
+  if (L >= 4 && L <= 28) build_chain_split(op.get());
   return op.release();
 }
 

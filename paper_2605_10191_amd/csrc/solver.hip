@@ -132,16 +132,22 @@ struct Ws {
 // w <- w - V V^T w twice over the first k1 basis vectors; the first column
 // projection of each pass adds up alpha[k]; then beta_next = ||w|| and
 // v_next = w / beta_next.
+void cgs2_raw(hipStream_t s, int64_t D, int k1, const double* V, double* w,
+              double* c, double* partial, int64_t nseg, int* flag, double* alpha_k,
+              double* beta_next, double* v_next) {
+  for (int pass = 0; pass < 2; ++pass) {
+    dev_gemv_t(s, D, k1, V, D, w, partial, nseg, c, alpha_k, pass);
+    dev_gemv_n_sub(s, D, k1, V, D, c, w);
+  }
+  dev_dot(s, D, w, w, partial, 1024, beta_next, 1);
+  dev_scale_into(s, D, w, beta_next, v_next, flag);
+}
+
 void cgs2_normalize(hipStream_t s, int64_t D, int k1, const Basis& B, Ws& ws,
                     double* alpha_k, double* beta_next, double* v_next) {
-  double* w = ws.w.as<double>();
-  for (int pass = 0; pass < 2; ++pass) {
-    dev_gemv_t(s, D, k1, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
-               ws.c.as<double>(), alpha_k, pass);
-    dev_gemv_n_sub(s, D, k1, B.V.as<double>(), D, ws.c.as<double>(), w);
-  }
-  dev_dot(s, D, w, w, ws.partial.as<double>(), 1024, beta_next, 1);
-  dev_scale_into(s, D, w, beta_next, v_next, ws.flag.as<int>());
+  cgs2_raw(s, D, k1, B.V.as<double>(), ws.w.as<double>(), ws.c.as<double>(),
+           ws.partial.as<double>(), ws.nseg, ws.flag.as<int>(), alpha_k, beta_next,
+           v_next);
 }
 
 void normalize_into(hipStream_t s, int64_t D, const double* x, Ws& ws, double* out) {
@@ -534,6 +540,88 @@ polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p
   R.t_total = now_seconds() - t_start;
   if (rep) *rep = R;
   return status;
+}
+
+// ---------------------------------------------- single Lanczos step (API) ----
+
+void* ctx_scratch(polfed_ctx* ctx, int slot, size_t bytes) {
+  DevBuf& b = ctx->ws[slot];
+  if (b.bytes() < bytes) b.alloc(bytes);
+  return b.get();
+}
+
+void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                  const double* a, int K, double* V, int k, double* alpha,
+                  double* beta, int precision) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  const size_t nd = (size_t)std::max<int64_t>(D, 1);
+  double* w = static_cast<double*>(ctx_scratch(ctx, 0, nd * sizeof(double)));
+  const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(256, (D + 8191) / 8192));
+  double* c = static_cast<double*>(ctx_scratch(ctx, 1, (size_t)(k + 2) * sizeof(double)));
+  double* part = static_cast<double*>(
+      ctx_scratch(ctx, 2, ((size_t)nseg * (k + 2) + 8192) * sizeof(double)));
+  int* flag = static_cast<int*>(ctx_scratch(ctx, 3, 64));
+  double* vk = V + (size_t)k * D;
+  if (precision == POLFED_FP32) {
+    float* v32 = static_cast<float*>(ctx_scratch(ctx, 4, nd * sizeof(float)));
+    float* w32 = static_cast<float*>(ctx_scratch(ctx, 5, nd * sizeof(float)));
+    float* bA = static_cast<float*>(ctx_scratch(ctx, 6, nd * sizeof(float)));
+    float* bB = static_cast<float*>(ctx_scratch(ctx, 7, nd * sizeof(float)));
+    dev_copy_d2f(s, D, vk, v32);
+    filter_apply<float>(ctx, op, E_c, dE, a, K, v32, w32, bA, bB);
+    dev_copy_f2d(s, D, w32, w);
+  } else {
+    double* bA = static_cast<double*>(ctx_scratch(ctx, 6, nd * sizeof(double)));
+    double* bB = static_cast<double*>(ctx_scratch(ctx, 7, nd * sizeof(double)));
+    filter_apply<double>(ctx, op, E_c, dE, a, K, vk, w, bA, bB);
+  }
+  cgs2_raw(s, D, k + 1, V, w, c, part, nseg, flag, alpha, beta, V + (size_t)(k + 1) * D);
+}
+
+// Times `iters` back-to-back launches of the fused step kernel with a pair
+// of HIP events around each launch on the context stream.
+void profile_step(polfed_ctx* ctx, const polfed_op* op, int precision, int iters,
+                  double* avg_ms, double* min_ms) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  const size_t nd = (size_t)std::max<int64_t>(D, 1);
+  DevBuf v(nd * 8), b1(nd * 8), b2(nd * 8);
+  dev_random(s, D, 11, v.as<double>());
+  dev_random(s, D, 12, b1.as<double>());
+  dev_random(s, D, 13, b2.as<double>());
+  if (precision == POLFED_FP32) {
+    DevBuf t(nd * 4);
+    for (DevBuf* b : {&v, &b1, &b2}) {
+      dev_copy_d2f(s, D, b->as<double>(), t.as<float>());
+      HIPC(hipMemcpyAsync(b->get(), t.get(), nd * 4, hipMemcpyDeviceToDevice, s));
+    }
+    HIPC(hipStreamSynchronize(s));
+  }
+  std::vector<hipEvent_t> ev(2 * (size_t)iters);
+  for (auto& e : ev) HIPC(hipEventCreate(&e));
+  const double sigma = 0.1, tau = -0.01, a = 1e-3;
+  for (int i = 0; i < iters; ++i) {
+    HIPC(hipEventRecord(ev[2 * i], s));
+    if (precision == POLFED_FP32)
+      op_step<float>(s, op, (float)sigma, (float)tau, (float)a, v.as<float>(), b1.as<float>(),
+                     b2.as<float>(), b2.as<float>());
+    else
+      op_step<double>(s, op, sigma, tau, a, v.as<double>(), b1.as<double>(), b2.as<double>(),
+                      b2.as<double>());
+    HIPC(hipEventRecord(ev[2 * i + 1], s));
+  }
+  HIPC(hipStreamSynchronize(s));
+  double sum = 0, mn = 1e300;
+  for (int i = 0; i < iters; ++i) {
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+    sum += ms;
+    mn = std::min(mn, (double)ms);
+  }
+  for (auto& e : ev) HIPC(hipEventDestroy(e));
+  *avg_ms = iters ? sum / iters : 0;
+  *min_ms = iters ? mn : 0;
 }
 
 }  // namespace polfed
