@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_step_xxz_L24_fp64.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_10191_amd", "csrc", "ops.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_10191_amd", "csrc", "chain.hip")
 
 
 def log(*a):
@@ -198,7 +198,7 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(),
-                "kernel": "k_chain_step<double,4>",
+                "kernel": f"k_chain_split<double, {args.L}>",
                 "kernel_ms_avg": round(avg_ms, 5), "kernel_ms_min": round(min_ms, 5),
                 "bytes_per_launch": step_bytes}
     log(f"step kernel {avg_ms * 1e3:.2f} us avg -> {achieved:.0f} GB/s")

@@ -211,6 +211,31 @@ polfed_status polfed_clenshaw_step(polfed_ctx* ctx, const polfed_op* op,
                                    const void* v, const void* b1, void* b2,
                                    int precision, int final);
 
+/* Multi-column filter for B chain operators that share the off-diagonal
+ * pattern (same model, L, N, boundary and couplings; on-site fields may
+ * differ): column c of the device blocks v and w (D x B, column-major,
+ * column stride D, in the chosen precision) gets
+ *     w_c = P_c(H~_c) v_c,   H~_c = (H_c - E_c[c]) / dE[c],
+ * with the Chebyshev coefficients a[c][0..K[c]] (host arrays) evaluated by
+ * the Clenshaw recurrence of eq. clenshaw_chebyshev_prod as one recurrence
+ * of max K[c] steps over all columns.  Synchronizes.  Operators of another
+ * pattern or outside L = 4..28 give POLFED_ERR_INVALID. */
+polfed_status polfed_filter_apply_batch(polfed_ctx* ctx, int B,
+                                        const polfed_op* const* ops,
+                                        const double* E_c, const double* dE,
+                                        const double* const* a, const int* K,
+                                        const void* v, void* w, int precision);
+/* One multi-column Clenshaw step, in place on the block b2 (D x B):
+ *   b2_c <- a_i[c] v_c + 2 H~_c b1_c - b2_c   (final == 0)
+ *   b2_c <- a_i[c] v_c +   H~_c b1_c - b2_c   (final != 0)
+ * a_i: host [B].  Synchronizes. */
+polfed_status polfed_clenshaw_step_batch(polfed_ctx* ctx, int B,
+                                         const polfed_op* const* ops,
+                                         const double* E_c, const double* dE,
+                                         const double* a_i, const void* v,
+                                         const void* b1, void* b2, int precision,
+                                         int final);
+
 /* --------------------------------------------------------------- Lanczos */
 
 /* Spectral extremes by plain Lanczos on H with full reorthogonalization

@@ -103,6 +103,10 @@ SIGNATURES = {
     "polfed_filter_value": [_D, _I, _DP, _I64, _DP],
     "polfed_filter_apply": [_P, _P, _D, _D, _DP, _I, _P, _P, _I],
     "polfed_clenshaw_step": [_P, _P, _D, _D, _D, _P, _P, _P, _I, _I],
+    "polfed_filter_apply_batch": [_P, _I, ctypes.POINTER(_P), _DP, _DP,
+                                  ctypes.POINTER(_DP), _I32P, _P, _P, _I],
+    "polfed_clenshaw_step_batch": [_P, _I, ctypes.POINTER(_P), _DP, _DP, _DP,
+                                   _P, _P, _P, _I, _I],
     "polfed_bounds": [_P, _P, _P, _D, _I, _DP, _DP],
     "polfed_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _P, _P, _I],
     "polfed_profile_step": [_P, _P, _I, _I, _DP, _DP],
@@ -390,6 +394,46 @@ def clenshaw_step(op: Operator, E_c, dE, a_i, v, b1, b2, precision=FP64,
     return b2
 
 
+def _op_array(ops):
+    ctx = ops[0].ctx
+    for o in ops:
+        if o.ctx is not ctx:
+            raise ValueError("operators belong to different contexts")
+    return (_P * len(ops))(*[o.handle for o in ops]), ctx
+
+
+def filter_apply_batch(ops, E_c, dE, a, v, precision=FP64, w=None):
+    """Column c of the (B, D) device block w gets P_c(H~_c) v_c for chain
+    operators sharing one off-diagonal pattern; a is a list of B coefficient
+    arrays (orders may differ)."""
+    import torch
+    B = len(ops)
+    arr, ctx = _op_array(ops)
+    Ec = np.ascontiguousarray(E_c, dtype=np.float64)
+    dE_ = np.ascontiguousarray(dE, dtype=np.float64)
+    coef = [np.ascontiguousarray(x, dtype=np.float64) for x in a]
+    K = np.array([len(x) - 1 for x in coef], dtype=np.int32)
+    aptr = (_DP * B)(*[_dptr(x) for x in coef])
+    if w is None:
+        w = torch.empty_like(v)
+    _check(_lib.polfed_filter_apply_batch(ctx.handle, B, arr, _dptr(Ec), _dptr(dE_),
+                                          aptr, K.ctypes.data_as(_I32P), _ptr(v),
+                                          _ptr(w), precision))
+    return w
+
+
+def clenshaw_step_batch(ops, E_c, dE, a_i, v, b1, b2, precision=FP64, final=False):
+    B = len(ops)
+    arr, ctx = _op_array(ops)
+    Ec = np.ascontiguousarray(E_c, dtype=np.float64)
+    dE_ = np.ascontiguousarray(dE, dtype=np.float64)
+    ai = np.ascontiguousarray(a_i, dtype=np.float64)
+    _check(_lib.polfed_clenshaw_step_batch(ctx.handle, B, arr, _dptr(Ec), _dptr(dE_),
+                                           _dptr(ai), _ptr(v), _ptr(b1), _ptr(b2),
+                                           precision, int(final)))
+    return b2
+
+
 def bounds(op: Operator, x0, tol=1e-10, max_iter=300):
     lo, hi = ctypes.c_double(), ctypes.c_double()
     _check(_lib.polfed_bounds(op.ctx.handle, op.handle, _ptr(x0), tol,
@@ -447,3 +491,27 @@ def solve(op: Operator, x0, n_ev, target, target_kind="normalized",
     n = nf.value
     return (evals[:n], evecs.view(n_ev, op.D)[:n].T, resid[:n], rep.as_dict(),
             STATUS[code])
+
+
+def solve_batch(ops, x0s, n_ev, target, target_kind="normalized", precision=FP64,
+                allow_partial=False, **kw):
+    """Batched solve of chain realizations sharing the off-diagonal pattern.
+    Returns a list of (evals, evecs, resid, report dict) and the status."""
+    B = len(ops)
+    arr, ctx = _op_array(ops)
+    p = make_params(n_ev, target, target_kind, precision, **kw)
+    evals = [ctx.empty(n_ev) for _ in ops]
+    evecs = [ctx.empty(n_ev * o.D) for o in ops]
+    resid = [ctx.empty(n_ev) for _ in ops]
+    nf = (_I * B)()
+    reps = (Report * B)()
+    ptrs = lambda ts: (_P * B)(*[_ptr(t) for t in ts])
+    code = _lib.polfed_solve_batch(ctx.handle, B, arr, ctypes.byref(p), ptrs(x0s),
+                                   ptrs(evals), ptrs(evecs), ptrs(resid), nf, reps)
+    _check(code, ok=(0, 1) if allow_partial else (0,))
+    out = []
+    for i, o in enumerate(ops):
+        n = nf[i]
+        out.append((evals[i][:n], evecs[i].view(n_ev, o.D)[:n].T, resid[i][:n],
+                    reps[i].as_dict()))
+    return out, STATUS[code]

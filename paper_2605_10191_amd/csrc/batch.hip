@@ -1,0 +1,195 @@
+// Multi-column filter P(H~_c) v_c for a batch of chain realizations that
+// share the off-diagonal pattern, and the batched solve built on it: every
+// realization runs its own filtered Lanczos iteration (its own bounds, plan,
+// Krylov basis and checks), while the filter of all unfinished
+// realizations is one multi-column Clenshaw recurrence.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "internal.hpp"
+#include "solve_run.hpp"
+
+namespace polfed {
+
+template <typename T>
+__global__ void k_scale_cols(int64_t D, int nb, const T* __restrict__ a, const T* v, T* y) {
+  const int64_t n = D * nb;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a[i / D] * v[i];
+}
+
+template <typename T>
+static void scale_cols(hipStream_t s, int64_t D, int nb, const T* a, const T* v, T* y) {
+  const int64_t n = D * nb;
+  if (!n) return;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256));
+  hipLaunchKernelGGL((k_scale_cols<T>), dim3(g), dim3(256), 0, s, D, nb, a, v, y);
+  HIPC(hipGetLastError());
+}
+
+void BatchCoef::set(hipStream_t s, int nb_, const double* const* a, const int* K) {
+  nb = nb_;
+  Kmax = 0;
+  for (int c = 0; c < nb; ++c) {
+    REQUIRE(K[c] >= 0, "batch filter: need K >= 0");
+    Kmax = std::max(Kmax, K[c]);
+  }
+  std::vector<double> A((size_t)(Kmax + 1) * nb, 0.0);
+  for (int c = 0; c < nb; ++c)
+    for (int i = 0; i <= K[c]; ++i) A[(size_t)i * nb + c] = a[c][i];
+  std::vector<float> A32(A.begin(), A.end());
+  upload(d64, A.data(), A.size(), s);
+  upload(d32, A32.data(), A32.size(), s);
+  HIPC(hipStreamSynchronize(s));
+}
+
+// Clenshaw recurrence of eq. clenshaw_chebyshev_prod for all columns at once.
+// A column whose order K_c is below the batch maximum has zero coefficients
+// above K_c, so its b_i stay zero until i = K_c.
+template <typename T>
+void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& co,
+                        const T* v, T* w, T* bufA, T* bufB) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = bt.ops[0]->D;
+  const int nb = bt.nb;
+  REQUIRE(co.nb == nb, "batch filter: coefficient table of another batch");
+  const T* A = (const T*)(sizeof(T) == 8 ? co.d64.get() : co.d32.get());
+  const int K = co.Kmax;
+  if (K == 0) {
+    scale_cols<T>(s, D, nb, A, v, w);
+    return;
+  }
+  scale_cols<T>(s, D, nb, A + (size_t)K * nb, v, bufA);
+  const T* cur = bufA;
+  T* prev = nullptr;
+  for (int i = K - 1; i >= 1; --i) {
+    T* out = prev ? prev : bufB;
+    chain_batch_step<T>(s, bt, D, false, A + (size_t)i * nb, v, cur, prev, out);
+    prev = const_cast<T*>(cur);
+    cur = out;
+  }
+  chain_batch_step<T>(s, bt, D, true, A, v, cur, prev, w);
+}
+
+template void filter_apply_batch<double>(polfed_ctx*, const ChainBatch&, const BatchCoef&,
+                                         const double*, double*, double*, double*);
+template void filter_apply_batch<float>(polfed_ctx*, const ChainBatch&, const BatchCoef&,
+                                        const float*, float*, float*, float*);
+
+void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
+  ctx = c;
+  members = runs;
+  const int nb = (int)runs.size();
+  std::vector<const polfed_op*> ops(nb);
+  std::vector<double> Ec(nb), dE(nb);
+  std::vector<const double*> a(nb);
+  std::vector<int> K(nb);
+  fp32 = runs[0]->fp32;
+  for (int i = 0; i < nb; ++i) {
+    REQUIRE(runs[i]->fp32 == fp32, "batch: members must share the precision");
+    ops[i] = runs[i]->op;
+    Ec[i] = runs[i]->pl.E_c;
+    dE[i] = runs[i]->pl.dE;
+    a[i] = runs[i]->a.data();
+    K[i] = runs[i]->pl.K;
+  }
+  bt.init(c, ops.data(), nb);
+  bt.set_scale(Ec.data(), dE.data());
+  co.set(c->stream, nb, a.data(), K.data());
+  const int64_t D = ops[0]->D;
+  const size_t tb = fp32 ? sizeof(float) : sizeof(double);
+  const size_t need = (size_t)D * nb * tb;
+  if (vb.bytes() < need) {
+    vb.alloc(need);
+    wb.alloc(need);
+    bA.alloc(need);
+    bB.alloc(need);
+  }
+}
+
+// One filter application for every member: gather v_k of each member into
+// the block, run the recurrence, scatter P(H~) v_k into each member's w.
+double BatchFilter::run() {
+  hipStream_t s = ctx->stream;
+  const int nb = (int)members.size();
+  const int64_t D = bt.ops[0]->D;
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  HIPC(hipEventRecord(e0, s));
+  for (int i = 0; i < nb; ++i) {
+    if (fp32)
+      dev_copy_d2f(s, D, members[i]->vec(), vb.as<float>() + (size_t)i * D);
+    else
+      HIPC(hipMemcpyAsync(vb.as<double>() + (size_t)i * D, members[i]->vec(),
+                          (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (fp32)
+    filter_apply_batch<float>(ctx, bt, co, vb.as<float>(), wb.as<float>(), bA.as<float>(),
+                              bB.as<float>());
+  else
+    filter_apply_batch<double>(ctx, bt, co, vb.as<double>(), wb.as<double>(),
+                               bA.as<double>(), bB.as<double>());
+  for (int i = 0; i < nb; ++i) {
+    if (fp32)
+      dev_copy_f2d(s, D, wb.as<float>() + (size_t)i * D, members[i]->wbuf());
+    else
+      HIPC(hipMemcpyAsync(members[i]->wbuf(), wb.as<double>() + (size_t)i * D,
+                          (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  HIPC(hipEventRecord(e1, s));
+  HIPC(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPC(hipEventElapsedTime(&ms, e0, e1));
+  HIPC(hipEventDestroy(e0));
+  HIPC(hipEventDestroy(e1));
+  const double t = 1e-3 * ms;
+  for (auto* r : members) {
+    r->R.t_filter += t / nb;
+    r->R.filter_steps += r->pl.K;
+  }
+  return t;
+}
+
+polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
+                          const polfed_params& p, const double* const* x0,
+                          double* const* evals, double* const* evecs, double* const* resid,
+                          int* n_found, polfed_report* rep) {
+  REQUIRE(B >= 1, "solve_batch: need B >= 1");
+  REQUIRE(ops && x0 && evals && evecs && resid && n_found, "solve_batch: null array");
+  for (int i = 0; i < B; ++i) {
+    REQUIRE(ops[i] && ops[i]->ctx == ctx, "solve_batch: operator missing or of another context");
+    REQUIRE(ops[i]->model == Model::Chain && !ops[i]->pattern_key.empty() &&
+                ops[i]->pattern_key == ops[0]->pattern_key,
+            "solve_batch: operators must be chains sharing the off-diagonal pattern");
+  }
+  std::vector<std::unique_ptr<SolveRun>> runs;
+  for (int i = 0; i < B; ++i) {
+    runs.emplace_back(new SolveRun());
+    runs.back()->setup(ctx, ops[i], p, x0[i], evals[i], evecs[i], resid[i], &n_found[i]);
+  }
+  BatchFilter bf;
+  std::vector<SolveRun*> active;
+  for (;;) {
+    std::vector<SolveRun*> now;
+    for (auto& r : runs)
+      if (!r->done) now.push_back(r.get());
+    if (now.empty()) break;
+    if (now != active) {
+      bf.form(ctx, now);
+      active = now;
+    }
+    bf.run();
+    for (auto* r : active) r->advance();
+  }
+  polfed_status st = POLFED_OK;
+  for (int i = 0; i < B; ++i) {
+    if (rep) rep[i] = runs[i]->R;
+    if (runs[i]->status != POLFED_OK) st = POLFED_NOT_CONVERGED;
+  }
+  return st;
+}
+
+}  // namespace polfed

@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "solve_run.hpp"
 
 namespace polfed {
 
@@ -470,6 +471,88 @@ polfed_status polfed_clenshaw_step(polfed_ctx* ctx, const polfed_op* op, double 
       op_step<float>(ctx->stream, op, (float)sigma, (float)tau, (float)a_i,
                      static_cast<const float*>(v), static_cast<const float*>(b1),
                      static_cast<const float*>(b2), static_cast<float*>(b2));
+    return POLFED_OK;
+  });
+}
+
+// ----------------------------------------------------- multi-column filter
+
+static void check_batch_args(polfed_ctx* ctx, int B, const polfed_op* const* ops,
+                             const double* E_c, const double* dE, int precision) {
+  CTX_OK(ctx);
+  REQUIRE(B >= 1 && ops && E_c && dE, "batch: need B >= 1 and arrays ops, E_c, dE");
+  REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
+  for (int i = 0; i < B; ++i) {
+    REQUIRE(ops[i] && ops[i]->ctx == ctx, "batch: operator missing or from another context");
+    REQUIRE(std::isfinite(E_c[i]) && std::isfinite(dE[i]) && dE[i] > 0,
+            "batch: E_c must be finite and dE finite and positive");
+  }
+}
+
+polfed_status polfed_filter_apply_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
+                                        const double* E_c, const double* dE,
+                                        const double* const* a, const int* K, const void* v,
+                                        void* w, int precision) {
+  return guarded([&]() -> polfed_status {
+    check_batch_args(ctx, B, ops, E_c, dE, precision);
+    REQUIRE(a && K, "batch: need coefficient arrays a and orders K");
+    for (int i = 0; i < B; ++i) REQUIRE(a[i] && K[i] >= 0, "batch: need K >= 0 and a[K+1]");
+    REQUIRE(v && w && v != w, "batch: null or overlapping vector blocks");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ChainBatch bt;
+    bt.init(ctx, ops, B);
+    bt.set_scale(E_c, dE);
+    BatchCoef co;
+    co.set(ctx->stream, B, a, K);
+    const size_t n = (size_t)ops[0]->D * B;
+    if (precision == POLFED_FP64) {
+      DevBuf A(n * sizeof(double)), Bb(n * sizeof(double));
+      filter_apply_batch<double>(ctx, bt, co, static_cast<const double*>(v),
+                                 static_cast<double*>(w), A.as<double>(), Bb.as<double>());
+      HIPC(hipStreamSynchronize(ctx->stream));
+    } else {
+      DevBuf A(n * sizeof(float)), Bb(n * sizeof(float));
+      filter_apply_batch<float>(ctx, bt, co, static_cast<const float*>(v),
+                                static_cast<float*>(w), A.as<float>(), Bb.as<float>());
+      HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_clenshaw_step_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
+                                         const double* E_c, const double* dE,
+                                         const double* a_i, const void* v, const void* b1,
+                                         void* b2, int precision, int final) {
+  return guarded([&]() -> polfed_status {
+    check_batch_args(ctx, B, ops, E_c, dE, precision);
+    REQUIRE(a_i, "batch: need coefficients a_i[B]");
+    for (int i = 0; i < B; ++i) REQUIRE(std::isfinite(a_i[i]), "batch: non-finite a_i");
+    REQUIRE(v && b1 && b2, "batch: null vector block");
+    REQUIRE(b1 != b2 && b1 != v, "batch: b1 must not overlap v or b2");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ChainBatch bt;
+    bt.init(ctx, ops, B);
+    bt.set_scale(E_c, dE);
+    const int64_t D = ops[0]->D;
+    if (precision == POLFED_FP64) {
+      DevBuf ad;
+      upload(ad, a_i, (size_t)B, ctx->stream);
+      chain_batch_step<double>(ctx->stream, bt, D, final != 0, ad.as<double>(),
+                               static_cast<const double*>(v), static_cast<const double*>(b1),
+                               static_cast<const double*>(b2), static_cast<double*>(b2));
+      HIPC(hipStreamSynchronize(ctx->stream));
+    } else {
+      std::vector<float> af(a_i, a_i + B);
+      DevBuf ad;
+      upload(ad, af.data(), af.size(), ctx->stream);
+      chain_batch_step<float>(ctx->stream, bt, D, final != 0, ad.as<float>(),
+                              static_cast<const float*>(v), static_cast<const float*>(b1),
+                              static_cast<const float*>(b2), static_cast<float*>(b2));
+      HIPC(hipStreamSynchronize(ctx->stream));
+    }
     return POLFED_OK;
   });
 }

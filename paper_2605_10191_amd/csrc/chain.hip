@@ -19,8 +19,7 @@
 //     block at r + d + lo_rank[lo'] - lo_rank[lo] (d uniform);
 //   - the diagonal is DLO[lo] (LDS) + a uniform high part + two cross terms.
 // All wave-uniform data of a segment (offsets, flags, diagonal part) is
-// precomputed into a 128-byte record read with scalar loads, prefetched one
-// segment ahead.  Every gather is issued unconditionally (a bond that cannot
+// precomputed into a 128-byte record read with scalar loads.  Every gather is issued unconditionally (a bond that cannot
 // hop reads the row's own entry, which is subtracted again), so the gathers
 // of a lane's rows are in flight together.
 //
@@ -32,6 +31,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "chain_dev.hpp"
 #include "internal.hpp"
 
 namespace polfed {
@@ -79,6 +79,7 @@ void build_chain_split(polfed_op* op) {
   hi_off[nhi] = (int32_t)acc;
   // one record per segment
   std::vector<int32_t> rec;
+  op->split_dseg.clear();
   for (int64_t hi = 0; hi < nhi; ++hi) {
     const int need = N - __builtin_popcountll(hi);
     if (need < 0 || need > Lb) continue;
@@ -98,6 +99,8 @@ void build_chain_split(polfed_op* op) {
     w[5] = hi_off[hi ^ 1] - hoff;
     w[6] = hi_off[hi ^ (1LL << (Lh - 1))] - hoff;
     std::memcpy(&w[8], &dhi, sizeof(double));
+    const int nseg_hi = (bs + kChainSegRows - 1) / kChainSegRows;
+    op->split_dseg.insert(op->split_dseg.end(), nseg_hi, dhi);
     for (int st = 0; st < bs; st += kChainSegRows) {
       w[0] = hoff + st;
       w[1] = std::min(kChainSegRows, bs - st);
@@ -106,6 +109,14 @@ void build_chain_split(polfed_op* op) {
       rec.insert(rec.end(), w, w + kChainRecWords);
     }
   }
+  // field sums over low bits 0-4 and 5-9 (per-column diagonals of a batch)
+  op->split_fab.assign(64, 0.0);
+  for (int e = 0; e < 32; ++e)
+    for (int k = 0; k < 5; ++k)
+      if ((e >> k) & 1) {
+        if (k < Lb) op->split_fab[e] += op->site_f[k];
+        if (5 + k < Lb) op->split_fab[32 + e] += op->site_f[5 + k];
+      }
   hipStream_t s = op->ctx->stream;
   op->split_Lb = Lb;
   op->split_nseg = (int64_t)(rec.size() / kChainRecWords);
@@ -130,67 +141,6 @@ void build_chain_split(polfed_op* op) {
   }
   upload(op->d_rec, rec.data(), rec.size(), s);
   HIPC(hipStreamSynchronize(s));
-}
-
-__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Orders the LDS accesses of a wavefront around a staging step.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wave-uniform data of one segment (see the record layout).
-template <int NH>
-struct SegRec {
-  int row0, len, lidx, flags, n_idle_h, d_join, d_pbc;
-  double dhi;
-  int dh[NH > 0 ? NH : 1];
-};
-
-template <int NH>
-__device__ __forceinline__ SegRec<NH> load_rec(const int32_t* rec) {
-  SegRec<NH> r;
-  r.row0 = uniform(rec[0]);
-  r.len = uniform(rec[1]);
-  r.lidx = uniform(rec[2]);
-  r.flags = uniform(rec[3]);
-  r.n_idle_h = uniform(rec[4]);
-  r.d_join = uniform(rec[5]);
-  r.d_pbc = uniform(rec[6]);
-  int dw[2] = {uniform(rec[8]), uniform(rec[9])};
-  __builtin_memcpy(&r.dhi, dw, sizeof(double));
-#pragma unroll
-  for (int b = 0; b < NH; ++b) r.dh[b] = uniform(rec[10 + b]);
-  return r;
-}
-
-// Buffer accesses: a 128-bit resource for each vector, a per-lane 32-bit
-// byte offset (VGPR) and a wave-uniform byte offset (SGPR), so gathers at
-// uniform row offsets need no per-lane address arithmetic.  Accesses beyond
-// the resource's size return 0 / are dropped by the hardware.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-constexpr int kAuxNT = 2;  // non-temporal cache policy
-
-__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
-                                           0x00020000);
-}
-template <typename T, int AUX = 0>
-__device__ __forceinline__ T bload(rsrc_t r, uint32_t vo, uint32_t so) {
-  if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, AUX));
-  else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, AUX));
-}
-template <int AUX, typename T>
-__device__ __forceinline__ void bstore(T x, rsrc_t r, uint32_t vo, uint32_t so) {
-  using u2 = __attribute__((ext_vector_type(2))) unsigned int;
-  if constexpr (sizeof(T) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, vo, so, AUX);
-  else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, vo, so, AUX);
 }
 
 template <typename T, int L>

@@ -1,0 +1,269 @@
+// Multi-column fused Clenshaw step for a batch of chain operators that share
+// the off-diagonal pattern (same L, N, boundary and couplings) and differ in
+// their on-site fields.  Column c of every vector block belongs to operator
+// c; the step computes, for each column,
+//     out_c = a_c v_c + h sigma_c (H_c b1_c) + h tau_c b1_c - b2_c
+// with h = 1, or 1/2 on the closing Clenshaw step.
+//
+// The row decoding of the split layout (low part, neighbour positions,
+// activity of the joining and periodic bonds, the interaction part of the
+// diagonal) is done once per segment and reused by every column.  Only the
+// field part of the diagonal is per column: the sum over the low bits comes
+// from two 32-entry LDS tables per column (bits 0-4 and 5-9) and the sum over
+// the high bits plus the constant is one wave-uniform value per segment and
+// column.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "chain_dev.hpp"
+#include "internal.hpp"
+
+namespace polfed {
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_chain_split_batch(
+    ChainSplitDev c, int nb, int col0, int ncols, int64_t ld, T half,
+    const T* __restrict__ fab, const T* __restrict__ dseg, const T* __restrict__ sc,
+    const T* __restrict__ acoef, const T* __restrict__ v, const T* __restrict__ b1,
+    const T* b2, T* out, int nxcd, const int32_t* __restrict__ recs) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;
+  constexpr int NL = Lb - 1;
+  constexpr int RPL = kChainSegRows / 64;
+  constexpr int SPL = kChainStageRows / 64;
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  {
+    const u4* src = reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blob64 : c.blob32);
+    u4* dst = reinterpret_cast<u4*>(smem);
+    constexpr int PER = (CHUNKS + 255) / 256;
+    u4 tmp[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CHUNKS) tmp[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CHUNKS) dst[i] = tmp[k];
+    }
+  }
+  T* s_fab = reinterpret_cast<T*>(smem + BLOB);
+  for (int i = threadIdx.x; i < ncols * 64; i += 256) s_fab[i] = fab[(int64_t)col0 * 64 + i];
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(smem + 16 * NLO + TB * NLO);
+  T* stage = s_fab + ncols * 64 + (threadIdx.x >> 6) * kChainStageRows;
+  __syncthreads();
+
+  const int xcd = blockIdx.x % nxcd;
+  const int blocks_x = gridDim.x / nxcd;
+  const int64_t s_begin = c.nseg * xcd / nxcd, s_end = c.nseg * (xcd + 1) / nxcd;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wstride = (int64_t)blocks_x * wpb;
+  const int lane = threadIdx.x & 63;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t vbytes = (uint32_t)(c.D * TB);
+  int64_t si = s_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
+  if (si >= s_end) return;
+  for (; si < s_end; si += wstride) {
+    const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform((int)si) * kChainRecWords);
+    const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+    const int bs = (cur.flags >> 2) & 1023, st = (cur.flags >> 12) & 1023;
+    const int blk0 = cur.row0 - st;
+    const uint32_t so_blk = (uint32_t)blk0 * TB, so_row = (uint32_t)cur.row0 * TB;
+    // per-row decoding shared by all columns
+    int jj[RPL], lo[RPL], gj[RPL], gp[RPL];
+    u4 np[RPL];
+    bool act_j[RPL], act_p[RPL];
+    T zz[RPL], nidle[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      jj[i] = min(lane + 64 * i, cur.len - 1);
+      const int l = s_lo[cur.lidx + jj[i]];
+      lo[i] = l;
+      np[i] = s_np[l];
+      act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
+      act_p[i] = c.periodic && ((l & 1) != hitop);
+      const int rj = (int)((np[i][2] >> 8) & 255u);
+      const int rp = (int)((np[i][2] >> 16) & 255u);
+      gj[i] = act_j[i] ? blk0 + cur.d_join + rj : cur.row0 + jj[i];
+      gp[i] = act_p[i] ? blk0 + cur.d_pbc + rp : cur.row0 + jj[i];
+      const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+      nidle[i] = (T)((NL - __popc(xlo)) + cur.n_idle_h);
+      const int n11x = ((l >> (Lb - 1)) & 1 & hi0) + (c.periodic ? (hitop & l & 1) : 0);
+      zz[i] = vzz * (T)(__popc(l & (l >> 1)) + n11x);
+    }
+#pragma unroll 1
+    for (int cc = 0; cc < ncols; ++cc) {
+      const int col = col0 + cc;
+      const int64_t coff = (int64_t)col * ld;
+      const T sig = sc[col] * half, ta = sc[nb + col] * half;
+      const T ac = acoef ? acoef[col] : T(0);
+      const T dsg = dseg[si * nb + col];
+      const rsrc_t rb1 = make_rsrc(b1 + coff, vbytes);
+      const rsrc_t rv = make_rsrc(v ? v + coff : nullptr, v ? vbytes : 0);
+      const rsrc_t rb2 = make_rsrc(b2 ? b2 + coff : nullptr, b2 ? vbytes : 0);
+      const rsrc_t rout = make_rsrc(out + coff, vbytes);
+      T stg[SPL];
+#pragma unroll
+      for (int m = 0; m < SPL; ++m)
+        stg[m] = bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk);
+      T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const uint32_t off = (uint32_t)jj[i] * TB;
+#pragma unroll
+        for (int b = 0; b < NH; ++b)
+          g_hi[i][b] = bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB);
+        g_j[i] = bload<T>(rb1, (uint32_t)gj[i] * TB, 0);
+        g_p[i] = bload<T>(rb1, (uint32_t)gp[i] * TB, 0);
+        vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
+        bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
+      }
+      wave_sync();
+#pragma unroll
+      for (int m = 0; m < SPL; ++m) stage[min(lane + 64 * m, bs - 1)] = stg[m];
+      wave_sync();
+      const T* fa = s_fab + cc * 64;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int l = lo[i];
+        const T bo = stage[st + jj[i]];
+        T hop = 0;
+#pragma unroll
+        for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+#pragma unroll
+        for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
+        hop -= nidle[i] * bo;
+        hop += act_j[i] ? g_j[i] : T(0);
+        const T dg = zz[i] + fa[l & 31] + fa[32 + (l >> 5)] + dsg;
+        const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+        T o = sig * acc + ta * bo - bt[i];
+        if (v) o += ac * vv[i];
+        bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+      }
+    }
+  }
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  return (s && *s) ? std::atoi(s) : dflt;
+}
+
+template <typename T, int L>
+static void launch_batch(hipStream_t s, const polfed_op* op0, const ChainBatch& bt,
+                         int col0, int ncols, int64_t ld, T half, const T* acoef,
+                         const T* v, const T* b1, const T* b2, T* out) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int NLO = 1 << Lb;
+  static const int bpc_env = env_int("POLFED_BATCH_BPC", 0);
+  const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) +
+                     (size_t)ncols * 64 * sizeof(T) + 4 * kChainStageRows * sizeof(T);
+  const int fit = std::max(1, (int)(kLdsPerCU / shm));
+  const int bpc = bpc_env > 0 ? bpc_env : std::min(fit, kChainBlocksPerCU);
+  ChainSplitDev c = op0->chain_split();
+  const int64_t blocks_needed = (c.nseg + 3) / 4;
+  int64_t grid = std::min<int64_t>(blocks_needed, (int64_t)op0->ctx->n_cu * bpc);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  const bool f64 = sizeof(T) == 8;
+  hipLaunchKernelGGL((k_chain_split_batch<T, L>), dim3((unsigned)grid), dim3(256), shm, s, c,
+                     bt.nb, col0, ncols, ld, half,
+                     (const T*)(f64 ? bt.fab64.get() : bt.fab32.get()),
+                     (const T*)(f64 ? bt.dseg64.get() : bt.dseg32.get()),
+                     (const T*)(f64 ? bt.sc64.get() : bt.sc32.get()), acoef, v, b1, b2, out,
+                     nxcd, c.rec);
+  HIPC(hipGetLastError());
+}
+
+void ChainBatch::init(polfed_ctx* c, const polfed_op* const* o, int n) {
+  REQUIRE(n >= 1, "batch: need at least one operator");
+  ctx = c;
+  nb = n;
+  ops.assign(o, o + n);
+  const polfed_op* op0 = ops[0];
+  for (int i = 0; i < n; ++i) {
+    REQUIRE(ops[i] != nullptr, "batch: null operator");
+    REQUIRE(ops[i]->model == Model::Chain && !ops[i]->pattern_key.empty(),
+            "batch: operators must be XXZ or t-V chains");
+    REQUIRE(ops[i]->pattern_key == op0->pattern_key,
+            "batch: operators must share the off-diagonal pattern (model, L, N, boundary, "
+            "couplings)");
+    REQUIRE(ops[i]->ctx == c, "batch: operator belongs to another context");
+  }
+  REQUIRE(op0->split_nseg > 0, "batch: chain length outside 4..28");
+  const int64_t nseg = op0->split_nseg;
+  std::vector<double> fab((size_t)n * 64), dseg((size_t)nseg * n);
+  for (int i = 0; i < n; ++i) {
+    std::copy(ops[i]->split_fab.begin(), ops[i]->split_fab.end(), fab.begin() + (size_t)i * 64);
+    for (int64_t q = 0; q < nseg; ++q) dseg[(size_t)q * n + i] = ops[i]->split_dseg[q];
+  }
+  hipStream_t s = ctx->stream;
+  upload(fab64, fab.data(), fab.size(), s);
+  upload(dseg64, dseg.data(), dseg.size(), s);
+  std::vector<float> f32(fab.begin(), fab.end()), d32(dseg.begin(), dseg.end());
+  upload(fab32, f32.data(), f32.size(), s);
+  upload(dseg32, d32.data(), d32.size(), s);
+  sc64.alloc((size_t)2 * n * sizeof(double));
+  sc32.alloc((size_t)2 * n * sizeof(float));
+  HIPC(hipStreamSynchronize(s));
+}
+
+void ChainBatch::set_scale(const double* E_c, const double* dE) {
+  std::vector<double> sc(2 * (size_t)nb);
+  for (int i = 0; i < nb; ++i) {
+    REQUIRE(dE[i] > 0 && std::isfinite(dE[i]) && std::isfinite(E_c[i]),
+            "batch: need finite E_c and dE > 0");
+    sc[i] = 2.0 / dE[i];
+    sc[nb + i] = -2.0 * E_c[i] / dE[i];
+  }
+  std::vector<float> s32(sc.begin(), sc.end());
+  hipStream_t s = ctx->stream;
+  HIPC(hipMemcpyAsync(sc64.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(sc32.get(), s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPC(hipStreamSynchronize(s));
+}
+
+template <typename T>
+void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool final_step,
+                      const T* acoef, const T* v, const T* b1, const T* b2, T* out) {
+  const polfed_op* op0 = bt.ops[0];
+  const T half = final_step ? T(0.5) : T(1);
+  for (int col0 = 0; col0 < bt.nb; col0 += kBatchMaxCols) {
+    const int ncols = std::min(kBatchMaxCols, bt.nb - col0);
+    switch (op0->L) {
+#define POLFED_CASE(LL)                                                                   \
+  case LL:                                                                                \
+    launch_batch<T, LL>(s, op0, bt, col0, ncols, ld, half, acoef, v, b1, b2, out); \
+    break;
+      POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
+      POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
+      POLFED_CASE(14) POLFED_CASE(15) POLFED_CASE(16) POLFED_CASE(17) POLFED_CASE(18)
+      POLFED_CASE(19) POLFED_CASE(20) POLFED_CASE(21) POLFED_CASE(22) POLFED_CASE(23)
+      POLFED_CASE(24) POLFED_CASE(25) POLFED_CASE(26) POLFED_CASE(27) POLFED_CASE(28)
+#undef POLFED_CASE
+      default: fail(POLFED_ERR_INVALID, "batch: chain length outside 4..28");
+    }
+  }
+}
+
+template void chain_batch_step<double>(hipStream_t, const ChainBatch&, int64_t, bool,
+                                       const double*, const double*, const double*,
+                                       const double*, double*);
+template void chain_batch_step<float>(hipStream_t, const ChainBatch&, int64_t, bool,
+                                      const float*, const float*, const float*,
+                                      const float*, float*);
+
+}  // namespace polfed

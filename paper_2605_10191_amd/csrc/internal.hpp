@@ -93,6 +93,8 @@ constexpr int kChainLoBits = 10;      // Lb = min(10, L / 2); blocks <= 252 rows
 constexpr int kChainSegRows = 128;    // rows per wavefront segment
 constexpr int kChainStageRows = 256;  // LDS rows staged per wavefront
 constexpr int kChainBlocksPerCU = 6;  // persistent blocks per compute unit
+constexpr int kBatchMaxCols = 16;     // columns per multi-column launch
+constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kChainRecWords = 32;
 constexpr int kChainMaxHighBonds = kChainRecWords - 10;
 // bytes of the packed LDS image of the low-part tables, per low part lo:
@@ -180,6 +182,8 @@ struct polfed_op {
   int split_Lb = 0;
   int64_t split_nseg = 0;
   polfed::DevBuf d_blob64, d_blob32, d_rec;
+  std::vector<double> split_dseg;  // uniform diagonal part of each segment
+  std::vector<double> split_fab;   // field sums of low bits 0-4 | 5-9
   polfed::ChainSplitDev chain_split() const;
   // CSR copy
   bool has_csr = false;
@@ -206,6 +210,25 @@ void basis_unrank(hipStream_t s, int L, int N, int64_t D, const int64_t* ranks,
 void build_split_rank_tables(int L, int N, int Lb, std::vector<int32_t>& hi_off,
                              std::vector<int32_t>& lo_rank);
 
+// A batch of chain operators that share the off-diagonal pattern; column i
+// of every vector block belongs to ops[i].
+struct ChainBatch {
+  polfed_ctx* ctx = nullptr;
+  std::vector<const polfed_op*> ops;
+  int nb = 0;
+  DevBuf fab64, fab32;    // [nb][64] low-bit field sums (bits 0-4 | 5-9)
+  DevBuf dseg64, dseg32;  // [nseg][nb] uniform diagonal part per segment
+  DevBuf sc64, sc32;      // [2][nb] sigma = 2/dE, tau = -2 E_c/dE
+  void init(polfed_ctx* c, const polfed_op* const* o, int n);
+  void set_scale(const double* E_c, const double* dE);
+};
+// out_c = a_c v_c + h (sigma_c H_c b1_c + tau_c b1_c) - b2_c for every
+// column, h = 1/2 on the closing step; acoef: device [nb] (null: no v term);
+// blocks are column-major with column stride ld; out may alias b2.
+template <typename T>
+void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool final_step,
+                      const T* acoef, const T* v, const T* b1, const T* b2, T* out);
+
 // ----------------------------------------------------------- operators ----
 // Fused Clenshaw step for every operator kind and precision:
 //   out = a * v + sigma * (H b1) + tau * b1 - (b2 ? b2 : 0)
@@ -213,8 +236,6 @@ void build_split_rank_tables(int L, int N, int Lb, std::vector<int32_t>& hi_off,
 template <typename T>
 void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
              const T* v, const T* b1, const T* b2, T* out);
-// Multi-column step for B columns stored row-interleaved (element (r, c) at
-// r * B + c); per-column scalars and diagonal tables.
 void op_moments(hipStream_t s, const polfed_op* op, double* d_two, double* partial,
                 int64_t npart);
 // Split-layout chain step; false when no instantiation covers op->L.

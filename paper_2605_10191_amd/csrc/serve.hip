@@ -1,13 +1,8 @@
-// Placeholder for the batched solve and the continuous-batching server.
+// Placeholder for the continuous-batching server.
 #include "internal.hpp"
 
 namespace polfed {
 
-polfed_status solve_batch(polfed_ctx*, int, const polfed_op* const*, const polfed_params&,
-                          const double* const*, double* const*, double* const*,
-                          double* const*, int*, polfed_report*) {
-  fail(POLFED_ERR_INVALID, "batched solve not available yet");
-}
 polfed_status serve_start(polfed_ctx*, size_t, int) {
   fail(POLFED_ERR_INVALID, "serving not available yet");
 }

@@ -1,0 +1,131 @@
+// Resumable POLFED solve: the per-realization state of the filtered Lanczos
+// iteration, driven either one column at a time or by a multi-column filter
+// shared with other realizations.
+#pragma once
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace polfed {
+
+struct Basis {
+  int64_t D = 0;
+  int cap = 0;  // columns available beyond v_0: V holds cap + 1 vectors
+  DevBuf V;
+  void ensure(hipStream_t s, int64_t D_, int need_cap, int keep_cols) {
+    if (need_cap <= cap && D_ == D) return;
+    DevBuf nv((size_t)D_ * (need_cap + 1) * sizeof(double));
+    if (keep_cols > 0)
+      HIPC(hipMemcpyAsync(nv.get(), V.get(), (size_t)D_ * keep_cols * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    V = std::move(nv);
+    D = D_;
+    cap = need_cap;
+  }
+  double* col(int j) const { return V.as<double>() + (size_t)j * D; }
+};
+
+struct Ws {
+  DevBuf w, c, partial, scal, flag, alpha, beta, bA, bB, v32, w32;
+  int64_t nseg = 0;
+  int coef_cap = 0;
+  void init(hipStream_t s, int64_t D, int max_cols, bool fp32) {
+    w.alloc(std::max<int64_t>(D, 1) * sizeof(double));
+    nseg = std::max<int64_t>(1, std::min<int64_t>(256, (D + 8191) / 8192));
+    grow(s, max_cols);
+    scal.alloc(64 * sizeof(double));
+    flag.alloc(sizeof(int));
+    HIPC(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+    const size_t tb = fp32 ? sizeof(float) : sizeof(double);
+    bA.alloc(std::max<int64_t>(D, 1) * tb);
+    bB.alloc(std::max<int64_t>(D, 1) * tb);
+    if (fp32) {
+      v32.alloc(std::max<int64_t>(D, 1) * sizeof(float));
+      w32.alloc(std::max<int64_t>(D, 1) * sizeof(float));
+    }
+  }
+  void grow(hipStream_t s, int max_cols) {
+    if (max_cols <= coef_cap) return;
+    DevBuf na((size_t)(max_cols + 1) * sizeof(double)), nb((size_t)(max_cols + 2) * sizeof(double));
+    if (coef_cap > 0) {
+      HIPC(hipMemcpyAsync(na.get(), alpha.get(), (size_t)(coef_cap + 1) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+      HIPC(hipMemcpyAsync(nb.get(), beta.get(), (size_t)(coef_cap + 2) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+      HIPC(hipStreamSynchronize(s));
+    }
+    alpha = std::move(na);
+    beta = std::move(nb);
+    c.alloc((size_t)(max_cols + 1) * sizeof(double));
+    partial.alloc((size_t)nseg * (max_cols + 1) * sizeof(double) + 8192 * sizeof(double));
+    coef_cap = max_cols;
+  }
+};
+
+struct SolveRun {
+  // inputs
+  polfed_ctx* ctx = nullptr;
+  const polfed_op* op = nullptr;
+  polfed_params p{};
+  double* evals = nullptr;
+  double* evecs = nullptr;
+  double* resid = nullptr;
+  int* n_found = nullptr;
+  // plan
+  bool fp32 = false;
+  double tol_resid = 1e-8, tol_ritz = 1e-10, lam = 0, sbytes = 0, t_start = 0;
+  polfed_plan pl{};
+  std::vector<double> a;  // filter coefficients a_0..a_K
+  // Lanczos state
+  int n_want = 0, M_alloc = 0, M_max = 0, cap = 0, check_every = 0, next_check = 0, k = 0;
+  uint64_t restart_seed = 0;
+  Basis B;
+  Ws ws;
+  polfed_report R{};
+  polfed_status status = POLFED_NOT_CONVERGED;
+  bool done = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> fev, rev;
+
+  SolveRun() = default;
+  SolveRun(const SolveRun&) = delete;
+  SolveRun& operator=(const SolveRun&) = delete;
+  ~SolveRun();
+  // bounds, plan, basis allocation, v_0 = x0 / ||x0||
+  void setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm, const double* x0,
+             double* ev, double* vecs, double* res, int* nf);
+  // device bytes a solve of this operator holds at its expected Krylov size
+  static size_t footprint(const polfed_op* op, const polfed_params& p);
+  const double* vec() const { return B.col(k); }  // v_k, the vector to filter
+  double* wbuf() const { return ws.w.as<double>(); }  // where P(H~) v_k goes
+  void filter_self();  // single-column filter of v_k into wbuf()
+  void advance();      // CGS2, k += 1, periodic check; sets done when finished
+  void finish();
+  void drain();
+};
+
+// Device coefficient table [(Kmax + 1)][nb] of a multi-column filter; column
+// c is zero above its own order K[c].
+struct BatchCoef {
+  DevBuf d64, d32;
+  int nb = 0, Kmax = 0;
+  void set(hipStream_t s, int nb, const double* const* a, const int* K);
+};
+
+template <typename T>
+void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& co,
+                        const T* v, T* w, T* bufA, T* bufB);
+
+// The multi-column filter shared by a set of running solves.
+struct BatchFilter {
+  polfed_ctx* ctx = nullptr;
+  std::vector<SolveRun*> members;
+  bool fp32 = false;
+  ChainBatch bt;
+  BatchCoef co;
+  DevBuf vb, wb, bA, bB;  // D x nb blocks
+  void form(polfed_ctx* c, const std::vector<SolveRun*>& runs);
+  double run();  // filters v_k of every member into its w; seconds
+};
+
+}  // namespace polfed

@@ -13,6 +13,7 @@
 #include <numeric>
 
 #include "internal.hpp"
+#include "solve_run.hpp"
 
 namespace polfed {
 
@@ -74,60 +75,6 @@ template void filter_apply<float>(polfed_ctx*, const polfed_op*, double, double,
 // ------------------------------------------------------------ Lanczos ----
 
 namespace {
-
-struct Basis {
-  int64_t D = 0;
-  int cap = 0;  // columns available beyond v_0: V holds cap + 1 vectors
-  DevBuf V;
-  void ensure(hipStream_t s, int64_t D_, int need_cap, int keep_cols) {
-    if (need_cap <= cap && D_ == D) return;
-    DevBuf nv((size_t)D_ * (need_cap + 1) * sizeof(double));
-    if (keep_cols > 0)
-      HIPC(hipMemcpyAsync(nv.get(), V.get(), (size_t)D_ * keep_cols * sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
-    V = std::move(nv);
-    D = D_;
-    cap = need_cap;
-  }
-  double* col(int j) const { return V.as<double>() + (size_t)j * D; }
-};
-
-struct Ws {
-  DevBuf w, c, partial, scal, flag, alpha, beta, bA, bB, v32, w32;
-  int64_t nseg = 0;
-  int coef_cap = 0;
-  void init(hipStream_t s, int64_t D, int max_cols, bool fp32) {
-    w.alloc(std::max<int64_t>(D, 1) * sizeof(double));
-    nseg = std::max<int64_t>(1, std::min<int64_t>(256, (D + 8191) / 8192));
-    grow(s, max_cols);
-    scal.alloc(64 * sizeof(double));
-    flag.alloc(sizeof(int));
-    HIPC(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
-    const size_t tb = fp32 ? sizeof(float) : sizeof(double);
-    bA.alloc(std::max<int64_t>(D, 1) * tb);
-    bB.alloc(std::max<int64_t>(D, 1) * tb);
-    if (fp32) {
-      v32.alloc(std::max<int64_t>(D, 1) * sizeof(float));
-      w32.alloc(std::max<int64_t>(D, 1) * sizeof(float));
-    }
-  }
-  void grow(hipStream_t s, int max_cols) {
-    if (max_cols <= coef_cap) return;
-    DevBuf na((size_t)(max_cols + 1) * sizeof(double)), nb((size_t)(max_cols + 2) * sizeof(double));
-    if (coef_cap > 0) {
-      HIPC(hipMemcpyAsync(na.get(), alpha.get(), (size_t)(coef_cap + 1) * sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
-      HIPC(hipMemcpyAsync(nb.get(), beta.get(), (size_t)(coef_cap + 2) * sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
-      HIPC(hipStreamSynchronize(s));
-    }
-    alpha = std::move(na);
-    beta = std::move(nb);
-    c.alloc((size_t)(max_cols + 1) * sizeof(double));
-    partial.alloc((size_t)nseg * (max_cols + 1) * sizeof(double) + 8192 * sizeof(double));
-    coef_cap = max_cols;
-  }
-};
 
 // w <- w - V V^T w twice over the first k1 basis vectors; the first column
 // projection of each pass adds up alpha[k]; then beta_next = ||w|| and
@@ -325,21 +272,29 @@ double step_bytes(const polfed_op* op, int precision) {
 
 }  // namespace
 
-polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p,
-                    const double* x0, double* evals, double* evecs, double* resid,
-                    int* n_found, polfed_report* rep) {
+// ---------------------------------------------------------- SolveRun ----
+
+void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm,
+                     const double* x0, double* ev, double* vecs, double* res, int* nf) {
+  ctx = c;
+  op = o;
+  p = prm;
+  evals = ev;
+  evecs = vecs;
+  resid = res;
+  n_found = nf;
   hipStream_t s = ctx->stream;
-  const double t_start = now_seconds();
+  t_start = now_seconds();
   const int64_t D = op->D;
   REQUIRE(D >= 1, "solve: empty operator");
   REQUIRE(p.n_ev >= 1 && p.n_ev <= D, "solve: need 1 <= n_ev <= D");
   REQUIRE(p.precision == POLFED_FP64 || p.precision == POLFED_FP32, "solve: bad precision");
   REQUIRE(x0 && evals && evecs && resid && n_found, "solve: null buffer");
-  const bool fp32 = p.precision == POLFED_FP32;
-  const double tol_resid = p.tol_resid > 0 ? p.tol_resid : 1e-8;
+  fp32 = p.precision == POLFED_FP32;
+  tol_resid = p.tol_resid > 0 ? p.tol_resid : 1e-8;
   const double pad = p.bound_pad > 0 ? p.bound_pad : 1e-3;
   const double eta = p.eta > 0 ? p.eta : 1.5;
-  polfed_report R{};
+  R = polfed_report{};
   *n_found = 0;
 
   // 1. spectral bounds
@@ -361,11 +316,10 @@ polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p
   HIPC(hipMemcpyAsync(tr, two.get(), sizeof tr, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   const double tr1 = tr[0] / (double)D, tr2 = tr[1] / (double)D;
-  const double lam = target_energy(p.target_kind, p.target, E_min, E_max);
-  int n_want = (int)std::min<int64_t>(D, p.n_ev + buffer_size(p.n_ev));
-  const polfed_plan pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega,
-                                   p.K_override);
-  std::vector<double> a(pl.K + 1);
+  lam = target_energy(p.target_kind, p.target, E_min, E_max);
+  n_want = (int)std::min<int64_t>(D, p.n_ev + buffer_size(p.n_ev));
+  pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega, p.K_override);
+  a.assign(pl.K + 1, 0.0);
   filter_coefficients(pl.lambda_t, pl.K, a.data());
   R.t_plan = now_seconds() - t0;
   R.lambda = lam;
@@ -376,27 +330,55 @@ polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p
   R.rho = pl.rho;
   R.K = pl.K;
 
-  // 4. filtered Lanczos
-  const int M_alloc = expected_krylov_dim(n_want, 1, eta);
-  const int M_max = (int)std::min<int64_t>(D, p.max_iter > 0 ? p.max_iter : 4 * M_alloc);
-  int cap = std::min(M_alloc, M_max);
+  // 4. filtered Lanczos state
+  M_alloc = expected_krylov_dim(n_want, 1, eta);
+  M_max = (int)std::min<int64_t>(D, p.max_iter > 0 ? p.max_iter : 4 * M_alloc);
+  cap = std::min(M_alloc, M_max);
   R.M_alloc = M_alloc;
-  Basis B;
   B.ensure(s, D, cap, 0);
-  Ws ws;
   ws.init(s, D, cap + 1, fp32);
   normalize_into(s, D, x0, ws, B.col(0));
-  const int check_every = std::max(10, (int)std::ceil(0.05 * M_alloc));
-  int next_check = std::min(n_want, M_max);
-  std::vector<double> al, be;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> fev, rev;
-  auto ev_pair = [&]() {
-    hipEvent_t e0, e1;
-    HIPC(hipEventCreate(&e0));
-    HIPC(hipEventCreate(&e1));
-    return std::make_pair(e0, e1);
-  };
-  auto drain = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& acc) {
+  check_every = std::max(10, (int)std::ceil(0.05 * M_alloc));
+  next_check = std::min(n_want, M_max);
+  k = 0;
+  done = false;
+  status = POLFED_NOT_CONVERGED;
+  restart_seed = 0x5EEDULL;
+  sbytes = step_bytes(op, p.precision);
+}
+
+size_t SolveRun::footprint(const polfed_op* op, const polfed_params& p) {
+  const int n_ev = std::max(1, p.n_ev);
+  const int n_want = (int)std::min<int64_t>(op->D, n_ev + buffer_size(n_ev));
+  const int M = expected_krylov_dim(n_want, 1, p.eta > 0 ? p.eta : 1.5);
+  const size_t D = (size_t)op->D;
+  // basis, the work vectors and the extraction blocks (U, HU, U2, HU2)
+  return D * 8 * ((size_t)M + 2) + D * 8 * 4 * (size_t)n_want + D * 8 * 3;
+}
+
+void SolveRun::filter_self() {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  HIPC(hipEventRecord(e0, s));
+  if (fp32) {
+    dev_copy_d2f(s, D, B.col(k), ws.v32.as<float>());
+    filter_apply<float>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, ws.v32.as<float>(),
+                        ws.w32.as<float>(), ws.bA.as<float>(), ws.bB.as<float>());
+    dev_copy_f2d(s, D, ws.w32.as<float>(), ws.w.as<double>());
+  } else {
+    filter_apply<double>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, B.col(k), ws.w.as<double>(),
+                         ws.bA.as<double>(), ws.bB.as<double>());
+  }
+  HIPC(hipEventRecord(e1, s));
+  fev.emplace_back(e0, e1);
+  R.filter_steps += pl.K;
+}
+
+void SolveRun::drain() {
+  auto one = [](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& acc) {
     for (auto& pr : v) {
       float ms = 0;
       HIPC(hipEventElapsedTime(&ms, pr.first, pr.second));
@@ -406,140 +388,156 @@ polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p
     }
     v.clear();
   };
-  const double sbytes = step_bytes(op, p.precision);
-  int k = 0;
-  polfed_status status = POLFED_NOT_CONVERGED;
-  uint64_t restart_seed = 0x5EEDULL;
-  for (;;) {
-    auto fe = ev_pair();
-    HIPC(hipEventRecord(fe.first, s));
-    if (fp32) {
-      dev_copy_d2f(s, D, B.col(k), ws.v32.as<float>());
-      filter_apply<float>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, ws.v32.as<float>(),
-                          ws.w32.as<float>(), ws.bA.as<float>(), ws.bB.as<float>());
-      dev_copy_f2d(s, D, ws.w32.as<float>(), ws.w.as<double>());
-    } else {
-      filter_apply<double>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, B.col(k),
-                           ws.w.as<double>(), ws.bA.as<double>(), ws.bB.as<double>());
-    }
-    HIPC(hipEventRecord(fe.second, s));
-    fev.push_back(fe);
-    R.filter_steps += pl.K;
-    auto re = ev_pair();
-    HIPC(hipEventRecord(re.first, s));
-    cgs2_normalize(s, D, k + 1, B, ws, ws.alpha.as<double>() + k,
-                   ws.beta.as<double>() + k + 1, B.col(k + 1));
-    HIPC(hipEventRecord(re.second, s));
-    rev.push_back(re);
-    ++k;
-    if (k >= cap && cap < M_max) {
-      const int ncap = std::min(M_max, (int)std::ceil(1.25 * cap) + 1);
-      B.ensure(s, D, ncap, k + 1);
-      ws.grow(s, ncap + 1);
-      cap = ncap;
-    }
-    if (k < next_check && k < M_max) continue;
+  one(fev, R.t_filter);
+  one(rev, R.t_reorth);
+}
 
-    // periodic check (eq. lan_criterion)
-    const double tc = now_seconds();
-    al.resize(k);
-    be.resize(k + 1);
-    int flag = 0;
-    HIPC(hipMemcpyAsync(al.data(), ws.alpha.get(), k * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(be.data(), ws.beta.get(), (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(&flag, ws.flag.get(), sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    drain(fev, R.t_filter);
-    drain(rev, R.t_reorth);
-    for (int i = 0; i < k; ++i)
-      if (!std::isfinite(al[i]) || std::fabs(al[i]) > 4.0 || !std::isfinite(be[i + 1]))
-        fail(POLFED_ERR_BOUNDS,
-             "filter blow-up: Lanczos coefficient " + std::to_string(al[i]) +
-                 " at step " + std::to_string(i) + " (spectral bounds too tight?)");
-    // breakdown: restart from the first vanishing beta with a random vector
-    int kb = -1;
-    for (int i = 1; i <= k; ++i)
-      if (be[i] <= 1e-13) { kb = i; break; }
-    if (kb > 0 && kb < M_max) {
-      if (R.restarts >= 8) fail(POLFED_ERR_BREAKDOWN, "Lanczos breakdown: too many restarts");
-      ++R.restarts;
-      k = kb;
-      double* w = ws.w.as<double>();
-      dev_random(s, D, restart_seed++, w);
-      double* junk = ws.scal.as<double>() + 8;
-      for (int pass = 0; pass < 2; ++pass) {
-        dev_gemv_t(s, D, k, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
-                   ws.c.as<double>(), junk, 0);
-        dev_gemv_n_sub(s, D, k, B.V.as<double>(), D, ws.c.as<double>(), w);
-      }
-      double zero = 0.0;
-      HIPC(hipMemcpyAsync(ws.beta.as<double>() + k, &zero, sizeof(double), hipMemcpyHostToDevice, s));
-      normalize_into(s, D, w, ws, B.col(k));
-      HIPC(hipMemsetAsync(ws.flag.get(), 0, sizeof(int), s));
-      HIPC(hipStreamSynchronize(s));
-      next_check = k + 1;
-      R.t_check += now_seconds() - tc;
-      continue;
+SolveRun::~SolveRun() {
+  for (auto* v : {&fev, &rev})
+    for (auto& pr : *v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
     }
-    ++R.checks;
-    std::vector<double> th, zl;
-    ritz_last(k, al, be, th, zl);
-    std::vector<int> order(k);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return th[x] > th[y]; });
-    const int nw = std::min(n_want, k);
-    double thmax = 0;
-    for (double t : th) thmax = std::max(thmax, std::fabs(t));
-    bool conv = true;
-    for (int j = 0; j < nw; ++j)
-      if (std::fabs(be[k] * zl[order[j]]) > 1e-10 * std::max(1.0, thmax)) conv = false;
-    R.t_check += now_seconds() - tc;
-    if (conv || k >= M_max) {
-      const double tx = now_seconds();
-      std::vector<double> thf, Y;
-      ritz_full(k, al, be, thf, Y);
-      // the full solve orders eigenvalues alike; pick the n_want largest
-      std::vector<int> ord(k);
-      std::iota(ord.begin(), ord.end(), 0);
-      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return thf[x] > thf[y]; });
-      std::vector<double> Ysel((size_t)k * nw);
-      for (int j = 0; j < nw; ++j)
-        for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
-      const double theta_min = thf[ord[nw - 1]];
-      Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw, theta_min, lam, p.n_ev, tol_resid, pl);
-      R.t_extract += now_seconds() - tx;
-      const bool done = (int)ex.sel.size() == p.n_ev && ex.complete;
-      if (done || k >= M_max) {
-        const int nf = (int)ex.sel.size();
-        std::vector<double> Eo(nf), Ro(nf);
-        for (int j = 0; j < nf; ++j) {
-          Eo[j] = ex.E[ex.sel[j]];
-          Ro[j] = ex.res[ex.sel[j]];
-          dcopy_async(s, evecs + (size_t)j * D, ex.U2.as<double>() + (size_t)ex.sel[j] * D,
-                      (size_t)D, hipMemcpyDeviceToDevice);
-        }
-        dcopy_async(s, evals, Eo.data(), (size_t)nf, hipMemcpyHostToDevice);
-        dcopy_async(s, resid, Ro.data(), (size_t)nf, hipMemcpyHostToDevice);
-        HIPC(hipStreamSynchronize(s));
-        *n_found = nf;
-        R.n_converged = nf;
-        status = done ? POLFED_OK : POLFED_NOT_CONVERGED;
-        break;
-      }
-      if ((int)ex.sel.size() == p.n_ev && !ex.complete)
-        n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
-    }
-    next_check = k + check_every;
+}
+
+// Full reorthogonalization of w = P(H~) v_k against the basis (CGS2), then
+// the periodic convergence check (eq. lan_criterion), extraction and the
+// completeness test once the check passes.
+void SolveRun::advance() {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  hipEvent_t r0, r1;
+  HIPC(hipEventCreate(&r0));
+  HIPC(hipEventCreate(&r1));
+  HIPC(hipEventRecord(r0, s));
+  cgs2_normalize(s, D, k + 1, B, ws, ws.alpha.as<double>() + k, ws.beta.as<double>() + k + 1,
+                 B.col(k + 1));
+  HIPC(hipEventRecord(r1, s));
+  rev.emplace_back(r0, r1);
+  ++k;
+  if (k >= cap && cap < M_max) {
+    const int ncap = std::min(M_max, (int)std::ceil(1.25 * cap) + 1);
+    B.ensure(s, D, ncap, k + 1);
+    ws.grow(s, ncap + 1);
+    cap = ncap;
   }
-  drain(fev, R.t_filter);
-  drain(rev, R.t_reorth);
+  if (k < next_check && k < M_max) return;
+
+  const double tc = now_seconds();
+  std::vector<double> al(k), be(k + 1);
+  HIPC(hipMemcpyAsync(al.data(), ws.alpha.get(), k * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(be.data(), ws.beta.get(), (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  drain();
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(al[i]) || std::fabs(al[i]) > 4.0 || !std::isfinite(be[i + 1]))
+      fail(POLFED_ERR_BOUNDS, "filter blow-up: Lanczos coefficient " + std::to_string(al[i]) +
+                                  " at step " + std::to_string(i) +
+                                  " (spectral bounds too tight?)");
+  // breakdown: restart from the first vanishing beta with a random vector
+  int kb = -1;
+  for (int i = 1; i <= k; ++i)
+    if (be[i] <= 1e-13) {
+      kb = i;
+      break;
+    }
+  if (kb > 0 && kb < M_max) {
+    if (R.restarts >= 8) fail(POLFED_ERR_BREAKDOWN, "Lanczos breakdown: too many restarts");
+    ++R.restarts;
+    k = kb;
+    double* w = ws.w.as<double>();
+    dev_random(s, D, restart_seed++, w);
+    double* junk = ws.scal.as<double>() + 8;
+    for (int pass = 0; pass < 2; ++pass) {
+      dev_gemv_t(s, D, k, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
+                 ws.c.as<double>(), junk, 0);
+      dev_gemv_n_sub(s, D, k, B.V.as<double>(), D, ws.c.as<double>(), w);
+    }
+    double zero = 0.0;
+    HIPC(hipMemcpyAsync(ws.beta.as<double>() + k, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+    normalize_into(s, D, w, ws, B.col(k));
+    HIPC(hipMemsetAsync(ws.flag.get(), 0, sizeof(int), s));
+    HIPC(hipStreamSynchronize(s));
+    next_check = k + 1;
+    R.t_check += now_seconds() - tc;
+    return;
+  }
+  ++R.checks;
+  std::vector<double> th, zl;
+  ritz_last(k, al, be, th, zl);
+  std::vector<int> order(k);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return th[x] > th[y]; });
+  const int nw = std::min(n_want, k);
+  double thmax = 0;
+  for (double t : th) thmax = std::max(thmax, std::fabs(t));
+  bool conv = true;
+  for (int j = 0; j < nw; ++j)
+    if (std::fabs(be[k] * zl[order[j]]) > tol_ritz * std::max(1.0, thmax)) conv = false;
+  R.t_check += now_seconds() - tc;
+  if (conv || k >= M_max) {
+    const double tx = now_seconds();
+    std::vector<double> thf, Y;
+    ritz_full(k, al, be, thf, Y);
+    // the full solve orders eigenvalues alike; pick the n_want largest
+    std::vector<int> ord(k);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return thf[x] > thf[y]; });
+    std::vector<double> Ysel((size_t)k * nw);
+    for (int j = 0; j < nw; ++j)
+      for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
+    const double theta_min = thf[ord[nw - 1]];
+    Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw, theta_min, lam, p.n_ev, tol_resid, pl);
+    R.t_extract += now_seconds() - tx;
+    const bool ok = (int)ex.sel.size() == p.n_ev && ex.complete;
+    if (ok || k >= M_max) {
+      const int nf = (int)ex.sel.size();
+      std::vector<double> Eo(nf), Ro(nf);
+      for (int j = 0; j < nf; ++j) {
+        Eo[j] = ex.E[ex.sel[j]];
+        Ro[j] = ex.res[ex.sel[j]];
+        dcopy_async(s, evecs + (size_t)j * D, ex.U2.as<double>() + (size_t)ex.sel[j] * D,
+                    (size_t)D, hipMemcpyDeviceToDevice);
+      }
+      dcopy_async(s, evals, Eo.data(), (size_t)nf, hipMemcpyHostToDevice);
+      dcopy_async(s, resid, Ro.data(), (size_t)nf, hipMemcpyHostToDevice);
+      HIPC(hipStreamSynchronize(s));
+      *n_found = nf;
+      R.n_converged = nf;
+      status = ok ? POLFED_OK : POLFED_NOT_CONVERGED;
+      finish();
+      return;
+    }
+    if ((int)ex.sel.size() == p.n_ev && !ex.complete)
+      n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
+  }
+  next_check = k + check_every;
+}
+
+void SolveRun::finish() {
+  drain();
   R.iters = k;
   R.n_want = n_want;
   R.filter_bytes = R.filter_steps * sbytes;
   R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
   R.t_total = now_seconds() - t_start;
-  if (rep) *rep = R;
-  return status;
+  done = true;
+  // the basis and work vectors are not needed any more
+  B = Basis{};
+  ws = Ws{};
+}
+
+polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p,
+                    const double* x0, double* evals, double* evecs, double* resid,
+                    int* n_found, polfed_report* rep) {
+  SolveRun run;
+  run.setup(ctx, op, p, x0, evals, evecs, resid, n_found);
+  while (!run.done) {
+    run.filter_self();
+    run.advance();
+  }
+  if (rep) *rep = run.R;
+  return run.status;
 }
 
 // ---------------------------------------------- single Lanczos step (API) ----
