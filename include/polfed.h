@@ -287,6 +287,8 @@ typedef struct {
   double filter_steps;   /* Clenshaw steps executed */
   double filter_bytes;   /* algorithmic HBM bytes of those steps */
   double filter_GBps;    /* filter_bytes / t_filter / 1e9 */
+  double t_queue;        /* served requests: submission to admission (s) */
+  double t_latency;      /* served requests: submission to result (s) */
 } polfed_report;
 
 polfed_status polfed_params_default(polfed_params* p);

@@ -59,7 +59,7 @@ class Report(ctypes.Structure):
                 [(n, ctypes.c_double) for n in
                  ("t_bounds", "t_plan", "t_filter", "t_reorth", "t_check",
                   "t_extract", "t_refine", "t_total", "filter_steps",
-                  "filter_bytes", "filter_GBps")])
+                  "filter_bytes", "filter_GBps", "t_queue", "t_latency")])
 
     def as_dict(self) -> dict:
         d = {n: getattr(self, n) for n, _ in self._fields_}
@@ -515,3 +515,73 @@ def solve_batch(ops, x0s, n_ev, target, target_kind="normalized", precision=FP64
         out.append((evals[i][:n], evecs[i].view(n_ev, o.D)[:n].T, resid[i][:n],
                     reps[i].as_dict()))
     return out, STATUS[code]
+
+
+class Request:
+    """A solve queued on a Server; keeps its start vector and output tensors
+    alive until the result has been collected."""
+
+    def __init__(self, server, op, x0, n_ev, params):
+        self.server, self.op, self.x0, self.n_ev = server, op, x0, n_ev
+        ctx = op.ctx
+        self.evals = ctx.empty(n_ev)
+        self.evecs = ctx.empty(n_ev * op.D)
+        self.resid = ctx.empty(n_ev)
+        self.params = params
+        self.handle = _P()
+        _check(_lib.polfed_submit(ctx.handle, op.handle, ctypes.byref(params),
+                                  _ptr(x0), _ptr(self.evals), _ptr(self.evecs),
+                                  _ptr(self.resid), ctypes.byref(self.handle)))
+        self.result = None
+
+    def poll(self) -> bool:
+        d = _I()
+        _check(_lib.polfed_poll(self.handle, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, allow_partial=False):
+        """(evals, evecs (D x n), resid, report dict, status)."""
+        if self.result is None:
+            nf = _I()
+            rep = Report()
+            code = _lib.polfed_wait(self.handle, ctypes.byref(nf), ctypes.byref(rep))
+            msg = _lib.polfed_last_error().decode(errors="replace") if code < 0 else ""
+            _lib.polfed_req_destroy(self.handle)
+            self.handle = None
+            if code < 0:
+                raise PolfedError(code, msg)
+            if code == 1 and not allow_partial:
+                raise PolfedError(code, "not converged")
+            n = nf.value
+            self.result = (self.evals[:n], self.evecs.view(self.n_ev, self.op.D)[:n].T,
+                           self.resid[:n], rep.as_dict(), STATUS[code])
+        return self.result
+
+
+class Server:
+    """Continuous-batching solve server on a context: requests are admitted
+    while their Krylov bases fit `hbm_budget_bytes` and fewer than `max_cols`
+    solves run; solves of chains sharing one pattern filter together."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_cols: int = 16):
+        self.ctx = ctx
+        _check(_lib.polfed_serve_start(ctx.handle, ctypes.c_size_t(int(hbm_budget_bytes)),
+                                       int(max_cols)))
+        self.running = True
+
+    def submit(self, op: Operator, x0, n_ev, target, target_kind="normalized",
+               precision=FP64, **kw) -> Request:
+        p = make_params(n_ev, target, target_kind, precision, **kw)
+        return Request(self, op, x0, n_ev, p)
+
+    def stop(self):
+        """Finishes every submitted request, then stops the scheduler."""
+        if self.running:
+            self.running = False
+            _check(_lib.polfed_serve_stop(self.ctx.handle))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

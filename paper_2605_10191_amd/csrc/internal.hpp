@@ -147,6 +147,10 @@ enum class Model { Chain, Qsun, Csr };
 }  // namespace polfed
 
 // Opaque handles of the C ABI.
+namespace polfed {
+struct Server;
+}
+
 struct polfed_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -158,7 +162,7 @@ struct polfed_ctx {
   polfed::DevBuf scratch_scalar;
   polfed::DevBuf binom;  // binomial table for the basis calls
   polfed::DevBuf ws[8];  // scratch of the single-step entry points
-  struct Server* server = nullptr;
+  polfed::Server* server = nullptr;
 };
 
 struct polfed_op {

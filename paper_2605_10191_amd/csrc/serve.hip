@@ -1,20 +1,281 @@
-// Placeholder for the continuous-batching server.
+// Continuous-batching solve server.
+//
+// A scheduler thread owns the context's stream while serving.  Each cycle it
+//   1. admits queued requests in arrival order while a column slot is free
+//      and the device bytes their Krylov bases need fit the budget (a request
+//      that does not fit waits; one larger than the whole budget is refused
+//      at submission), running their bounds and plan;
+//   2. groups the running solves by operator pattern and precision; each
+//      group filters the current Lanczos vector of all its members as one
+//      multi-column recurrence, then every member takes its own Lanczos step
+//      (reorthogonalization, convergence check, extraction);
+//   3. retires the members that finished, which frees their slots and bytes
+//      for the next admissions.
+// Requests thus join and leave a running batch between Lanczos iterations,
+// and a request's result does not depend on which others share its batch
+// beyond the rounding of the batched filter.
+#include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
 #include "internal.hpp"
+#include "solve_run.hpp"
+
+struct polfed_req {
+  polfed_ctx* ctx = nullptr;
+  const polfed_op* op = nullptr;
+  polfed_params p{};
+  const double* x0 = nullptr;
+  double *evals = nullptr, *evecs = nullptr, *resid = nullptr;
+  size_t footprint = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  std::mutex m;
+  std::condition_variable cv;
+  bool done = false;
+  polfed_status status = POLFED_OK;
+  std::string err;
+  int n_found = 0;
+  polfed_report rep{};
+  std::unique_ptr<polfed::SolveRun> run;
+};
 
 namespace polfed {
 
-polfed_status serve_start(polfed_ctx*, size_t, int) {
-  fail(POLFED_ERR_INVALID, "serving not available yet");
+struct Server {
+  polfed_ctx* ctx = nullptr;
+  size_t budget = 0, used = 0;
+  int max_cols = 0;
+  std::mutex m;
+  std::condition_variable cv;
+  std::deque<polfed_req*> pending;
+  std::vector<polfed_req*> active;
+  bool stop = false;
+  std::thread th;
+  struct Group {
+    std::vector<SolveRun*> members;
+    BatchFilter bf;
+  };
+  std::map<std::string, Group> groups;
+  void loop();
+  void admit();
+  void complete(polfed_req* r, polfed_status st, const std::string& err);
+};
+
+static std::string group_key(const polfed_req* r) {
+  const polfed_op* op = r->op;
+  const bool batchable = op->model == Model::Chain && !op->pattern_key.empty() &&
+                         op->split_nseg > 0;
+  // operators that cannot share a recurrence each form their own group
+  std::string k = batchable ? op->pattern_key : "op:" + std::to_string((uintptr_t)op) + ":" +
+                                                    std::to_string((uintptr_t)r);
+  return k + (r->p.precision == POLFED_FP32 ? "|f32" : "|f64");
 }
-polfed_status serve_submit(polfed_ctx*, const polfed_op*, const polfed_params*, const double*,
-                           double*, double*, double*, polfed_req**) {
-  fail(POLFED_ERR_INVALID, "serving not available yet");
+
+void Server::complete(polfed_req* r, polfed_status st, const std::string& err) {
+  {
+    std::lock_guard<std::mutex> lk(r->m);
+    r->status = st;
+    r->err = err;
+    if (r->run) r->rep = r->run->R;
+    r->t_done = now_seconds();
+    r->rep.t_queue = r->t_admit > 0 ? r->t_admit - r->t_submit : 0;
+    r->rep.t_latency = r->t_done - r->t_submit;
+    r->done = true;
+  }
+  r->cv.notify_all();
 }
-polfed_status req_poll(polfed_req*, int*) { fail(POLFED_ERR_INVALID, "serving not available yet"); }
-polfed_status req_wait(polfed_req*, int*, polfed_report*) {
-  fail(POLFED_ERR_INVALID, "serving not available yet");
+
+// Admission in arrival order: stop at the first request that does not fit,
+// so a large request is not overtaken for ever by smaller ones.
+void Server::admit() {
+  for (;;) {
+    polfed_req* r = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(m);
+      if (pending.empty() || (int)active.size() >= max_cols) return;
+      if (used + pending.front()->footprint > budget) return;
+      r = pending.front();
+      pending.pop_front();
+      used += r->footprint;
+    }
+    r->t_admit = now_seconds();
+    try {
+      r->run.reset(new SolveRun());
+      r->run->setup(ctx, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
+      active.push_back(r);
+    } catch (const Error& e) {
+      {
+        std::lock_guard<std::mutex> lk(m);
+        used -= r->footprint;
+      }
+      complete(r, e.code, e.what());
+    } catch (const std::exception& e) {
+      {
+        std::lock_guard<std::mutex> lk(m);
+        used -= r->footprint;
+      }
+      complete(r, POLFED_ERR_INVALID, e.what());
+    }
+  }
 }
-polfed_status req_destroy(polfed_req*) { return POLFED_OK; }
-polfed_status serve_stop(polfed_ctx*) { return POLFED_OK; }
+
+void Server::loop() {
+  (void)hipSetDevice(ctx->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(m);
+      cv.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
+      if (stop && pending.empty() && active.empty()) return;
+    }
+    std::lock_guard<std::mutex> ctx_lk(ctx->mu);
+    admit();
+    // current groups
+    std::map<std::string, std::vector<polfed_req*>> by_key;
+    for (auto* r : active) by_key[group_key(r)].push_back(r);
+    for (auto it = groups.begin(); it != groups.end();)
+      it = by_key.count(it->first) ? std::next(it) : groups.erase(it);
+    std::vector<polfed_req*> retired;
+    for (auto& kv : by_key) {
+      std::vector<SolveRun*> runs;
+      for (auto* r : kv.second) runs.push_back(r->run.get());
+      Group& g = groups[kv.first];
+      try {
+        if (runs.size() == 1 && kv.first.rfind("op:", 0) == 0) {
+          runs[0]->filter_self();
+        } else {
+          if (runs != g.members) {
+            g.bf.form(ctx, runs);
+            g.members = runs;
+          }
+          g.bf.run();
+        }
+      } catch (const Error& e) {
+        for (auto* r : kv.second) {
+          complete(r, e.code, e.what());
+          retired.push_back(r);
+        }
+        continue;
+      }
+      for (auto* r : kv.second) {
+        try {
+          r->run->advance();
+          if (r->run->done) {
+            complete(r, r->run->status, "");
+            retired.push_back(r);
+          }
+        } catch (const Error& e) {
+          complete(r, e.code, e.what());
+          retired.push_back(r);
+        } catch (const std::exception& e) {
+          complete(r, POLFED_ERR_INVALID, e.what());
+          retired.push_back(r);
+        }
+      }
+    }
+    if (!retired.empty()) {
+      std::lock_guard<std::mutex> lk(m);
+      for (auto* r : retired) {
+        active.erase(std::remove(active.begin(), active.end(), r), active.end());
+        used -= r->footprint;
+        r->run.reset();
+      }
+    }
+  }
+}
+
+polfed_status serve_start(polfed_ctx* ctx, size_t budget, int max_cols) {
+  REQUIRE(!ctx->server, "serving already started on this context");
+  REQUIRE(budget > 0, "serve: need a positive HBM budget");
+  REQUIRE(max_cols >= 1, "serve: need max_cols >= 1");
+  auto* s = new Server();
+  s->ctx = ctx;
+  s->budget = budget;
+  s->max_cols = max_cols;
+  ctx->server = s;
+  s->th = std::thread([s] { s->loop(); });
+  return POLFED_OK;
+}
+
+polfed_status serve_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_params* p,
+                           const double* x0, double* evals, double* evecs, double* resid,
+                           polfed_req** out) {
+  REQUIRE(ctx->server, "serve: call polfed_serve_start first");
+  REQUIRE(op && op->ctx == ctx, "serve: operator missing or from another context");
+  REQUIRE(p && x0 && evals && evecs && resid && out, "serve: null argument");
+  REQUIRE(p->n_ev >= 1 && p->n_ev <= op->D, "serve: need 1 <= n_ev <= D");
+  REQUIRE(p->precision == POLFED_FP64 || p->precision == POLFED_FP32, "serve: bad precision");
+  Server* s = ctx->server;
+  const size_t tb = p->precision == POLFED_FP32 ? 4 : 8;
+  const size_t fp = SolveRun::footprint(op, *p) + 4 * (size_t)op->D * tb;
+  if (fp > s->budget)
+    fail(POLFED_ERR_REJECTED, "serve: request needs " + std::to_string(fp) +
+                                  " device bytes, more than the whole budget of " +
+                                  std::to_string(s->budget));
+  auto* r = new polfed_req();
+  r->ctx = ctx;
+  r->op = op;
+  r->p = *p;
+  r->x0 = x0;
+  r->evals = evals;
+  r->evecs = evecs;
+  r->resid = resid;
+  r->footprint = fp;
+  r->t_submit = now_seconds();
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    REQUIRE(!s->stop, "serve: server is stopping");
+    s->pending.push_back(r);
+  }
+  s->cv.notify_all();
+  *out = r;
+  return POLFED_OK;
+}
+
+polfed_status req_poll(polfed_req* r, int* done) {
+  REQUIRE(r && done, "null request");
+  std::lock_guard<std::mutex> lk(r->m);
+  *done = r->done ? 1 : 0;
+  return POLFED_OK;
+}
+
+polfed_status req_wait(polfed_req* r, int* n_found, polfed_report* rep) {
+  REQUIRE(r, "null request");
+  std::unique_lock<std::mutex> lk(r->m);
+  r->cv.wait(lk, [&] { return r->done; });
+  if (n_found) *n_found = r->n_found;
+  if (rep) *rep = r->rep;
+  if (r->status < 0) fail(r->status, r->err);
+  return r->status;
+}
+
+polfed_status req_destroy(polfed_req* r) {
+  if (!r) return POLFED_OK;
+  {
+    std::lock_guard<std::mutex> lk(r->m);
+    if (!r->done) fail(POLFED_ERR_BUSY, "request still running; wait for it first");
+  }
+  delete r;
+  return POLFED_OK;
+}
+
+// Finishes every submitted request, then ends the scheduler thread.
+polfed_status serve_stop(polfed_ctx* ctx) {
+  Server* s = ctx->server;
+  if (!s) return POLFED_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->th.joinable()) s->th.join();
+  ctx->server = nullptr;
+  delete s;
+  return POLFED_OK;
+}
 
 }  // namespace polfed

@@ -1,0 +1,107 @@
+"""GPU tests of the continuous-batching server: every served result matches
+the dense oracle and the same request solved alone, under mixed patterns,
+arrivals while others run, and a tight HBM budget."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense
+from tests.test_gpu_parity import ctx, dev, host, pk, say, tv_case, xxz_case  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def make(pk, ctx, kind, L, W, seed):
+    if kind == "xxz":
+        h, H, _ = xxz_case(L, L // 2, W, seed)
+        return pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, h, True), H
+    eps, H, _ = tv_case(L, L // 2, seed)
+    return pk.Operator.tv(ctx, L, L // 2, 1.0, 1.0, eps, True), H
+
+
+def check(H, n_ev, res):
+    ev, U, R, rep, status = res
+    assert status == "OK"
+    E, Uh, Rh = host(ev), host(U), host(R)
+    Er, Ur = dense.nearest_eigenpairs(H, rep["lambda"], n_ev)
+    rel = np.abs(E - Er) / np.maximum(np.abs(Er), 1.0)
+    assert rel.max() <= 1e-10
+    assert Rh.max() <= 1e-8
+    assert np.linalg.norm(H @ Uh - Uh * E, axis=0).max() <= 1e-8
+    assert np.abs(np.sum(Uh * Ur, axis=0)).min() >= 1 - 1e-8
+    return E
+
+
+MIX = [("xxz", 12, 1.0, 0), ("xxz", 12, 3.0, 1), ("xxz", 14, 5.0, 2), ("tv", 12, 0, 3),
+       ("xxz", 12, 5.0, 4), ("xxz", 14, 1.0, 5), ("xxz", 10, 3.0, 6), ("xxz", 12, 3.0, 7)]
+
+
+def test_serve_mixed_stream_matches_dense_and_alone(pk, ctx):
+    say("serve mixed stream")
+    n_ev = 20
+    cases = [make(pk, ctx, *m) for m in MIX]
+    x0s = [dev(wl.start_vector(op.D, 40 + i)) for i, (op, _) in enumerate(cases)]
+    with pk.Server(ctx, 8 << 30, max_cols=4) as srv:
+        reqs = []
+        for i, (op, _) in enumerate(cases):
+            reqs.append(srv.submit(op, x0s[i], n_ev, 0.5, "normalized"))
+            time.sleep(0.01 * (i % 3))  # staggered arrivals join running batches
+        results = [r.wait() for r in reqs]
+    for i, (op, H) in enumerate(cases):
+        E = check(H, n_ev, results[i])
+        say(f"   req {i} {MIX[i]}: latency {results[i][3]['t_latency']:.3f}s "
+            f"queue {results[i][3]['t_queue']:.3f}s iters {results[i][3]['iters']}")
+        ev1, _, _, rep1, st = pk.solve(op, x0s[i], n_ev, 0.5, "normalized")
+        assert st == "OK"
+        assert abs(rep1["lambda"] - results[i][3]["lambda"]) <= 1e-12 * max(1.0, abs(rep1["lambda"]))
+        assert np.max(np.abs(host(ev1) - E) / np.maximum(np.abs(E), 1.0)) <= 1e-10
+
+
+def test_serve_admission_under_tight_budget(pk, ctx):
+    """A budget that holds about two L=14 solves: later arrivals wait in the
+    queue and are admitted as earlier ones finish; all results are right."""
+    say("serve tight budget")
+    n_ev = 20
+    cases = [make(pk, ctx, "xxz", 14, W, s) for s, W in enumerate((1.0, 3.0, 5.0, 3.0, 1.0))]
+    # footprint: (M + 2) basis vectors, 4 n_want extraction vectors, 3 work
+    # vectors and 4 filter vectors, M = ceil((20.427 + 1.696 n_want) 1.5)
+    D = cases[0][0].D
+    n_want = n_ev + 10
+    M = int(np.ceil((20.427 + 1.696 * n_want) * 1.5))
+    budget = int(2.5 * D * 8 * (M + 2 + 4 * n_want + 3 + 4))
+    x0s = [dev(wl.start_vector(D, s)) for s in range(len(cases))]
+    with pk.Server(ctx, budget, max_cols=8) as srv:
+        reqs = [srv.submit(op, x0s[i], n_ev, 0.5, "normalized") for i, (op, _) in enumerate(cases)]
+        results = [r.wait() for r in reqs]
+    for i, (op, H) in enumerate(cases):
+        check(H, n_ev, results[i])
+    # the third request (submitted right after the first two) could only be
+    # admitted once one of them had finished
+    first = min(results[0][3]["t_latency"], results[1][3]["t_latency"])
+    assert results[2][3]["t_queue"] >= 0.5 * first
+
+
+def test_serve_rejects_request_over_budget(pk, ctx):
+    say("serve reject")
+    op, _ = make(pk, ctx, "xxz", 14, 1.0, 0)
+    with pk.Server(ctx, 1 << 20, max_cols=4) as srv:
+        with pytest.raises(pk.PolfedError) as e:
+            srv.submit(op, dev(wl.start_vector(op.D, 0)), 20, 0.5)
+        assert e.value.code == -8
+
+
+def test_serve_invalid_request_and_stop_with_pending(pk, ctx):
+    say("serve invalid + stop")
+    op, H = make(pk, ctx, "xxz", 10, 3.0, 1)
+    srv = pk.Server(ctx, 4 << 30, max_cols=2)
+    with pytest.raises(pk.PolfedError):
+        srv.submit(op, dev(wl.start_vector(op.D, 0)), op.D + 1, 0.5)
+    reqs = [srv.submit(op, dev(wl.start_vector(op.D, s)), 10, 0.5) for s in range(4)]
+    srv.stop()  # finishes everything submitted
+    for r in reqs:
+        assert r.poll()
+        check(H, 10, r.wait())
