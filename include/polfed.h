@@ -191,6 +191,15 @@ polfed_status polfed_filter_coefficients(double lambda_t, int K, double* a);
 polfed_status polfed_filter_value(double lambda_t, int K, const double* x,
                                   int64_t n, double* out);
 
+/* Divided difference of the Chebyshev series p = sum_{n<=K} a_n T_n at theta:
+ * q[0..K-1] are the Chebyshev coefficients of (p(x) - p(theta)) / (x - theta)
+ * and *p_theta = p(theta) (may be NULL).  Used by the FP32 refinement, where
+ * P(H~) u = P(theta) u + Q(H~) (H~ - theta) u moves only the small residual
+ * through the low-precision recurrence.  Host arrays; K >= 0 (q unused for
+ * K = 0). */
+polfed_status polfed_filter_quotient(const double* a, int K, double theta,
+                                     double* q, double* p_theta);
+
 /* ------------------------------------------------------- filter (device) */
 
 /* w = P(H~) v by the Clenshaw recurrence, eq. clenshaw_chebyshev_prod, with
@@ -257,10 +266,11 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
                                   double E_c, double dE, const double* a,
                                   int K, double* V, int k, double* alpha,
                                   double* beta, int precision);
-/* Measurement helper: runs `iters` back-to-back launches of the fused
- * Clenshaw step kernel on scratch vectors with HIP events around each
- * launch, and returns the mean and minimum kernel time in milliseconds
- * (host results; synchronizes). */
+/* Measurement helper: times `iters` back-to-back launches of the fused
+ * Clenshaw step kernel on scratch vectors with one pair of HIP events on the
+ * context stream (mean = elapsed / iters, the rate of a running recurrence)
+ * and up to 20 single launches each between its own event pair (minimum).
+ * Milliseconds, host results; synchronizes. */
 polfed_status polfed_profile_step(polfed_ctx* ctx, const polfed_op* op,
                                   int precision, int iters, double* avg_ms,
                                   double* min_ms);

@@ -101,6 +101,7 @@ SIGNATURES = {
                          ctypes.POINTER(Plan)],
     "polfed_filter_coefficients": [_D, _I, _DP],
     "polfed_filter_value": [_D, _I, _DP, _I64, _DP],
+    "polfed_filter_quotient": [_DP, _I, _D, _DP, _DP],
     "polfed_filter_apply": [_P, _P, _D, _D, _DP, _I, _P, _P, _I],
     "polfed_clenshaw_step": [_P, _P, _D, _D, _D, _P, _P, _P, _I, _I],
     "polfed_filter_apply_batch": [_P, _I, ctypes.POINTER(_P), _DP, _DP,
@@ -201,6 +202,17 @@ def filter_value(lambda_t: float, K: int, x) -> np.ndarray:
     out = np.empty_like(x)
     _check(lib.polfed_filter_value(lambda_t, K, _dptr(x), x.size, _dptr(out)))
     return out
+
+
+def filter_quotient(a, theta: float):
+    """(q, p(theta)): Chebyshev coefficients of (p(x) - p(theta)) / (x - theta)
+    for p = sum a_n T_n."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    K = len(a) - 1
+    q = np.zeros(max(K, 1))
+    p = ctypes.c_double()
+    _check(_lib.polfed_filter_quotient(_dptr(a), K, float(theta), _dptr(q), ctypes.byref(p)))
+    return q[:K], p.value
 
 
 def default_params() -> Params:

@@ -78,9 +78,18 @@ template void filter_apply_batch<double>(polfed_ctx*, const ChainBatch&, const B
 template void filter_apply_batch<float>(polfed_ctx*, const ChainBatch&, const BatchCoef&,
                                         const float*, float*, float*, float*);
 
+bool BatchFilter::same_members(const std::vector<SolveRun*>& runs) const {
+  if (runs.size() != ids.size()) return false;
+  for (size_t i = 0; i < runs.size(); ++i)
+    if (runs[i] != members[i] || runs[i]->uid != ids[i]) return false;
+  return true;
+}
+
 void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
   ctx = c;
   members = runs;
+  ids.clear();
+  for (auto* r : runs) ids.push_back(r->uid);
   const int nb = (int)runs.size();
   std::vector<const polfed_op*> ops(nb);
   std::vector<double> Ec(nb), dE(nb);
@@ -171,18 +180,14 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
     runs.back()->setup(ctx, ops[i], p, x0[i], evals[i], evecs[i], resid[i], &n_found[i]);
   }
   BatchFilter bf;
-  std::vector<SolveRun*> active;
   for (;;) {
     std::vector<SolveRun*> now;
     for (auto& r : runs)
       if (!r->done) now.push_back(r.get());
     if (now.empty()) break;
-    if (now != active) {
-      bf.form(ctx, now);
-      active = now;
-    }
+    if (!bf.same_members(now)) bf.form(ctx, now);
     bf.run();
-    for (auto* r : active) r->advance();
+    for (auto* r : now) r->advance();
   }
   polfed_status st = POLFED_OK;
   for (int i = 0; i < B; ++i) {

@@ -407,6 +407,16 @@ polfed_status polfed_filter_coefficients(double lambda_t, int K, double* a) {
   });
 }
 
+polfed_status polfed_filter_quotient(const double* a, int K, double theta, double* q,
+                                     double* p_theta) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(K >= 0 && a && (K == 0 || q), "need K >= 0, a[K+1] and q[K]");
+    REQUIRE(std::isfinite(theta), "theta must be finite");
+    filter_quotient(a, K, theta, q, p_theta);
+    return POLFED_OK;
+  });
+}
+
 polfed_status polfed_filter_value(double lambda_t, int K, const double* x, int64_t n,
                                   double* out) {
   return guarded([&]() -> polfed_status {

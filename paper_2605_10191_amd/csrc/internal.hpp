@@ -294,6 +294,7 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
 // ---------------------------------------------------------------- plan ----
 double filter_value_closed(double lambda_t, int K, double x);
 void filter_coefficients(double lambda_t, int K, double* a);
+void filter_quotient(const double* a, int K, double theta, double* q, double* p_theta);
 polfed_plan make_plan(int64_t D, double E_min, double E_max, double pad,
                       double lambda, double tr1, double tr2, int n_window,
                       double omega, int K_override);

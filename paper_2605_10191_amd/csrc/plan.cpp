@@ -39,6 +39,28 @@ void filter_coefficients(double lambda_t, int K, double* a) {
   for (int n = 1; n <= K; ++n) a[n] = 2.0 * std::cos(n * phi) / chi;
 }
 
+// Divided difference of a Chebyshev series p(x) = sum_{n=0}^{K} a_n T_n(x)
+// at theta: Q(x) = (p(x) - p(theta)) / (x - theta), a polynomial of degree
+// K - 1.  With the Clenshaw intermediates at theta,
+//   b_{K+1} = b_{K+2} = 0,  b_k = a_k + 2 theta b_{k+1} - b_{k+2},
+// one has b_k = sum_{n >= k} a_n U_{n-k}(theta), and expanding
+// (T_n(x) - T_n(theta)) / (x - theta) in U_k(x) with T-valued weights, then
+// U_k in T_j, telescopes to
+//   Q(x) = b_1 T_0(x) + 2 sum_{j=1}^{K-1} b_{j+1} T_j(x),
+// while p(theta) = a_0 + theta b_1 - b_2.  q receives K coefficients
+// (none for K = 0, where Q = 0).
+void filter_quotient(const double* a, int K, double theta, double* q, double* p_theta) {
+  double b1 = 0.0, b2 = 0.0;  // b_{k+1}, b_{k+2}
+  for (int k = K; k >= 1; --k) {
+    const double bk = a[k] + 2.0 * theta * b1 - b2;
+    b2 = b1;
+    b1 = bk;
+    if (k >= 2) q[k - 1] = 2.0 * bk;  // q_{k-1} = 2 b_k
+    else if (K >= 1) q[0] = bk;       // q_0 = b_1
+  }
+  if (p_theta) *p_theta = a[0] + theta * b1 - b2;
+}
+
 static bool meets_cutoff(int K, double lt, double delta, double omega) {
   const double lo = filter_value_closed(lt, K, lt - delta);
   const double hi = filter_value_closed(lt, K, lt + delta);

@@ -57,7 +57,6 @@ struct Server {
   bool stop = false;
   std::thread th;
   struct Group {
-    std::vector<SolveRun*> members;
     BatchFilter bf;
   };
   std::map<std::string, Group> groups;
@@ -148,10 +147,9 @@ void Server::loop() {
         if (runs.size() == 1 && kv.first.rfind("op:", 0) == 0) {
           runs[0]->filter_self();
         } else {
-          if (runs != g.members) {
-            g.bf.form(ctx, runs);
-            g.members = runs;
-          }
+          // rebuilt whenever a member joined or left (a new solve may reuse
+          // a finished one's address, so members are compared by uid)
+          if (!g.bf.same_members(runs)) g.bf.form(ctx, runs);
           g.bf.run();
         }
       } catch (const Error& e) {

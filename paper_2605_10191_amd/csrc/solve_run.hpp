@@ -63,6 +63,21 @@ struct Ws {
   }
 };
 
+// Ritz pairs of H on a subspace: U2 (D x n, orthonormal), HU2 = H U2, E,
+// residual norms, and the selection made from them.
+struct Extracted {
+  std::vector<double> E, res;
+  std::vector<int> sel;  // chosen columns of U2, ordered by (|E - lambda|, E)
+  bool complete = false;
+  DevBuf U2, HU2;
+};
+
+// Rayleigh-Ritz of H on span(U) (U orthonormal D x n, HU = H U).
+void rayleigh_ritz(hipStream_t s, int64_t D, int n, const double* U, const double* HU,
+                   int64_t nseg, Extracted& ex);
+void select_pairs(Extracted& ex, double lam, int n_ev, double tol_resid, double theta_min,
+                  const polfed_plan& pl);
+
 struct SolveRun {
   // inputs
   polfed_ctx* ctx = nullptr;
@@ -85,6 +100,7 @@ struct SolveRun {
   polfed_report R{};
   polfed_status status = POLFED_NOT_CONVERGED;
   bool done = false;
+  uint64_t uid = 0;  // unique per setup(), identifies the solve in a batch
   std::vector<std::pair<hipEvent_t, hipEvent_t>> fev, rev;
 
   SolveRun() = default;
@@ -104,6 +120,10 @@ struct SolveRun {
   void drain();
 };
 
+// FP64-accurate refinement of the Ritz pairs of an FP32-filtered run (ex is
+// updated in place, selection included).
+void refine(SolveRun& run, Extracted& ex, double theta_min);
+
 // Device coefficient table [(Kmax + 1)][nb] of a multi-column filter; column
 // c is zero above its own order K[c].
 struct BatchCoef {
@@ -120,6 +140,9 @@ void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& 
 struct BatchFilter {
   polfed_ctx* ctx = nullptr;
   std::vector<SolveRun*> members;
+  std::vector<uint64_t> ids;  // uid of each member when the batch was formed
+  // true when runs are exactly the members the tables were built for
+  bool same_members(const std::vector<SolveRun*>& runs) const;
   bool fp32 = false;
   ChainBatch bt;
   BatchCoef co;

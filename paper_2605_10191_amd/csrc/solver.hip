@@ -8,6 +8,7 @@
 // coefficients (copied at the periodic checks) and the small projected
 // matrices of the extraction.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <numeric>
@@ -196,51 +197,48 @@ double target_energy(int kind, double target, double E_min, double E_max) {
   fail(POLFED_ERR_INVALID, "unknown target kind");
 }
 
-struct Extracted {
-  std::vector<double> E, res;
-  std::vector<int> sel;  // chosen columns of U2, ordered by (|E - lam|, E)
-  bool complete = false;
-  DevBuf U2;             // D x n
-};
+}  // namespace
 
-// u = V t for the selected Ritz vectors, Rayleigh-Ritz with H on their span,
-// residual norms, choice of the n_ev nearest accepted pairs and the check
-// that no nearer eigenvalue can be missing.
-Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, int m,
-                  const std::vector<double>& Ysel /* m x n col-major */, int n,
-                  double theta_min, double lam, int n_ev, double tol_resid,
-                  const polfed_plan& pl) {
-  hipStream_t s = ctx->stream;
-  const int64_t D = op->D;
-  Extracted ex;
-  DevBuf dY((size_t)m * n * sizeof(double));
-  dcopy_async(s, dY.as<double>(), Ysel.data(), (size_t)m * n, hipMemcpyHostToDevice);
-  DevBuf U((size_t)D * n * sizeof(double)), HU((size_t)D * n * sizeof(double));
-  dev_gemm_nn(s, D, m, n, B.V.as<double>(), D, dY.as<double>(), U.as<double>(), D);
-  for (int j = 0; j < n; ++j) apply_H(s, op, U.as<double>() + (size_t)j * D, HU.as<double>() + (size_t)j * D);
+void rayleigh_ritz(hipStream_t s, int64_t D, int n, const double* U, const double* HU,
+                   int64_t nseg, Extracted& ex) {
   DevBuf dG((size_t)n * n * sizeof(double));
-  DevBuf part((size_t)ws.nseg * n * sizeof(double) + 8192 * sizeof(double));
-  dev_gemm_tn(s, D, n, U.as<double>(), HU.as<double>(), part.as<double>(), ws.nseg,
-              dG.as<double>());
+  DevBuf part((size_t)nseg * n * sizeof(double) + 8192 * sizeof(double));
+  dev_gemm_tn(s, D, n, U, HU, part.as<double>(), nseg, dG.as<double>());
   std::vector<double> G((size_t)n * n);
   dcopy_async(s, G.data(), dG.as<double>(), G.size(), hipMemcpyDeviceToHost);
   HIPC(hipStreamSynchronize(s));
+  // symmetrize: G is symmetric up to rounding
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double m = 0.5 * (G[(size_t)i * n + j] + G[(size_t)j * n + i]);
+      G[(size_t)i * n + j] = G[(size_t)j * n + i] = m;
+    }
   std::vector<double> w, Z;
   sym_eig(n, G, w, Z);
   DevBuf dZ((size_t)n * n * sizeof(double)), dE((size_t)n * sizeof(double)),
       dR((size_t)n * sizeof(double));
   dcopy_async(s, dZ.as<double>(), Z.data(), Z.size(), hipMemcpyHostToDevice);
   dcopy_async(s, dE.as<double>(), w.data(), w.size(), hipMemcpyHostToDevice);
-  ex.U2.alloc((size_t)D * n * sizeof(double));
-  DevBuf HU2((size_t)D * n * sizeof(double));
-  dev_gemm_nn(s, D, n, n, U.as<double>(), D, dZ.as<double>(), ex.U2.as<double>(), D);
-  dev_gemm_nn(s, D, n, n, HU.as<double>(), D, dZ.as<double>(), HU2.as<double>(), D);
-  dev_resid(s, D, n, ex.U2.as<double>(), HU2.as<double>(), dE.as<double>(), part.as<double>(),
-            ws.nseg, dR.as<double>());
+  DevBuf U2((size_t)D * n * sizeof(double)), HU2((size_t)D * n * sizeof(double));
+  dev_gemm_nn(s, D, n, n, U, D, dZ.as<double>(), U2.as<double>(), D);
+  dev_gemm_nn(s, D, n, n, HU, D, dZ.as<double>(), HU2.as<double>(), D);
+  dev_resid(s, D, n, U2.as<double>(), HU2.as<double>(), dE.as<double>(), part.as<double>(),
+            nseg, dR.as<double>());
   ex.res.resize(n);
   dcopy_async(s, ex.res.data(), dR.as<double>(), (size_t)n, hipMemcpyDeviceToHost);
   HIPC(hipStreamSynchronize(s));
   ex.E = w;
+  ex.U2 = std::move(U2);
+  ex.HU2 = std::move(HU2);
+}
+
+// The n_ev accepted pairs nearest lambda, ordered by (|E - lambda|, E), and
+// the check that no nearer eigenvalue can be missing: the filter at the
+// farthest selected energy must not fall below the smallest converged
+// P-Ritz value theta_min.
+void select_pairs(Extracted& ex, double lam, int n_ev, double tol_resid, double theta_min,
+                  const polfed_plan& pl) {
+  const int n = (int)ex.E.size();
   std::vector<int> ok;
   for (int j = 0; j < n; ++j)
     if (ex.res[j] <= tol_resid) ok.push_back(j);
@@ -251,6 +249,7 @@ Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, 
   });
   if ((int)ok.size() > n_ev) ok.resize(n_ev);
   ex.sel = ok;
+  ex.complete = false;
   if ((int)ok.size() == n_ev && n_ev > 0) {
     double d = 0;
     for (int j : ok) d = std::max(d, std::fabs(ex.E[j] - lam));
@@ -259,6 +258,23 @@ Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, 
     const double pp = filter_value_closed(pl.lambda_t, pl.K, pl.lambda_t + d);
     ex.complete = std::min(pm, pp) >= theta_min;
   }
+}
+
+namespace {
+
+// u = V t for the selected Ritz vectors, Rayleigh-Ritz with H on their span
+// and residual norms.
+Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, int m,
+                  const std::vector<double>& Ysel /* m x n col-major */, int n) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  Extracted ex;
+  DevBuf dY((size_t)m * n * sizeof(double));
+  dcopy_async(s, dY.as<double>(), Ysel.data(), (size_t)m * n, hipMemcpyHostToDevice);
+  DevBuf U((size_t)D * n * sizeof(double)), HU((size_t)D * n * sizeof(double));
+  dev_gemm_nn(s, D, m, n, B.V.as<double>(), D, dY.as<double>(), U.as<double>(), D);
+  for (int j = 0; j < n; ++j) apply_H(s, op, U.as<double>() + (size_t)j * D, HU.as<double>() + (size_t)j * D);
+  rayleigh_ritz(s, D, n, U.as<double>(), HU.as<double>(), ws.nseg, ex);
   return ex;
 }
 
@@ -290,8 +306,11 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   REQUIRE(p.n_ev >= 1 && p.n_ev <= D, "solve: need 1 <= n_ev <= D");
   REQUIRE(p.precision == POLFED_FP64 || p.precision == POLFED_FP32, "solve: bad precision");
   REQUIRE(x0 && evals && evecs && resid && n_found, "solve: null buffer");
+  static std::atomic<uint64_t> next_uid{1};
+  uid = next_uid.fetch_add(1);
   fp32 = p.precision == POLFED_FP32;
   tol_resid = p.tol_resid > 0 ? p.tol_resid : 1e-8;
+  tol_ritz = 1e-10;
   const double pad = p.bound_pad > 0 ? p.bound_pad : 1e-3;
   const double eta = p.eta > 0 ? p.eta : 1.5;
   R = polfed_report{};
@@ -321,6 +340,10 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega, p.K_override);
   a.assign(pl.K + 1, 0.0);
   filter_coefficients(pl.lambda_t, pl.K, a.data());
+  // An FP32 recurrence carries a relative error of a few times sqrt(K) unit
+  // roundoffs; the Lanczos check stops at ten times that level and the
+  // refinement takes the pairs the rest of the way.
+  if (fp32) tol_ritz = std::max(1e-10, 10.0 * 4.0 * std::sqrt((double)pl.K) * 6e-8);
   R.t_plan = now_seconds() - t0;
   R.lambda = lam;
   R.lambda_t = pl.lambda_t;
@@ -487,8 +510,14 @@ void SolveRun::advance() {
     for (int j = 0; j < nw; ++j)
       for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
     const double theta_min = thf[ord[nw - 1]];
-    Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw, theta_min, lam, p.n_ev, tol_resid, pl);
+    Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw);
+    select_pairs(ex, lam, p.n_ev, tol_resid, theta_min, pl);
     R.t_extract += now_seconds() - tx;
+    if (fp32 && !((int)ex.sel.size() == p.n_ev && ex.complete)) {
+      const double tr = now_seconds();
+      refine(*this, ex, theta_min);
+      R.t_refine += now_seconds() - tr;
+    }
     const bool ok = (int)ex.sel.size() == p.n_ev && ex.complete;
     if (ok || k >= M_max) {
       const int nf = (int)ex.sel.size();
@@ -596,28 +625,40 @@ void profile_step(polfed_ctx* ctx, const polfed_op* op, int precision, int iters
     }
     HIPC(hipStreamSynchronize(s));
   }
-  std::vector<hipEvent_t> ev(2 * (size_t)iters);
-  for (auto& e : ev) HIPC(hipEventCreate(&e));
   const double sigma = 0.1, tau = -0.01, a = 1e-3;
-  for (int i = 0; i < iters; ++i) {
-    HIPC(hipEventRecord(ev[2 * i], s));
+  auto launch = [&]() {
     if (precision == POLFED_FP32)
       op_step<float>(s, op, (float)sigma, (float)tau, (float)a, v.as<float>(), b1.as<float>(),
                      b2.as<float>(), b2.as<float>());
     else
       op_step<double>(s, op, sigma, tau, a, v.as<double>(), b1.as<double>(), b2.as<double>(),
                       b2.as<double>());
-    HIPC(hipEventRecord(ev[2 * i + 1], s));
-  }
-  HIPC(hipStreamSynchronize(s));
-  double sum = 0, mn = 1e300;
-  for (int i = 0; i < iters; ++i) {
+  };
+  // mean: one event pair around iters back-to-back launches, as the
+  // recurrence runs them; min: event pairs around single launches
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  launch();
+  HIPC(hipEventRecord(e0, s));
+  for (int i = 0; i < iters; ++i) launch();
+  HIPC(hipEventRecord(e1, s));
+  HIPC(hipEventSynchronize(e1));
+  float total = 0;
+  HIPC(hipEventElapsedTime(&total, e0, e1));
+  double mn = 1e300;
+  for (int i = 0; i < std::min(iters, 20); ++i) {
+    HIPC(hipEventRecord(e0, s));
+    launch();
+    HIPC(hipEventRecord(e1, s));
+    HIPC(hipEventSynchronize(e1));
     float ms = 0;
-    HIPC(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
-    sum += ms;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
     mn = std::min(mn, (double)ms);
   }
-  for (auto& e : ev) HIPC(hipEventDestroy(e));
+  HIPC(hipEventDestroy(e0));
+  HIPC(hipEventDestroy(e1));
+  const double sum = total;
   *avg_ms = iters ? sum / iters : 0;
   *min_ms = iters ? mn : 0;
 }

@@ -128,3 +128,28 @@ def _lib_plan(pk, lam_t, delta):
     p = pk.make_plan(1, -1.0, 1.0, 0.0, lam_t, tr1, tr2, 1)
     assert abs(p.delta - delta) < 1e-9 * delta
     return p
+
+
+@pytest.mark.parametrize("K,theta", [(1, 0.3), (2, -0.7), (3, 0.11), (60, 0.25),
+                                     (281, -0.4), (1500, 0.02)])
+def test_filter_quotient_is_the_divided_difference(pk, K, theta):
+    """Q(x) (x - theta) = p(x) - p(theta), checked with NumPy's Chebyshev
+    series at points away from theta, and Q(theta) = p'(theta)."""
+    from numpy.polynomial import chebyshev as C
+    rng = np.random.default_rng(K)
+    a = rng.standard_normal(K + 1) / (K + 1)
+    q, p_th = pk.filter_quotient(a, theta)
+    assert q.shape == (K,)
+    assert abs(p_th - C.chebval(theta, a)) <= 1e-13
+    x = rng.uniform(-1, 1, 200)
+    x = x[np.abs(x - theta) > 0.05]
+    lhs = C.chebval(x, q) * (x - theta)
+    rhs = C.chebval(x, a) - C.chebval(theta, a)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * max(1.0, np.max(np.abs(rhs))) * K
+    deriv = C.chebval(theta, C.chebder(a))
+    assert abs(C.chebval(theta, q) - deriv) <= 1e-11 * max(1.0, abs(deriv)) * K
+
+
+def test_filter_quotient_order_zero(pk):
+    q, p_th = pk.filter_quotient([0.7], 0.2)
+    assert q.shape == (0,) and p_th == 0.7
