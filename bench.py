@@ -20,7 +20,15 @@ Beside it the JSON line carries
                 8 TB/s HBM peak; traffic = HBM bytes per launch from the
                 rocprofv3 counters recorded in profiles/, when they were taken
                 on the current kernel source;
-  eigenpairs_per_s  a complete solve of the XXZ L=20 workload (100 pairs);
+  kernels       the same step kernel in FP32, as CSR SpMV, and as the
+                multi-column kernel over 8 realizations (a working set of
+                692 MB per step, larger than the 256 MB last-level cache);
+  eigenpairs_per_s  complete solves of the XXZ L=20 workload (100 pairs),
+                plain FP64 and FP32 bulk + FP64 refinement, with the FP32
+                result's error per eigenpair against the FP64 one;
+  serving       a Poisson stream of XXZ requests (L in 14, 16, 18; W in 1,
+                3, 5; 50 pairs each) through the continuous-batching server:
+                p50 / p99 latency and throughput;
   cpu_baseline  the CPU oracle's Clenshaw steps at L=24 on a bounded sample.
 """
 from __future__ import annotations
@@ -32,6 +40,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -101,6 +111,142 @@ def cpu_baseline(L: int, W: float, seed: int, steps: int):
             "ms_per_clenshaw_step": round(1e3 * dt / steps, 3)}
 
 
+def kernel_legs(pk, wl, ctx, L, W, iters):
+    """Step-kernel rates beside the headline: FP32, CSR storage and the
+    multi-column kernel on 8 realizations sharing the pattern."""
+    import torch
+    out = {}
+    h = wl.xxz_fields(L, W, 0)
+    op = pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, h, True)
+    D = op.D
+    avg, mn = pk.profile_step(op, pk.FP32, iters)
+    out["fp32_matrix_free"] = {"GBps": round(4 * 4 * D / (avg * 1e-3) / 1e9, 1),
+                               "us": round(avg * 1e3, 2), "bytes": 4 * 4 * D}
+    # multi-column FP64: 8 realizations, K Clenshaw steps of the batched filter
+    B, Kb = 8, 200
+    ops = [pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, wl.xxz_fields(L, W, c), True)
+           for c in range(B)]
+    v = torch.rand((B, D), dtype=torch.float64, device=ctx.torch_device)
+    a = [np.full(Kb + 1, 1e-3) for _ in range(B)]
+    pk.filter_apply_batch(ops, [0.0] * B, [25.0] * B, [x[:3] for x in a], v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk.filter_apply_batch(ops, [0.0] * B, [25.0] * B, a, v)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / Kb
+    out["fp64_batched_8"] = {"GBps": round(4 * 8 * D * B / dt / 1e9, 1),
+                             "us_per_step": round(dt * 1e6, 2), "bytes": 4 * 8 * D * B,
+                             "note": f"{Kb} steps of the 8-column filter, host-timed"}
+    del ops, v
+    # CSR storage of the same operator
+    op.materialize_csr().set_storage(pk.CSR)
+    nnz = op.nnz
+    avg, mn = pk.profile_step(op, pk.FP64, max(20, iters // 4))
+    csr_bytes = 4 * 8 * D + nnz * 12 + 8 * (D + 1) + 8 * D
+    out["fp64_csr"] = {"GBps": round(csr_bytes / (avg * 1e-3) / 1e9, 1),
+                       "us": round(avg * 1e3, 2), "bytes": csr_bytes, "nnz": nnz,
+                       "note": "algorithmic bytes: vectors + nnz (8 B value, 4 B column) "
+                               "+ row pointers + diagonal"}
+    op.close()
+    return out
+
+
+def solve_legs(pk, wl, ctx, L, n_ev):
+    """Full solves of the XXZ workload in FP64 and FP32 bulk + FP64 refinement."""
+    import torch
+    res = {}
+    op, x0, (_, _, lam, _, _) = xxz_setup(pk, wl, ctx, L, 3.0, 0, n_ev)
+    runs = {}
+    for name, prec in (("fp64", pk.FP64), ("fp32_bulk", pk.FP32)):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ev, U, r, rep, status = pk.solve(op, x0, n_ev, lam, "absolute", precision=prec,
+                                         allow_partial=True)
+        torch.cuda.synchronize()
+        tsolve = time.perf_counter() - ts
+        runs[name] = ev.cpu().numpy()
+        res[name] = {"eigenpairs_per_s": round(len(runs[name]) / tsolve, 3) if status == "OK" else None,
+                     "solve_s": round(tsolve, 2), "status": status, "K": rep["K"],
+                     "iters": rep["iters"], "max_resid": float(r.max().item()) if len(r) else None,
+                     "refine_sweeps": rep["refine_sweeps"],
+                     "filter_GBps": round(rep["filter_GBps"], 1),
+                     "t_filter": round(rep["t_filter"], 2), "t_reorth": round(rep["t_reorth"], 2),
+                     "t_refine": round(rep["t_refine"], 2)}
+        log(f"solve L={L} {name}: {tsolve:.1f}s status={status} K={rep['K']} "
+            f"iters={rep['iters']} sweeps={rep['refine_sweeps']} t_filter={rep['t_filter']:.1f} "
+            f"t_reorth={rep['t_reorth']:.1f} t_refine={rep['t_refine']:.1f} "
+            f"t_check={rep['t_check']:.1f} t_extract={rep['t_extract']:.1f}")
+    e64, e32 = runs["fp64"], runs["fp32_bulk"]
+    if len(e64) == len(e32) == n_ev:
+        err = np.abs(np.sort(e32) - np.sort(e64)) / np.maximum(np.abs(np.sort(e64)), 1.0)
+        res["fp32_vs_fp64_rel_err"] = {"max": float(err.max()), "median": float(np.median(err)),
+                                       "per_pair": [float(x) for x in err]}
+    res["workload"] = (f"XXZ L={L} W=3 seed 0 (D={op.D}), {n_ev} pairs at normalized "
+                       "energy 0.5, full solve")
+    return res
+
+
+def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7):
+    """A Poisson stream through the server; arrival rate = measured
+    single-stream capacity (mean service time of one request per L)."""
+    import torch
+    n_ev = 50
+
+    def make(L, W, sd):
+        op = pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, wl.xxz_fields(L, W, sd), True)
+        x0 = torch.tensor(wl.start_vector(op.D, sd), device=ctx.torch_device)
+        return op, x0
+
+    # single-stream capacity: one request per chain length, solved alone
+    svc = []
+    for L in (14, 16, 18):
+        op, x0 = make(L, 3.0, 999)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, rep, st = pk.solve(op, x0, n_ev, 0.5, "normalized", precision=precision,
+                                    allow_partial=True)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+        log(f"serving capacity: L={L} alone {svc[-1]:.2f}s {st} K={rep['K']} iters={rep['iters']}")
+    mean_svc = float(np.mean(svc))
+    stream = wl.serving_stream(n_req, seed, mean_svc)
+    reqs = []
+    with pk.Server(ctx, int(budget_gb * (1 << 30)), max_cols=max_cols) as srv:
+        t_start = time.perf_counter()
+        for r in stream:
+            now = time.perf_counter() - t_start
+            if r["t_arrive"] > now:
+                time.sleep(r["t_arrive"] - now)
+            op, x0 = make(r["L"], r["W"], r["seed"])
+            reqs.append((r, op, srv.submit(op, x0, n_ev, 0.5, "normalized", precision=precision)))
+            log(f"serving: submitted request {len(reqs) - 1} L={r['L']} W={r['W']} "
+                f"at {time.perf_counter() - t_start:.2f}s")
+        left = set(range(len(reqs)))
+        while left:
+            for i in sorted(left):
+                if reqs[i][2].poll():
+                    left.discard(i)
+                    rp = reqs[i][2].wait(allow_partial=True)[3]
+                    log(f"serving: request {i} L={reqs[i][0]['L']} done, latency "
+                        f"{rp['t_latency']:.2f}s queue {rp['t_queue']:.2f}s ({len(left)} left)")
+            time.sleep(0.05)
+        results = [q.wait(allow_partial=True) for _, _, q in reqs]
+        t_end = time.perf_counter()
+    lat = np.array([res[3]["t_latency"] for res in results])
+    ok = sum(res[4] == "OK" for res in results)
+    return {"requests": n_req, "ok": int(ok), "n_ev": n_ev,
+            "precision": "fp32_bulk+fp64_refine" if precision == pk.FP32 else "fp64",
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 1),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 1),
+            "mean_ms": round(1e3 * float(lat.mean()), 1),
+            "throughput_req_per_s": round(n_req / (t_end - t_start), 3),
+            "single_stream_service_s": [round(x, 3) for x in svc],
+            "arrival_rate_per_s": round(1.0 / mean_svc, 3),
+            "hbm_budget_GiB": budget_gb, "max_cols": max_cols,
+            "stream": "L in {14,16,18}, W in {1,3,5} uniform, Poisson arrivals at the "
+                      "single-stream capacity"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +260,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--profile-iters", type=int, default=300)
+    ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0)
+    ap.add_argument("--serve-cols", type=int, default=16)
+    ap.add_argument("--serve-fp64", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the step kernel and a plain copy (counter runs)")
     args = ap.parse_args()
@@ -219,25 +371,21 @@ def main():
                       "K": K, "D": D, "hbm_frac": round(value / HBM_PEAK_GBS, 4)},
            "roofline": roofline}
 
+    if not args.no_kernels:
+        out["kernels"] = kernel_legs(pk, wl, ctx, args.L, args.W, args.profile_iters)
+        log(f"kernel legs: {out['kernels']}")
     if not args.no_solve:
-        opS, x0S, (_, _, lamS, _, _) = xxz_setup(pk, wl, ctx, args.solve_L, 3.0, 0,
-                                                 args.n_ev)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        ev, U, res, rep, status = pk.solve(opS, x0S, args.n_ev, lamS, "absolute")
-        torch.cuda.synchronize()
-        tsolve = time.perf_counter() - ts
-        out["eigenpairs_per_s"] = {
-            "value": round(args.n_ev / tsolve, 3) if status == "OK" else None,
-            "unit": "eigenpairs/s",
-            "workload": f"XXZ L={args.solve_L} W=3 seed 0 (D={opS.D}), "
-                        f"{args.n_ev} pairs at normalized energy 0.5, FP64, full solve",
-            "solve_s": round(tsolve, 2), "status": status, "K": rep["K"],
-            "iters": rep["iters"], "max_resid": float(res.max().item()),
-            "filter_GBps": round(rep["filter_GBps"], 1),
-            "t_filter": round(rep["t_filter"], 2), "t_reorth": round(rep["t_reorth"], 2)}
-        log(f"solve L={args.solve_L}: {tsolve:.1f}s status={status}")
-    out["p50_p99_batched_solve_ms"] = None
+        sl = solve_legs(pk, wl, ctx, args.solve_L, args.n_ev)
+        out["eigenpairs_per_s"] = {"value": sl["fp64"]["eigenpairs_per_s"],
+                                   "unit": "eigenpairs/s", **sl}
+    if not args.no_serve:
+        sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
+                         args.serve_cols, pk.FP64 if args.serve_fp64 else pk.FP32)
+        out["p50_p99_batched_solve_ms"] = [sv["p50_ms"], sv["p99_ms"]]
+        out["serving"] = sv
+        log(f"serving: {sv}")
+    else:
+        out["p50_p99_batched_solve_ms"] = None
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.L, args.W, 0, args.cpu_steps)

@@ -287,6 +287,10 @@ typedef struct {
   double bound_pad;    /* 0: 1e-3 */
   int max_iter;        /* 0: 4 * expectedkrylovdim */
   double E_min, E_max; /* both 0: compute the bounds */
+  int graph;           /* filter recurrence as one HIP graph: 0 = pick the
+                          faster of direct launches and graph replay on the
+                          first two filter applications, 1 = always graph,
+                          2 = never */
 } polfed_params;
 
 typedef struct {

@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
                 ("K_override", ctypes.c_int), ("omega", ctypes.c_double),
                 ("eta", ctypes.c_double), ("tol_resid", ctypes.c_double),
                 ("bound_pad", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("E_min", ctypes.c_double), ("E_max", ctypes.c_double)]
+                ("E_min", ctypes.c_double), ("E_max", ctypes.c_double),
+                ("graph", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

@@ -5,6 +5,7 @@
 // realizations is one multi-column Clenshaw recurrence.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <memory>
 
 #include "internal.hpp"
@@ -49,9 +50,8 @@ void BatchCoef::set(hipStream_t s, int nb_, const double* const* a, const int* K
 // A column whose order K_c is below the batch maximum has zero coefficients
 // above K_c, so its b_i stay zero until i = K_c.
 template <typename T>
-void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& co,
-                        const T* v, T* w, T* bufA, T* bufB) {
-  hipStream_t s = ctx->stream;
+void filter_apply_batch_on(hipStream_t s, const ChainBatch& bt, const BatchCoef& co,
+                           const T* v, T* w, T* bufA, T* bufB) {
   const int64_t D = bt.ops[0]->D;
   const int nb = bt.nb;
   REQUIRE(co.nb == nb, "batch filter: coefficient table of another batch");
@@ -71,6 +71,12 @@ void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& 
     cur = out;
   }
   chain_batch_step<T>(s, bt, D, true, A, v, cur, prev, w);
+}
+
+template <typename T>
+void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& co,
+                        const T* v, T* w, T* bufA, T* bufB) {
+  filter_apply_batch_on<T>(ctx->stream, bt, co, v, w, bufA, bufB);
 }
 
 template void filter_apply_batch<double>(polfed_ctx*, const ChainBatch&, const BatchCoef&,
@@ -107,6 +113,11 @@ void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
   bt.init(c, ops.data(), nb);
   bt.set_scale(Ec.data(), dE.data());
   co.set(c->stream, nb, a.data(), K.data());
+  graph.reset();
+  graph_pref = runs[0]->p.graph;
+  mode = kTimeDirect;
+  if (graph_pref == 2 || co.Kmax < 8) mode = kDirect;
+  if (graph_pref == 1 && mode == kTimeDirect) mode = kGraph;
   const int64_t D = ops[0]->D;
   const size_t tb = fp32 ? sizeof(float) : sizeof(double);
   const size_t need = (size_t)D * nb * tb;
@@ -124,6 +135,16 @@ double BatchFilter::run() {
   hipStream_t s = ctx->stream;
   const int nb = (int)members.size();
   const int64_t D = bt.ops[0]->D;
+  const bool use_graph = mode == kTimeGraph || mode == kGraph;
+  if (use_graph && !graph.ready())
+    graph.capture(ctx->cap_stream, [&](hipStream_t cs) {
+      if (fp32)
+        filter_apply_batch_on<float>(cs, bt, co, vb.as<float>(), wb.as<float>(), bA.as<float>(),
+                                     bB.as<float>());
+      else
+        filter_apply_batch_on<double>(cs, bt, co, vb.as<double>(), wb.as<double>(),
+                                      bA.as<double>(), bB.as<double>());
+    });
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
@@ -135,7 +156,9 @@ double BatchFilter::run() {
       HIPC(hipMemcpyAsync(vb.as<double>() + (size_t)i * D, members[i]->vec(),
                           (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  if (fp32)
+  if (use_graph)
+    graph.launch(s);
+  else if (fp32)
     filter_apply_batch<float>(ctx, bt, co, vb.as<float>(), wb.as<float>(), bA.as<float>(),
                               bB.as<float>());
   else
@@ -155,6 +178,16 @@ double BatchFilter::run() {
   HIPC(hipEventDestroy(e0));
   HIPC(hipEventDestroy(e1));
   const double t = 1e-3 * ms;
+  if (mode == kTimeDirect) {
+    t_direct_ms = ms;
+    mode = kTimeGraph;
+  } else if (mode == kTimeGraph) {
+    mode = ms < t_direct_ms ? kGraph : kDirect;
+    if (mode == kDirect) graph.reset();
+    if (verbose())
+      std::fprintf(stderr, "[polfed] batch filter nb=%d K=%d: direct %.3f ms, graph %.3f ms -> %s\n",
+                   nb, co.Kmax, t_direct_ms, ms, mode == kGraph ? "graph" : "direct");
+  }
   for (auto* r : members) {
     r->R.t_filter += t / nb;
     r->R.filter_steps += r->pl.K;

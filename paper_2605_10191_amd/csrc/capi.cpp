@@ -57,6 +57,36 @@ void DevBuf::release() {
   n_ = 0;
 }
 
+void GraphExec::reset() {
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  exec_ = nullptr;
+}
+
+void GraphExec::begin(hipStream_t cap) {
+  HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+}
+
+void GraphExec::end(hipStream_t cap) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamEndCapture(cap, &g));
+  const hipError_t e = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) exec_ = nullptr;
+  HIPC(e);
+}
+
+void GraphExec::abort(hipStream_t cap) {
+  hipGraph_t g = nullptr;
+  (void)hipStreamEndCapture(cap, &g);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+}
+
+void GraphExec::launch(hipStream_t s) {
+  REQUIRE(exec_ != nullptr, "graph not captured");
+  HIPC(hipGraphLaunch(exec_, s));
+}
+
 template <class F>
 polfed_status guarded(F&& f) {
   try {
@@ -121,6 +151,7 @@ polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out) {
       HIPC(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
       ctx->own_stream = true;
     }
+    HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     hipDeviceProp_t prop;
     HIPC(hipGetDeviceProperties(&prop, device));
     ctx->n_cu = prop.multiProcessorCount;
@@ -140,6 +171,7 @@ polfed_status polfed_destroy(polfed_ctx* ctx) {
       ctx->scratch_scalar.release();
       ctx->binom.release();
       if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+      if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     }
     delete ctx;
     return POLFED_OK;

@@ -55,6 +55,39 @@ class DevBuf {
   size_t n_ = 0;
 };
 
+// A sequence of launches recorded once on a capture stream and replayed as
+// one HIP graph on any stream.  The recorded launches keep their arguments,
+// so everything they touch must stay at the same addresses between replays.
+class GraphExec {
+ public:
+  GraphExec() = default;
+  GraphExec(const GraphExec&) = delete;
+  GraphExec& operator=(const GraphExec&) = delete;
+  ~GraphExec() { reset(); }
+  bool ready() const { return exec_ != nullptr; }
+  void reset();
+  // record(s) issues the launches on stream s (kernels only: no memset,
+  // copy, allocation or synchronization)
+  template <class F>
+  void capture(hipStream_t cap, F&& record) {
+    reset();
+    begin(cap);
+    try {
+      record(cap);
+    } catch (...) {
+      abort(cap);
+      throw;
+    }
+    end(cap);
+  }
+  void launch(hipStream_t s);
+ private:
+  void begin(hipStream_t cap);
+  void end(hipStream_t cap);
+  void abort(hipStream_t cap);
+  hipGraphExec_t exec_ = nullptr;
+};
+
 template <class T>
 void upload(DevBuf& b, const T* host, size_t n, hipStream_t s) {
   b.alloc(n * sizeof(T) > 0 ? n * sizeof(T) : 16);
@@ -155,6 +188,7 @@ struct polfed_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
   int n_cu = 256;
   std::mutex mu;  // serializes calls that use the shared workspaces
   // reusable workspaces
@@ -302,6 +336,10 @@ constexpr double kOmegaDefault = 0.17612720216036546;  // sin(2.655)/2.655
 int expected_krylov_dim(int howmany, int blocksize, double eta);
 
 // ---------------------------------------------------------------- solve ----
+// as filter_apply, on an explicit stream (graph capture)
+template <typename T>
+void filter_apply_on(hipStream_t s, const polfed_op* op, double E_c, double dE,
+                     const double* a, int K, const T* v, T* w, T* bufA, T* bufB);
 template <typename T>
 void filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
                   const double* a, int K, const T* v, T* w, T* bufA, T* bufB);
@@ -316,6 +354,7 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
                           double* const* resid, int* n_found,
                           polfed_report* rep);
 double now_seconds();
+bool verbose();  // POLFED_VERBOSE set: solver diagnostics on stderr
 void* ctx_scratch(polfed_ctx* ctx, int slot, size_t bytes);
 void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
                   const double* a, int K, double* V, int k, double* alpha,

@@ -15,6 +15,7 @@
 // the residual tolerance.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "internal.hpp"
 #include "solve_run.hpp"
@@ -87,6 +88,14 @@ static void cholqr(hipStream_t s, int64_t D, int n, DevBuf& W, DevBuf& tmp, int6
   HIPC(hipStreamSynchronize(s));
 }
 
+// Columns of X (D x n) listed in idx, packed into Y (D x idx.size()).
+static void gather_cols(hipStream_t s, int64_t D, const double* X, const std::vector<int>& idx,
+                        double* Y) {
+  for (size_t c = 0; c < idx.size(); ++c)
+    HIPC(hipMemcpyAsync(Y + c * D, X + (size_t)idx[c] * D, (size_t)D * sizeof(double),
+                        hipMemcpyDeviceToDevice, s));
+}
+
 void refine(SolveRun& run, Extracted& ex, double theta_min) {
   polfed_ctx* ctx = run.ctx;
   const polfed_op* op = run.op;
@@ -95,54 +104,69 @@ void refine(SolveRun& run, Extracted& ex, double theta_min) {
   const int n = (int)ex.E.size();
   const polfed_plan& pl = run.pl;
   const int K = pl.K;
-  constexpr int kMaxSweeps = 6;
+  // Sweeps filter only the pairs not yet locked; a pair locks once its
+  // residual is a tenth of the tolerance, so the slow tail of a few pairs
+  // near the window edge costs a few filters per sweep.
+  constexpr int kMaxSweeps = 24;
+  const double lock_tol = 0.1 * run.tol_resid;
   if (n == 0) return;
   const size_t n32 = (size_t)D * n * sizeof(float), n64 = (size_t)D * n * sizeof(double);
-  DevBuf r32(n32), z32(n32), bA(n32), bB(n32), W(n64), HW(n64), tmp(n64), dE, dP;
+  DevBuf r32(n32), z32(n32), bA(n32), bB(n32), Ua(n64), HUa(n64), W(n64), HW(n64), tmp(n64),
+      dE, dP;
   const bool batched = op->model == Model::Chain && !op->pattern_key.empty() && op->split_nseg > 0;
-  ChainBatch bt;
-  if (batched) {
-    std::vector<const polfed_op*> ops(n, op);
-    std::vector<double> Ec(n, pl.E_c), dEv(n, pl.dE);
-    bt.init(ctx, ops.data(), n);
-    bt.set_scale(Ec.data(), dEv.data());
-  }
   std::vector<std::vector<double>> q(n, std::vector<double>(std::max(K, 1)));
   std::vector<double> pv(n);
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if ((int)ex.sel.size() == run.p.n_ev && ex.complete) break;
     ++run.R.refine_sweeps;
-    // divided differences of P at the current Ritz values
-    for (int j = 0; j < n; ++j) {
-      const double t = (ex.E[j] - pl.E_c) / pl.dE;
-      filter_quotient(run.a.data(), K, t, q[j].data(), &pv[j]);
+    std::vector<int> act, lock;
+    for (int j = 0; j < n; ++j) (ex.res[j] <= lock_tol ? lock : act).push_back(j);
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    // active pairs, packed
+    std::vector<double> Ea(na);
+    for (int c = 0; c < na; ++c) Ea[c] = ex.E[act[c]];
+    gather_cols(s, D, ex.U2.as<double>(), act, Ua.as<double>());
+    gather_cols(s, D, ex.HU2.as<double>(), act, HUa.as<double>());
+    // divided differences of P at their Ritz values
+    for (int c = 0; c < na; ++c) {
+      const double t = (Ea[c] - pl.E_c) / pl.dE;
+      filter_quotient(run.a.data(), K, t, q[c].data(), &pv[c]);
     }
-    upload(dE, ex.E.data(), (size_t)n, s);
-    upload(dP, pv.data(), (size_t)n, s);
-    hipLaunchKernelGGL(k_resid_f32, dim3(grid_for(D * n)), dim3(256), 0, s, D, n,
-                       ex.U2.as<double>(), ex.HU2.as<double>(), dE.as<double>(), 1.0 / pl.dE,
+    upload(dE, Ea.data(), (size_t)na, s);
+    upload(dP, pv.data(), (size_t)na, s);
+    hipLaunchKernelGGL(k_resid_f32, dim3(grid_for(D * na)), dim3(256), 0, s, D, na,
+                       Ua.as<double>(), HUa.as<double>(), dE.as<double>(), 1.0 / pl.dE,
                        r32.as<float>());
     HIPC(hipGetLastError());
-    // z_j = Q_j(H~) r_j in FP32
+    // z_c = Q_c(H~) r_c in FP32
     if (K == 0) {
-      dev_fillf(s, D * n, 0.0f, z32.as<float>());
+      dev_fillf(s, D * na, 0.0f, z32.as<float>());
     } else if (batched) {
-      std::vector<const double*> qp(n);
-      std::vector<int> Kq(n, K - 1);
-      for (int j = 0; j < n; ++j) qp[j] = q[j].data();
+      std::vector<const polfed_op*> ops(na, op);
+      std::vector<double> Ec(na, pl.E_c), dEv(na, pl.dE);
+      ChainBatch bt;
+      bt.init(ctx, ops.data(), na);
+      bt.set_scale(Ec.data(), dEv.data());
+      std::vector<const double*> qp(na);
+      std::vector<int> Kq(na, K - 1);
+      for (int c = 0; c < na; ++c) qp[c] = q[c].data();
       BatchCoef co;
-      co.set(s, n, qp.data(), Kq.data());
+      co.set(s, na, qp.data(), Kq.data());
       filter_apply_batch<float>(ctx, bt, co, r32.as<float>(), z32.as<float>(), bA.as<float>(),
                                 bB.as<float>());
     } else {
-      for (int j = 0; j < n; ++j)
-        filter_apply<float>(ctx, op, pl.E_c, pl.dE, q[j].data(), K - 1,
-                            r32.as<float>() + (size_t)j * D, z32.as<float>() + (size_t)j * D,
+      for (int c = 0; c < na; ++c)
+        filter_apply<float>(ctx, op, pl.E_c, pl.dE, q[c].data(), K - 1,
+                            r32.as<float>() + (size_t)c * D, z32.as<float>() + (size_t)c * D,
                             bA.as<float>(), bB.as<float>());
     }
-    run.R.filter_steps += (double)n * std::max(K - 1, 0);
-    hipLaunchKernelGGL(k_combine, dim3(grid_for(D * n)), dim3(256), 0, s, D, n,
-                       ex.U2.as<double>(), dP.as<double>(), z32.as<float>(), W.as<double>());
+    run.R.filter_steps += (double)na * std::max(K - 1, 0);
+    // W = [locked pairs | P(t_c) u_c + z_c]
+    gather_cols(s, D, ex.U2.as<double>(), lock, W.as<double>());
+    double* Wa = W.as<double>() + lock.size() * (size_t)D;
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(D * na)), dim3(256), 0, s, D, na,
+                       Ua.as<double>(), dP.as<double>(), z32.as<float>(), Wa);
     HIPC(hipGetLastError());
     cholqr(s, D, n, W, tmp, run.ws.nseg);
     cholqr(s, D, n, W, tmp, run.ws.nseg);
@@ -151,6 +175,16 @@ void refine(SolveRun& run, Extracted& ex, double theta_min) {
                       HW.as<double>() + (size_t)j * D);
     rayleigh_ritz(s, D, n, W.as<double>(), HW.as<double>(), run.ws.nseg, ex);
     select_pairs(ex, run.lam, run.p.n_ev, run.tol_resid, theta_min, pl);
+    if (verbose()) {
+      int acc = 0;
+      double rmax = 0;
+      for (double x : ex.res) acc += x <= run.tol_resid;
+      for (int j : ex.sel) rmax = std::max(rmax, ex.res[j]);
+      std::fprintf(stderr,
+                   "[polfed] refine sweep %d: filtered=%d accepted=%d selected=%d complete=%d "
+                   "max sel res=%.1e\n",
+                   sweep, na, acc, (int)ex.sel.size(), (int)ex.complete, rmax);
+    }
   }
 }
 

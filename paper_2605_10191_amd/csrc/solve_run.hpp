@@ -102,6 +102,11 @@ struct SolveRun {
   bool done = false;
   uint64_t uid = 0;  // unique per setup(), identifies the solve in a batch
   std::vector<std::pair<hipEvent_t, hipEvent_t>> fev, rev;
+  // filter launch mode: direct launches or one graph replay per application
+  GraphExec graph;
+  DevBuf vst;  // FP64: fixed copy of v_k read by the graph
+  enum { kTimeDirect, kTimeGraph, kDirect, kGraph } mode = kTimeDirect;
+  float t_direct_ms = 0;
 
   SolveRun() = default;
   SolveRun(const SolveRun&) = delete;
@@ -116,6 +121,7 @@ struct SolveRun {
   double* wbuf() const { return ws.w.as<double>(); }  // where P(H~) v_k goes
   void filter_self();  // single-column filter of v_k into wbuf()
   void advance();      // CGS2, k += 1, periodic check; sets done when finished
+  void emit(const Extracted& ex, polfed_status st);
   void finish();
   void drain();
 };
@@ -135,10 +141,17 @@ struct BatchCoef {
 template <typename T>
 void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& co,
                         const T* v, T* w, T* bufA, T* bufB);
+template <typename T>
+void filter_apply_batch_on(hipStream_t s, const ChainBatch& bt, const BatchCoef& co,
+                           const T* v, T* w, T* bufA, T* bufB);
 
 // The multi-column filter shared by a set of running solves.
 struct BatchFilter {
   polfed_ctx* ctx = nullptr;
+  int graph_pref = 0;  // polfed_params.graph of the members
+  GraphExec graph;
+  enum { kTimeDirect, kTimeGraph, kDirect, kGraph } mode = kTimeDirect;
+  float t_direct_ms = 0;
   std::vector<SolveRun*> members;
   std::vector<uint64_t> ids;  // uid of each member when the batch was formed
   // true when runs are exactly the members the tables were built for

@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <numeric>
 
@@ -17,6 +19,14 @@
 #include "solve_run.hpp"
 
 namespace polfed {
+
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("POLFED_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
 
 double now_seconds() {
   using namespace std::chrono;
@@ -45,9 +55,8 @@ static void scale_t(hipStream_t s, int64_t n, T a, const T* x, T* y) {
 // w = a_0 v + H~ b_1 - b_2.  b_i overwrites b_{i+2} in place, so two buffers
 // carry the recurrence.
 template <typename T>
-void filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
-                  const double* a, int K, const T* v, T* w, T* bufA, T* bufB) {
-  hipStream_t s = ctx->stream;
+void filter_apply_on(hipStream_t s, const polfed_op* op, double E_c, double dE,
+                     const double* a, int K, const T* v, T* w, T* bufA, T* bufB) {
   const int64_t D = op->D;
   const T sigma = (T)(2.0 / dE), tau = (T)(-2.0 * E_c / dE);
   if (K == 0) {
@@ -66,6 +75,18 @@ void filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
   op_step<T>(s, op, (T)(0.5 * sigma), (T)(0.5 * tau), (T)a[0], v, cur, prev, w);
 }
 
+template <typename T>
+void filter_apply(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                  const double* a, int K, const T* v, T* w, T* bufA, T* bufB) {
+  filter_apply_on<T>(ctx->stream, op, E_c, dE, a, K, v, w, bufA, bufB);
+}
+
+template void filter_apply_on<double>(hipStream_t, const polfed_op*, double, double,
+                                      const double*, int, const double*, double*, double*,
+                                      double*);
+template void filter_apply_on<float>(hipStream_t, const polfed_op*, double, double,
+                                     const double*, int, const float*, float*, float*,
+                                     float*);
 template void filter_apply<double>(polfed_ctx*, const polfed_op*, double, double,
                                    const double*, int, const double*, double*,
                                    double*, double*);
@@ -382,22 +403,58 @@ size_t SolveRun::footprint(const polfed_op* op, const polfed_params& p) {
 void SolveRun::filter_self() {
   hipStream_t s = ctx->stream;
   const int64_t D = op->D;
+  if (mode == kTimeDirect && (p.graph == 2 || pl.K < 8)) mode = kDirect;
+  if (mode == kTimeDirect && p.graph == 1) mode = kGraph;
+  const bool use_graph = mode == kTimeGraph || mode == kGraph;
+  if (use_graph && !graph.ready()) {
+    if (!fp32) vst.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
+    graph.capture(ctx->cap_stream, [&](hipStream_t cs) {
+      if (fp32)
+        filter_apply_on<float>(cs, op, pl.E_c, pl.dE, a.data(), pl.K, ws.v32.as<float>(),
+                               ws.w32.as<float>(), ws.bA.as<float>(), ws.bB.as<float>());
+      else
+        filter_apply_on<double>(cs, op, pl.E_c, pl.dE, a.data(), pl.K, vst.as<double>(),
+                                ws.w.as<double>(), ws.bA.as<double>(), ws.bB.as<double>());
+    });
+  }
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
   HIPC(hipEventRecord(e0, s));
-  if (fp32) {
-    dev_copy_d2f(s, D, B.col(k), ws.v32.as<float>());
+  if (fp32) dev_copy_d2f(s, D, B.col(k), ws.v32.as<float>());
+  if (use_graph) {
+    if (!fp32)
+      HIPC(hipMemcpyAsync(vst.get(), B.col(k), (size_t)D * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    graph.launch(s);
+  } else if (fp32) {
     filter_apply<float>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, ws.v32.as<float>(),
                         ws.w32.as<float>(), ws.bA.as<float>(), ws.bB.as<float>());
-    dev_copy_f2d(s, D, ws.w32.as<float>(), ws.w.as<double>());
   } else {
     filter_apply<double>(ctx, op, pl.E_c, pl.dE, a.data(), pl.K, B.col(k), ws.w.as<double>(),
                          ws.bA.as<double>(), ws.bB.as<double>());
   }
+  if (fp32) dev_copy_f2d(s, D, ws.w32.as<float>(), ws.w.as<double>());
   HIPC(hipEventRecord(e1, s));
   fev.emplace_back(e0, e1);
   R.filter_steps += pl.K;
+  // autotuning: the first application runs direct, the second as a graph;
+  // the faster way serves the rest of the solve
+  if (mode == kTimeDirect || mode == kTimeGraph) {
+    HIPC(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    if (mode == kTimeDirect) {
+      t_direct_ms = ms;
+      mode = kTimeGraph;
+    } else {
+      mode = ms < t_direct_ms ? kGraph : kDirect;
+      if (mode == kDirect) graph.reset();
+      if (verbose())
+        std::fprintf(stderr, "[polfed] filter K=%d: direct %.3f ms, graph %.3f ms -> %s\n", pl.K,
+                     t_direct_ms, ms, mode == kGraph ? "graph" : "direct");
+    }
+  }
 }
 
 void SolveRun::drain() {
@@ -495,8 +552,15 @@ void SolveRun::advance() {
   double thmax = 0;
   for (double t : th) thmax = std::max(thmax, std::fabs(t));
   bool conv = true;
-  for (int j = 0; j < nw; ++j)
-    if (std::fabs(be[k] * zl[order[j]]) > tol_ritz * std::max(1.0, thmax)) conv = false;
+  double est_max = 0;
+  for (int j = 0; j < nw; ++j) {
+    const double e = std::fabs(be[k] * zl[order[j]]);
+    est_max = std::max(est_max, e);
+    if (e > tol_ritz * std::max(1.0, thmax)) conv = false;
+  }
+  if (verbose())
+    std::fprintf(stderr, "[polfed] check k=%d n_want=%d max |beta z|=%.2e tol=%.1e conv=%d\n", k,
+                 n_want, est_max, tol_ritz, (int)conv);
   R.t_check += now_seconds() - tc;
   if (conv || k >= M_max) {
     const double tx = now_seconds();
@@ -513,6 +577,12 @@ void SolveRun::advance() {
     Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw);
     select_pairs(ex, lam, p.n_ev, tol_resid, theta_min, pl);
     R.t_extract += now_seconds() - tx;
+    if (verbose()) {
+      int acc = 0;
+      for (double r : ex.res) acc += r <= tol_resid;
+      std::fprintf(stderr, "[polfed] extract k=%d accepted=%d selected=%d complete=%d theta_min=%.4f\n",
+                   k, acc, (int)ex.sel.size(), (int)ex.complete, theta_min);
+    }
     if (fp32 && !((int)ex.sel.size() == p.n_ev && ex.complete)) {
       const double tr = now_seconds();
       refine(*this, ex, theta_min);
@@ -520,27 +590,41 @@ void SolveRun::advance() {
     }
     const bool ok = (int)ex.sel.size() == p.n_ev && ex.complete;
     if (ok || k >= M_max) {
-      const int nf = (int)ex.sel.size();
-      std::vector<double> Eo(nf), Ro(nf);
-      for (int j = 0; j < nf; ++j) {
-        Eo[j] = ex.E[ex.sel[j]];
-        Ro[j] = ex.res[ex.sel[j]];
-        dcopy_async(s, evecs + (size_t)j * D, ex.U2.as<double>() + (size_t)ex.sel[j] * D,
-                    (size_t)D, hipMemcpyDeviceToDevice);
-      }
-      dcopy_async(s, evals, Eo.data(), (size_t)nf, hipMemcpyHostToDevice);
-      dcopy_async(s, resid, Ro.data(), (size_t)nf, hipMemcpyHostToDevice);
-      HIPC(hipStreamSynchronize(s));
-      *n_found = nf;
-      R.n_converged = nf;
-      status = ok ? POLFED_OK : POLFED_NOT_CONVERGED;
-      finish();
+      emit(ex, ok ? POLFED_OK : POLFED_NOT_CONVERGED);
+      return;
+    }
+    // The Ritz vectors of an FP32-filtered run stop improving once Lanczos
+    // has reached the FP32 noise level, so a refinement that did not finish
+    // will not finish later either: end with the pairs found.
+    if (fp32 && !ok) {
+      emit(ex, POLFED_NOT_CONVERGED);
       return;
     }
     if ((int)ex.sel.size() == p.n_ev && !ex.complete)
       n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
   }
   next_check = k + check_every;
+}
+
+// Copies the selected pairs to the caller's buffers and finishes the run.
+void SolveRun::emit(const Extracted& ex, polfed_status st) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  const int nf = (int)ex.sel.size();
+  std::vector<double> Eo(nf), Ro(nf);
+  for (int j = 0; j < nf; ++j) {
+    Eo[j] = ex.E[ex.sel[j]];
+    Ro[j] = ex.res[ex.sel[j]];
+    dcopy_async(s, evecs + (size_t)j * D, ex.U2.as<double>() + (size_t)ex.sel[j] * D, (size_t)D,
+                hipMemcpyDeviceToDevice);
+  }
+  dcopy_async(s, evals, Eo.data(), (size_t)nf, hipMemcpyHostToDevice);
+  dcopy_async(s, resid, Ro.data(), (size_t)nf, hipMemcpyHostToDevice);
+  HIPC(hipStreamSynchronize(s));
+  *n_found = nf;
+  R.n_converged = nf;
+  status = st;
+  finish();
 }
 
 void SolveRun::finish() {

@@ -151,3 +151,14 @@ def test_solve_batch_equals_single_solves(pk, ctx):
         assert np.max(np.abs(host(ev1) - evb) / np.maximum(np.abs(evb), 1.0)) <= 1e-10
         ov = np.abs(np.sum(host(U1) * Ub, axis=0))
         assert ov.min() >= 1 - 1e-8
+
+
+def test_solve_batch_graph_replay(pk, ctx):
+    """Batched filter replayed as a HIP graph every iteration."""
+    say("solve_batch graph replay")
+    ops, Hs = batch_ops(pk, ctx, "xxz", 12, 3)
+    x0s = [dev(wl.start_vector(o.D, c)) for c, o in enumerate(ops)]
+    out, status = pk.solve_batch(ops, x0s, 20, 0.5, "normalized", graph=1)
+    assert status == "OK"
+    for c, (ev, U, R, rep) in enumerate(out):
+        _check_pairs(Hs[c], rep["lambda"], 20, ev, U, R)

@@ -345,3 +345,19 @@ def test_solve_fp32_bulk_filter(pk, ctx):
     E_min, E_max = lanczos.spectral_extremes(H)
     lam = polfed.target_energy("normalized", 0.5, E_min, E_max)
     _check_solve(pk, op, H, 20, lam, precision=pk.FP32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_graph_replay_matches_direct_launches(pk, ctx, prec):
+    """The filter recurrence replayed as one HIP graph per Lanczos iteration
+    (graph=1: a replay every iteration, with the eager reorthogonalization
+    and checks in between) gives the eigenpairs of direct launches (graph=2)
+    and of the dense oracle."""
+    say(f"solve graph vs direct {prec}")
+    op, H = make_op(pk, ctx, *OPS[0])
+    E_min, E_max = lanczos.spectral_extremes(H)
+    lam = polfed.target_energy("normalized", 0.5, E_min, E_max)
+    p = pk.FP64 if prec == "fp64" else pk.FP32
+    rep_g = _check_solve(pk, op, H, 20, lam, precision=p, graph=1)
+    rep_d = _check_solve(pk, op, H, 20, lam, precision=p, graph=2)
+    assert rep_g["iters"] == rep_d["iters"] or prec == "fp32"
