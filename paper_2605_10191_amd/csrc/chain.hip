@@ -9,7 +9,9 @@
 // and the position of a row inside its block is lo_rank[lo].
 //
 // Each wavefront processes a segment of one block (up to 128 rows, lanes on
-// consecutive rows).  Within a wavefront hi is uniform, hence:
+// consecutive rows; a block of more rows is split into two segments, which
+// both stage it: one segment per block, processed in two passes, measured
+// slower since the second pass waits for the first).  Within a wavefront hi is uniform, hence:
 //   - a hop inside the low part stays in the block.  The wavefront stages
 //     the block's b_{i+1} entries in LDS once (coalesced) and reads those
 //     neighbours from LDS at position lo_rank[lo'];
@@ -19,9 +21,11 @@
 //     block at r + d + lo_rank[lo'] - lo_rank[lo] (d uniform);
 //   - the diagonal is DLO[lo] (LDS) + a uniform high part + two cross terms.
 // All wave-uniform data of a segment (offsets, flags, diagonal part) is
-// precomputed into a 128-byte record read with scalar loads.  Every gather is issued unconditionally (a bond that cannot
-// hop reads the row's own entry, which is subtracted again), so the gathers
-// of a lane's rows are in flight together.
+// precomputed into a 128-byte record read with scalar loads.  A high-part
+// bond whose two bits are equal in the segment's high part cannot hop: its
+// gather is skipped by a wave-uniform branch; the joining and periodic
+// gathers are masked per lane.  All gathers of a lane's rows are issued
+// before any is consumed, so they are in flight together.
 //
 // Locality: the eight XCDs each sweep a contiguous eighth of the segments
 // (workgroups are dispatched to the XCDs round robin), so most high-part
@@ -153,7 +157,8 @@ __global__ __launch_bounds__(256) void k_chain_split(
   constexpr int NLO = 1 << Lb;
   constexpr int NH = Lh - 1;  // bonds inside the high part
   constexpr int NL = Lb - 1;  // bonds inside the low part
-  constexpr int RPL = kChainSegRows / 64;  // rows per lane
+  constexpr int RPL = 2;                      // rows per lane and pass
+  constexpr int kPasses = kChainSegRows / 128;  // passes per segment
   constexpr int SPL = kChainStageRows / 64;  // staged rows per lane
   constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
   constexpr int CHUNKS = BLOB / 16;
@@ -205,62 +210,73 @@ __global__ __launch_bounds__(256) void k_chain_split(
     T stg[SPL];
 #pragma unroll
     for (int m = 0; m < SPL; ++m)
-      stg[m] = bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk);
-    // rows of this lane, clamped into the segment (a clamped lane repeats the
-    // last row and stores the same value)
-    int jj[RPL], lo[RPL];
-    u4 np[RPL];
+      stg[m] = 64 * m < bs ? bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk)
+                           : T(0);
+    // the segment's rows in passes of 128 (two rows per lane); the block is
+    // staged in LDS by the first pass
+    for (int pass = 0; pass < kPasses; ++pass) {
+      const int p0 = pass * 128;
+      if (p0 >= cur.len) break;
+      // rows of this lane, clamped into the segment (a clamped lane repeats
+      // the last row and stores the same value)
+      int jj[RPL], lo[RPL];
+      u4 np[RPL];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      jj[i] = min(lane + 64 * i, cur.len - 1);
-      lo[i] = s_lo[cur.lidx + jj[i]];
-      np[i] = s_np[lo[i]];
-    }
-    // global gathers: high-part hops at uniform offsets, joining and periodic
-    // bonds, and the streamed v and b_{i+2}
-    T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
-    bool act_j[RPL], act_p[RPL];
+      for (int i = 0; i < RPL; ++i) {
+        jj[i] = min(p0 + lane + 64 * i, cur.len - 1);
+        lo[i] = s_lo[cur.lidx + jj[i]];
+        np[i] = s_np[lo[i]];
+      }
+      // global gathers: high-part hops at uniform offsets, joining and
+      // periodic bonds, and the streamed v and b_{i+2}
+      T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
+      bool act_j[RPL], act_p[RPL];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const uint32_t off = (uint32_t)jj[i] * TB;
+      for (int i = 0; i < RPL; ++i) {
+        const uint32_t off = (uint32_t)jj[i] * TB;
 #pragma unroll
-      for (int b = 0; b < NH; ++b)
-        g_hi[i][b] = bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB);
-      const int l = lo[i];
-      act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
-      act_p[i] = c.periodic && ((l & 1) != hitop);
-      const int rj = (int)((np[i][2] >> 8) & 255u);   // byte 9
-      const int rp = (int)((np[i][2] >> 16) & 255u);  // byte 10
-      g_j[i] = bload<T>(rb1, (uint32_t)(act_j[i] ? blk0 + cur.d_join + rj : cur.row0 + jj[i]) * TB, 0);
-      g_p[i] = bload<T>(rb1, (uint32_t)(act_p[i] ? blk0 + cur.d_pbc + rp : cur.row0 + jj[i]) * TB, 0);
-      vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
-      bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
-    }
-    wave_sync();  // the previous segment's LDS reads are done
+        for (int b = 0; b < NH; ++b)
+          g_hi[i][b] = cur.dh[b] != 0
+                           ? bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB)
+                           : T(0);
+        const int l = lo[i];
+        act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
+        act_p[i] = c.periodic && ((l & 1) != hitop);
+        const int rj = (int)((np[i][2] >> 8) & 255u);   // byte 9
+        const int rp = (int)((np[i][2] >> 16) & 255u);  // byte 10
+        g_j[i] = act_j[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_join + rj) * TB, 0) : T(0);
+        g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_pbc + rp) * TB, 0) : T(0);
+        vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
+        bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
+      }
+      if (pass == 0) {
+        wave_sync();  // the previous segment's LDS reads are done
 #pragma unroll
-    for (int m = 0; m < SPL; ++m) stage[min(lane + 64 * m, bs - 1)] = stg[m];
-    wave_sync();
+        for (int m = 0; m < SPL; ++m)
+          if (64 * m < bs) stage[min(lane + 64 * m, bs - 1)] = stg[m];
+        wave_sync();
+      }
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int l = lo[i];
-      const int pos = st + jj[i];
-      const T bo = stage[pos];
-      T hop = 0;
+      for (int i = 0; i < RPL; ++i) {
+        const int l = lo[i];
+        const T bo = stage[st + jj[i]];
+        T hop = 0;
 #pragma unroll
-      for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+        for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
 #pragma unroll
-      for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
-      const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
-      const int n_idle = (NL - __popc(xlo)) + cur.n_idle_h;
-      hop -= (T)n_idle * bo;
-      hop += act_j[i] ? g_j[i] : T(0);
-      const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
-      const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
-      const T dg = s_dlo[l] + (T)cur.dhi + vzz * (T)n11x;
-      const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
-      T o = sigma * acc + tau * bo - bt[i];
-      if (v) o += a * vv[i];
-      bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+        for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
+        const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+        const int n_idle = NL - __popc(xlo);
+        hop -= (T)n_idle * bo;
+        hop += act_j[i] ? g_j[i] : T(0);
+        const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
+        const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
+        const T dg = s_dlo[l] + (T)cur.dhi + vzz * (T)n11x;
+        const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+        T o = sigma * acc + tau * bo - bt[i];
+        if (v) o += a * vv[i];
+        bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+      }
     }
   }
 }

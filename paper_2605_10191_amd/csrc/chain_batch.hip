@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
   constexpr int NLO = 1 << Lb;
   constexpr int NH = Lh - 1;
   constexpr int NL = Lb - 1;
-  constexpr int RPL = kChainSegRows / 64;
+  constexpr int RALL = kChainSegRows / 64;  // rows per lane in a segment
+  constexpr int RPL = 2;                     // rows per lane and pass
   constexpr int SPL = kChainStageRows / 64;
   constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
   constexpr int CHUNKS = BLOB / 16;
@@ -79,12 +80,12 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
     const int blk0 = cur.row0 - st;
     const uint32_t so_blk = (uint32_t)blk0 * TB, so_row = (uint32_t)cur.row0 * TB;
     // per-row decoding shared by all columns
-    int jj[RPL], lo[RPL], gj[RPL], gp[RPL];
-    u4 np[RPL];
-    bool act_j[RPL], act_p[RPL];
-    T zz[RPL], nidle[RPL];
+    int jj[RALL], lo[RALL], gj[RALL], gp[RALL];
+    u4 np[RALL];
+    bool act_j[RALL], act_p[RALL];
+    T zz[RALL], nidle[RALL];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
+    for (int i = 0; i < RALL; ++i) {
       jj[i] = min(lane + 64 * i, cur.len - 1);
       const int l = s_lo[cur.lidx + jj[i]];
       lo[i] = l;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
       gj[i] = act_j[i] ? blk0 + cur.d_join + rj : cur.row0 + jj[i];
       gp[i] = act_p[i] ? blk0 + cur.d_pbc + rp : cur.row0 + jj[i];
       const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
-      nidle[i] = (T)((NL - __popc(xlo)) + cur.n_idle_h);
+      nidle[i] = (T)(NL - __popc(xlo));
       const int n11x = ((l >> (Lb - 1)) & 1 & hi0) + (c.periodic ? (hitop & l & 1) : 0);
       zz[i] = vzz * (T)(__popc(l & (l >> 1)) + n11x);
     }
@@ -114,40 +115,51 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
       T stg[SPL];
 #pragma unroll
       for (int m = 0; m < SPL; ++m)
-        stg[m] = bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk);
-      T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const uint32_t off = (uint32_t)jj[i] * TB;
-#pragma unroll
-        for (int b = 0; b < NH; ++b)
-          g_hi[i][b] = bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB);
-        g_j[i] = bload<T>(rb1, (uint32_t)gj[i] * TB, 0);
-        g_p[i] = bload<T>(rb1, (uint32_t)gp[i] * TB, 0);
-        vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
-        bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
-      }
-      wave_sync();
-#pragma unroll
-      for (int m = 0; m < SPL; ++m) stage[min(lane + 64 * m, bs - 1)] = stg[m];
-      wave_sync();
+        stg[m] = 64 * m < bs ? bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk)
+                             : T(0);
       const T* fa = s_fab + cc * 64;
+      for (int pass = 0; pass < RALL / RPL; ++pass) {
+        if (pass * 128 >= cur.len) break;
+        T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int l = lo[i];
-        const T bo = stage[st + jj[i]];
-        T hop = 0;
+        for (int i = 0; i < RPL; ++i) {
+          const int r = RPL * pass + i;
+          const uint32_t off = (uint32_t)jj[r] * TB;
 #pragma unroll
-        for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+          for (int b = 0; b < NH; ++b)
+            g_hi[i][b] = cur.dh[b] != 0
+                             ? bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB)
+                             : T(0);
+          g_j[i] = act_j[r] ? bload<T>(rb1, (uint32_t)gj[r] * TB, 0) : T(0);
+          g_p[i] = act_p[r] ? bload<T>(rb1, (uint32_t)gp[r] * TB, 0) : T(0);
+          vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
+          bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
+        }
+        if (pass == 0) {
+          wave_sync();
 #pragma unroll
-        for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
-        hop -= nidle[i] * bo;
-        hop += act_j[i] ? g_j[i] : T(0);
-        const T dg = zz[i] + fa[l & 31] + fa[32 + (l >> 5)] + dsg;
-        const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
-        T o = sig * acc + ta * bo - bt[i];
-        if (v) o += ac * vv[i];
-        bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+          for (int m = 0; m < SPL; ++m)
+            if (64 * m < bs) stage[min(lane + 64 * m, bs - 1)] = stg[m];
+          wave_sync();
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = RPL * pass + i;
+          const int l = lo[r];
+          const T bo = stage[st + jj[r]];
+          T hop = 0;
+#pragma unroll
+          for (int b = 0; b < NL; ++b) hop += stage[(np[r][b >> 2] >> (8 * (b & 3))) & 255u];
+#pragma unroll
+          for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
+          hop -= nidle[r] * bo;
+          hop += act_j[r] ? g_j[i] : T(0);
+          const T dg = zz[r] + fa[l & 31] + fa[32 + (l >> 5)] + dsg;
+          const T acc = dg * bo + t_in * hop + (act_p[r] ? t_pb * g_p[i] : T(0));
+          T o = sig * acc + ta * bo - bt[i];
+          if (v) o += ac * vv[i];
+          bstore<kAuxNT>(o, rout, (uint32_t)jj[r] * TB, so_row);
+        }
       }
     }
   }

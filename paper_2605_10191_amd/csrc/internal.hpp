@@ -123,9 +123,9 @@ struct ChainDev {
 //   bond  [8..9] high-part diagonal (double)  [10..31] row offsets of the
 //   hops inside the high part (0 where no hop).
 constexpr int kChainLoBits = 10;      // Lb = min(10, L / 2); blocks <= 252 rows
-constexpr int kChainSegRows = 128;    // rows per wavefront segment
+constexpr int kChainSegRows = 128;   // rows per wavefront segment
 constexpr int kChainStageRows = 256;  // LDS rows staged per wavefront
-constexpr int kChainBlocksPerCU = 6;  // persistent blocks per compute unit
+constexpr int kChainBlocksPerCU = 4;  // persistent blocks per compute unit
 constexpr int kBatchMaxCols = 16;     // columns per multi-column launch
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kChainRecWords = 32;
