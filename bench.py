@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=300)
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     ap.add_argument("--serve-cols", type=int, default=16)
     ap.add_argument("--serve-fp64", action="store_true")

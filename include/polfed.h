@@ -291,6 +291,9 @@ typedef struct {
                           faster of direct launches and graph replay on the
                           first two filter applications, 1 = always graph,
                           2 = never */
+  int refine_max;      /* FP32 bulk: at most this many refinement sweeps
+                          (0: 16; -1: none); a refinement that stalls or
+                          runs out hands the solve to the FP64 filter */
 } polfed_params;
 
 typedef struct {
@@ -303,6 +306,8 @@ typedef struct {
   double filter_GBps;    /* filter_bytes / t_filter / 1e9 */
   double t_queue;        /* served requests: submission to admission (s) */
   double t_latency;      /* served requests: submission to result (s) */
+  int fp32_fallback;     /* 1: the FP32-bulk refinement stalled and the solve
+                            was completed by the FP64 filter */
 } polfed_report;
 
 polfed_status polfed_params_default(polfed_params* p);

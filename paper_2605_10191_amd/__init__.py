@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("tol_resid", ctypes.c_double),
                 ("bound_pad", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("E_min", ctypes.c_double), ("E_max", ctypes.c_double),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("refine_max", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -60,7 +60,8 @@ class Report(ctypes.Structure):
                 [(n, ctypes.c_double) for n in
                  ("t_bounds", "t_plan", "t_filter", "t_reorth", "t_check",
                   "t_extract", "t_refine", "t_total", "filter_steps",
-                  "filter_bytes", "filter_GBps", "t_queue", "t_latency")])
+                  "filter_bytes", "filter_GBps", "t_queue", "t_latency")] +
+                [("fp32_fallback", ctypes.c_int)])
 
     def as_dict(self) -> dict:
         d = {n: getattr(self, n) for n, _ in self._fields_}

@@ -191,6 +191,7 @@ double BatchFilter::run() {
   for (auto* r : members) {
     r->R.t_filter += t / nb;
     r->R.filter_steps += r->pl.K;
+    r->R.filter_bytes += r->pl.K * (fp32 ? 16.0 : 32.0) * (double)D;
   }
   return t;
 }
@@ -212,15 +213,20 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
     runs.emplace_back(new SolveRun());
     runs.back()->setup(ctx, ops[i], p, x0[i], evals[i], evecs[i], resid[i], &n_found[i]);
   }
-  BatchFilter bf;
+  // one batched filter per precision: an FP32-bulk run whose refinement
+  // stalls continues with the FP64 filter
+  BatchFilter bf[2];
   for (;;) {
-    std::vector<SolveRun*> now;
+    std::vector<SolveRun*> now[2];
     for (auto& r : runs)
-      if (!r->done) now.push_back(r.get());
-    if (now.empty()) break;
-    if (!bf.same_members(now)) bf.form(ctx, now);
-    bf.run();
-    for (auto* r : now) r->advance();
+      if (!r->done) now[r->fp32 ? 1 : 0].push_back(r.get());
+    if (now[0].empty() && now[1].empty()) break;
+    for (int g = 0; g < 2; ++g) {
+      if (now[g].empty()) continue;
+      if (!bf[g].same_members(now[g])) bf[g].form(ctx, now[g]);
+      bf[g].run();
+      for (auto* r : now[g]) r->advance();
+    }
   }
   polfed_status st = POLFED_OK;
   for (int i = 0; i < B; ++i) {

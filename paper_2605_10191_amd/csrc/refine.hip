@@ -107,7 +107,9 @@ void refine(SolveRun& run, Extracted& ex, double theta_min) {
   // Sweeps filter only the pairs not yet locked; a pair locks once its
   // residual is a tenth of the tolerance, so the slow tail of a few pairs
   // near the window edge costs a few filters per sweep.
-  constexpr int kMaxSweeps = 24;
+  constexpr int kStall = 4;
+  const int kMaxSweeps = run.p.refine_max > 0 ? run.p.refine_max : (run.p.refine_max < 0 ? 0 : 16);
+  int best = -1, since_best = 0;
   const double lock_tol = 0.1 * run.tol_resid;
   if (n == 0) return;
   const size_t n32 = (size_t)D * n * sizeof(float), n64 = (size_t)D * n * sizeof(double);
@@ -161,7 +163,6 @@ void refine(SolveRun& run, Extracted& ex, double theta_min) {
                             r32.as<float>() + (size_t)c * D, z32.as<float>() + (size_t)c * D,
                             bA.as<float>(), bB.as<float>());
     }
-    run.R.filter_steps += (double)na * std::max(K - 1, 0);
     // W = [locked pairs | P(t_c) u_c + z_c]
     gather_cols(s, D, ex.U2.as<double>(), lock, W.as<double>());
     double* Wa = W.as<double>() + lock.size() * (size_t)D;
@@ -175,6 +176,14 @@ void refine(SolveRun& run, Extracted& ex, double theta_min) {
                       HW.as<double>() + (size_t)j * D);
     rayleigh_ritz(s, D, n, W.as<double>(), HW.as<double>(), run.ws.nseg, ex);
     select_pairs(ex, run.lam, run.p.n_ev, run.tol_resid, theta_min, pl);
+    int n_acc = 0;
+    for (double x : ex.res) n_acc += x <= run.tol_resid;
+    if (n_acc > best) {
+      best = n_acc;
+      since_best = 0;
+    } else if (++since_best >= kStall) {
+      break;  // stalled: the caller falls back to the FP64 filter
+    }
     if (verbose()) {
       int acc = 0;
       double rmax = 0;

@@ -72,7 +72,7 @@ static std::string group_key(const polfed_req* r) {
   // operators that cannot share a recurrence each form their own group
   std::string k = batchable ? op->pattern_key : "op:" + std::to_string((uintptr_t)op) + ":" +
                                                     std::to_string((uintptr_t)r);
-  return k + (r->p.precision == POLFED_FP32 ? "|f32" : "|f64");
+  return k + (r->run->fp32 ? "|f32" : "|f64");
 }
 
 void Server::complete(polfed_req* r, polfed_status st, const std::string& err) {

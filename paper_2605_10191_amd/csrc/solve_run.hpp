@@ -93,7 +93,8 @@ struct SolveRun {
   polfed_plan pl{};
   std::vector<double> a;  // filter coefficients a_0..a_K
   // Lanczos state
-  int n_want = 0, M_alloc = 0, M_max = 0, cap = 0, check_every = 0, next_check = 0, k = 0;
+  int n_want = 0, n_want0 = 0, M_alloc = 0, M_max = 0, cap = 0, check_every = 0,
+      next_check = 0, k = 0;
   uint64_t restart_seed = 0;
   Basis B;
   Ws ws;
@@ -122,6 +123,7 @@ struct SolveRun {
   void filter_self();  // single-column filter of v_k into wbuf()
   void advance();      // CGS2, k += 1, periodic check; sets done when finished
   void emit(const Extracted& ex, polfed_status st);
+  void fallback_fp64();  // restart the Lanczos iteration with the FP64 filter
   void finish();
   void drain();
 };

@@ -358,6 +358,7 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   const double tr1 = tr[0] / (double)D, tr2 = tr[1] / (double)D;
   lam = target_energy(p.target_kind, p.target, E_min, E_max);
   n_want = (int)std::min<int64_t>(D, p.n_ev + buffer_size(p.n_ev));
+  n_want0 = n_want;
   pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega, p.K_override);
   a.assign(pl.K + 1, 0.0);
   filter_coefficients(pl.lambda_t, pl.K, a.data());
@@ -438,6 +439,7 @@ void SolveRun::filter_self() {
   HIPC(hipEventRecord(e1, s));
   fev.emplace_back(e0, e1);
   R.filter_steps += pl.K;
+  R.filter_bytes += pl.K * step_bytes(op, fp32 ? POLFED_FP32 : POLFED_FP64);
   // autotuning: the first application runs direct, the second as a graph;
   // the faster way serves the rest of the solve
   if (mode == kTimeDirect || mode == kTimeGraph) {
@@ -595,15 +597,32 @@ void SolveRun::advance() {
     }
     // The Ritz vectors of an FP32-filtered run stop improving once Lanczos
     // has reached the FP32 noise level, so a refinement that did not finish
-    // will not finish later either: end with the pairs found.
+    // will not finish later either: the solve is completed in FP64.
     if (fp32 && !ok) {
-      emit(ex, POLFED_NOT_CONVERGED);
+      fallback_fp64();
       return;
     }
     if ((int)ex.sel.size() == p.n_ev && !ex.complete)
       n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
   }
   next_check = k + check_every;
+}
+
+// Restarts the filtered Lanczos iteration from v_0 with the FP64 filter (the
+// bounds, plan and basis allocation are kept).
+void SolveRun::fallback_fp64() {
+  const int64_t D = op->D;
+  fp32 = false;
+  R.fp32_fallback = 1;
+  tol_ritz = 1e-10;
+  graph.reset();
+  mode = (p.graph == 2 || pl.K < 8) ? kDirect : (p.graph == 1 ? kGraph : kTimeDirect);
+  ws.bA.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
+  ws.bB.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
+  k = 0;
+  n_want = n_want0;
+  next_check = std::min(n_want, M_max);
+  if (verbose()) std::fprintf(stderr, "[polfed] FP32 refinement stalled: restarting in FP64\n");
 }
 
 // Copies the selected pairs to the caller's buffers and finishes the run.
@@ -631,7 +650,6 @@ void SolveRun::finish() {
   drain();
   R.iters = k;
   R.n_want = n_want;
-  R.filter_bytes = R.filter_steps * sbytes;
   R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
   R.t_total = now_seconds() - t_start;
   done = true;

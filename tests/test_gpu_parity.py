@@ -361,3 +361,33 @@ def test_solve_graph_replay_matches_direct_launches(pk, ctx, prec):
     rep_g = _check_solve(pk, op, H, 20, lam, precision=p, graph=1)
     rep_d = _check_solve(pk, op, H, 20, lam, precision=p, graph=2)
     assert rep_g["iters"] == rep_d["iters"] or prec == "fp32"
+
+
+def test_fp32_refinement_fallback_to_fp64(pk, ctx):
+    """With no refinement sweeps allowed, an FP32-bulk solve hands over to the
+    FP64 filter and still returns the dense oracle's pairs."""
+    say("fp32 fallback forced")
+    op, H = make_op(pk, ctx, *OPS[0])
+    E_min, E_max = lanczos.spectral_extremes(H)
+    lam = polfed.target_energy("normalized", 0.5, E_min, E_max)
+    rep = _check_solve(pk, op, H, 20, lam, precision=pk.FP32, refine_max=-1)
+    assert rep["fp32_fallback"] == 1
+
+
+def test_fp32_stalled_refinement_case(pk, ctx):
+    """XXZ L=16 W=3 seed 999, 50 pairs: a window-edge pair converges too
+    slowly under the FP32 refinement; the solve must still end OK, with the
+    FP64 run's eigenvalues and residuals checked with the oracle's H."""
+    say("fp32 stalled case L=16")
+    L = 16
+    h, H, _ = xxz_case(L, L // 2, 3.0, 999)
+    op = pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, h, True)
+    x0 = dev(wl.start_vector(op.D, 999))
+    e32, U32, r32, rep32, st32 = pk.solve(op, x0, 50, 0.5, "normalized", precision=pk.FP32)
+    e64, _, _, rep64, st64 = pk.solve(op, x0, 50, 0.5, "normalized")
+    assert st32 == "OK" and st64 == "OK"
+    E32, E64 = host(e32), host(e64)
+    assert np.max(np.abs(E32 - E64) / np.maximum(np.abs(E64), 1.0)) <= 1e-10
+    U = host(U32)
+    assert np.linalg.norm(H @ U - U * E32, axis=0).max() <= 1e-8
+    say(f"   fallback={rep32['fp32_fallback']} sweeps={rep32['refine_sweeps']} iters={rep32['iters']}")
