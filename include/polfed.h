@@ -147,6 +147,13 @@ polfed_status polfed_op_materialize_csr(polfed_ctx* ctx, polfed_op* op);
 /* Chooses which representation the filter uses (POLFED_MATRIX_FREE needs a
  * model operator; POLFED_CSR needs a CSR copy). */
 polfed_status polfed_op_set_storage(polfed_op* op, int storage);
+/* Step-kernel variant of a matrix-free chain (XXZ, t-V) in one precision:
+ * -1 = pick by timing on the next step (the default), 0 = segment kernel,
+ * 1 = tile kernel with the largest tile, 2 = tile kernel with half that tile.
+ * A variant that does not exist for the chain length (tiles need L >= 22)
+ * gives POLFED_ERR_INVALID.  *chosen (may be NULL) receives the variant in
+ * use after the call (-1 while not tuned yet). */
+polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, int* chosen);
 polfed_status polfed_op_dim(const polfed_op* op, int64_t* D);
 /* Off-diagonal nnz of the CSR copy (-1 if there is none). */
 polfed_status polfed_op_nnz(const polfed_op* op, int64_t* nnz_offdiag);

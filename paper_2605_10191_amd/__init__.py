@@ -93,6 +93,7 @@ SIGNATURES = {
     "polfed_op_csr": [_P, _I64, _I64P, _I32P, _DP, ctypes.POINTER(_P)],
     "polfed_op_materialize_csr": [_P, _P],
     "polfed_op_set_storage": [_P, _I],
+    "polfed_op_set_kernel": [_P, _I, _I, ctypes.POINTER(_I)],
     "polfed_op_dim": [_P, _I64P],
     "polfed_op_nnz": [_P, _I64P],
     "polfed_op_export_csr": [_P, _P, _P, _P, _P, _P],
@@ -344,6 +345,13 @@ class Operator:
     def set_storage(self, storage: int):
         _check(_lib.polfed_op_set_storage(self.handle, storage))
         return self
+
+    def set_kernel(self, precision: int, variant: int) -> int:
+        """Step-kernel variant for a chain (-1 auto, 0 segment, 1/2 tile);
+        returns the variant in use."""
+        out = _I()
+        _check(_lib.polfed_op_set_kernel(self.handle, precision, variant, ctypes.byref(out)))
+        return out.value
 
     @property
     def nnz(self) -> int:

@@ -335,6 +335,23 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage) {
   });
 }
 
+polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, int* chosen) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(op, "null operator");
+    REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
+    REQUIRE(variant >= -1 && variant <= 2, "variant must be -1, 0, 1 or 2");
+    const int pi = precision == POLFED_FP64 ? 0 : 1;
+    if (variant > 0) {
+      REQUIRE(op->model == Model::Chain && op->split_nseg > 0,
+              "tile kernels exist only for matrix-free chains");
+      REQUIRE(op->tiles[variant - 1].n > 0, "no tile kernel of this size for this chain length");
+    }
+    op->tuned[pi] = variant;
+    if (chosen) *chosen = op->tuned[pi];
+    return POLFED_OK;
+  });
+}
+
 polfed_status polfed_op_dim(const polfed_op* op, int64_t* D) {
   return guarded([&]() -> polfed_status {
     REQUIRE(op && D, "null argument");

@@ -33,6 +33,7 @@
 // output use non-temporal accesses so they do not evict the gathered one.
 #include <algorithm>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 
 #include "chain_dev.hpp"
@@ -144,6 +145,39 @@ void build_chain_split(polfed_op* op) {
     upload(w == 0 ? op->d_blob64 : op->d_blob32, blob.data(), blob.size(), s);
   }
   upload(op->d_rec, rec.data(), rec.size(), s);
+  // tiles of 2^KT consecutive high parts (segments are in ascending hi), for
+  // the largest KT with at least 512 tiles and for KT - 1
+  std::vector<int32_t> seg_of_hi(nhi + 1, 0);
+  {
+    int32_t sidx = 0;
+    for (int64_t hi = 0; hi < nhi; ++hi) {
+      seg_of_hi[hi] = sidx;
+      const int need = N - __builtin_popcountll(hi);
+      if (need >= 0 && need <= Lb) sidx += (cnt[need] + kChainSegRows - 1) / kChainSegRows;
+    }
+    seg_of_hi[nhi] = sidx;
+  }
+  const int KT = chain_tile_bits(L);
+  for (int v = 0; v < 2; ++v) {
+    auto& T = op->tiles[v];
+    T = polfed_op::Tiles{};
+    const int kt = KT - v;
+    if (KT == 0 || kt < 2) continue;
+    const int64_t nt = (int64_t)1 << (Lh - kt);
+    std::vector<int32_t> tiles((size_t)nt * 4, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t h0 = t << kt, h1 = (t + 1) << kt;
+      tiles[4 * t] = hi_off[h0];
+      tiles[4 * t + 1] = hi_off[h1] - hi_off[h0];
+      tiles[4 * t + 2] = seg_of_hi[h0];
+      tiles[4 * t + 3] = seg_of_hi[h1] - seg_of_hi[h0];
+      T.max_rows = std::max(T.max_rows, tiles[4 * t + 1]);
+    }
+    T.bits = kt;
+    T.n = (int)nt;
+    upload(T.d, tiles.data(), tiles.size(), s);
+  }
+  op->tuned[0] = op->tuned[1] = -1;
   HIPC(hipStreamSynchronize(s));
 }
 
@@ -281,12 +315,139 @@ __global__ __launch_bounds__(256) void k_chain_split(
   }
 }
 
-// Launch shape: persistent blocks per CU and the XCD-contiguous mapping can
-// be overridden through POLFED_CHAIN_BPC and POLFED_CHAIN_XCD (0 = off).
 static int env_int(const char* name, int dflt) {
   const char* s = std::getenv(name);
   return (s && *s) ? std::atoi(s) : dflt;
 }
+
+// Tile variant for long chains: a workgroup stages a whole tile of 2^KT
+// consecutive high parts of b_{i+1} in LDS (one coalesced read of its rows),
+// so the low-part hops, the joining bond (high bit 0) and the KT - 1 bonds
+// inside the tile's high bits are LDS reads; only the bonds among the
+// remaining high bits and the periodic bond gather from global memory.  The
+// tile's segments are shared among the workgroup's wavefronts.
+template <typename T, int L, int KT>
+__global__ __launch_bounds__(kTileThreads) void k_chain_tile(
+    ChainSplitDev c, T sigma, T tau, T a, const T* __restrict__ v,
+    const T* __restrict__ b1, const T* b2, T* out, int nxcd, int ntiles,
+    const int32_t* __restrict__ recs, const int32_t* __restrict__ tiles) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;   // bonds inside the high part
+  constexpr int NHL = KT - 1;  // of which inside the tile: b < NHL
+  constexpr int NL = Lb - 1;
+  constexpr int RPL = kChainSegRows / 64;
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  {
+    const u4* src = reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blob64 : c.blob32);
+    u4* dst = reinterpret_cast<u4*>(smem);
+    for (int i = threadIdx.x; i < CHUNKS; i += kTileThreads) dst[i] = src[i];
+  }
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const T* s_dlo = reinterpret_cast<const T*>(smem + 16 * NLO);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(s_dlo + NLO);
+  T* s_tile = reinterpret_cast<T*>(smem + BLOB);
+
+  const int xcd = blockIdx.x % nxcd;
+  const int wg = blockIdx.x / nxcd, nwg = gridDim.x / nxcd;
+  const int t_begin = (int)((int64_t)ntiles * xcd / nxcd);
+  const int t_end = (int)((int64_t)ntiles * (xcd + 1) / nxcd);
+  const int wave = uniform(threadIdx.x >> 6);
+  constexpr int NW = kTileThreads / 64;
+  const int lane = threadIdx.x & 63;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t vbytes = (uint32_t)(c.D * TB);
+  const rsrc_t rb1 = make_rsrc(b1, vbytes), rv = make_rsrc(v, v ? vbytes : 0),
+               rb2 = make_rsrc(b2, b2 ? vbytes : 0), rout = make_rsrc(out, vbytes);
+  for (int t = t_begin + wg; t < t_end; t += nwg) {
+    const int trow0 = tiles[4 * t], trows = tiles[4 * t + 1];
+    const int tseg0 = tiles[4 * t + 2], tnseg = tiles[4 * t + 3];
+    __syncthreads();  // the previous tile's LDS reads are done (and the tables)
+    {
+      constexpr int U = 4;
+      const uint32_t so = (uint32_t)trow0 * TB;
+      for (int i0 = 0; i0 < trows; i0 += U * kTileThreads) {
+        T x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kTileThreads + (int)threadIdx.x;
+          x[u] = i < trows ? bload<T>(rb1, (uint32_t)i * TB, so) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kTileThreads + (int)threadIdx.x;
+          if (i < trows) s_tile[i] = x[u];
+        }
+      }
+    }
+    __syncthreads();
+    for (int si = tseg0 + wave; si < tseg0 + tnseg; si += NW) {
+      const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform(si) * kChainRecWords);
+      const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+      const int st = (cur.flags >> 12) & 1023;
+      const int blk0 = cur.row0 - st;
+      const int lrow0 = cur.row0 - trow0, lblk0 = blk0 - trow0;
+      const uint32_t so_row = (uint32_t)cur.row0 * TB;
+      int jj[RPL], lo[RPL];
+      u4 np[RPL];
+      bool act_j[RPL], act_p[RPL];
+      T g_hi[RPL][NH - NHL > 0 ? NH - NHL : 1], g_p[RPL], vv[RPL], bt[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        jj[i] = min(lane + 64 * i, cur.len - 1);
+        const int l = s_lo[cur.lidx + jj[i]];
+        lo[i] = l;
+        np[i] = s_np[l];
+        act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
+        act_p[i] = c.periodic && ((l & 1) != hitop);
+        const uint32_t off = (uint32_t)jj[i] * TB;
+#pragma unroll
+        for (int b = NHL; b < NH; ++b)
+          g_hi[i][b - NHL] = cur.dh[b] != 0
+                                 ? bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB)
+                                 : T(0);
+        const int rp = (int)((np[i][2] >> 16) & 255u);
+        g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_pbc + rp) * TB, 0) : T(0);
+        vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
+        bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int l = lo[i];
+        const int lr = lrow0 + jj[i];
+        const T bo = s_tile[lr];
+        T hop = 0;
+#pragma unroll
+        for (int b = 0; b < NL; ++b)
+          hop += s_tile[lblk0 + (int)((np[i][b >> 2] >> (8 * (b & 3))) & 255u)];
+        const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+        hop -= (T)(NL - __popc(xlo)) * bo;
+#pragma unroll
+        for (int b = 0; b < NHL; ++b)
+          if (cur.dh[b] != 0) hop += s_tile[lr + cur.dh[b]];
+#pragma unroll
+        for (int b = NHL; b < NH; ++b) hop += g_hi[i][b - NHL];
+        const int rj = (int)((np[i][2] >> 8) & 255u);
+        if (act_j[i]) hop += s_tile[lblk0 + cur.d_join + rj];
+        const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
+        const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
+        const T dg = s_dlo[l] + (T)cur.dhi + vzz * (T)n11x;
+        const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+        T o = sigma * acc + tau * bo - bt[i];
+        if (v) o += a * vv[i];
+        bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+      }
+    }
+  }
+}
+
+// Launch shape: persistent blocks per CU and the XCD-contiguous mapping can
+// be overridden through POLFED_CHAIN_BPC and POLFED_CHAIN_XCD (0 = off).
 
 template <typename T, int L>
 static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
@@ -310,13 +471,115 @@ static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a
   HIPC(hipGetLastError());
 }
 
+template <typename T, int L, int KT>
+static void launch_tile(hipStream_t s, const polfed_op* op, const polfed_op::Tiles& tl, T sigma,
+                        T tau, T a, const T* v, const T* b1, const T* b2, T* out) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int NLO = 1 << Lb;
+  const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) + (size_t)tl.max_rows * sizeof(T);
+  const int per_cu = std::max(1, (int)(kLdsPerCU / shm));
+  ChainSplitDev c = op->chain_split();
+  int64_t grid = std::min<int64_t>(tl.n, (int64_t)op->ctx->n_cu * per_cu);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  hipLaunchKernelGGL((k_chain_tile<T, L, KT>), dim3((unsigned)grid), dim3(kTileThreads), shm, s, c,
+                     sigma, tau, a, v, b1, b2, out, nxcd, tl.n, c.rec, tl.d.as<int32_t>());
+  HIPC(hipGetLastError());
+}
+
+// Step-kernel variants of a chain: 0 = segment kernel, 1 + i = tile kernel
+// with tiles[i].  Returns false for a variant that does not exist.
+template <typename T, int L>
+static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma, T tau, T a,
+                           const T* v, const T* b1, const T* b2, T* out) {
+  constexpr int KT = chain_tile_bits(L);
+  if (var == 0) {
+    launch_split<T, L>(s, op, sigma, tau, a, v, b1, b2, out);
+    return true;
+  }
+  if constexpr (KT >= 2) {
+    constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+    const auto& tl = op->tiles[var - 1];
+    if (tl.n <= 0) return false;
+    if (chain_blob_bytes(1 << Lb, (int)sizeof(T)) + (size_t)tl.max_rows * sizeof(T) > kLdsPerCU)
+      return false;
+    if (var == 1 && tl.bits == KT) {
+      launch_tile<T, L, KT>(s, op, tl, sigma, tau, a, v, b1, b2, out);
+      return true;
+    }
+    if constexpr (KT - 1 >= 2) {
+      if (var == 2 && tl.bits == KT - 1) {
+        launch_tile<T, L, KT - 1>(s, op, tl, sigma, tau, a, v, b1, b2, out);
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+// Picks the fastest variant for (op, precision) by timing 20 launches of
+// each on scratch vectors; not while the stream is being captured.
+template <typename T, int L>
+static int tuned_variant(hipStream_t s, const polfed_op* op) {
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  if (op->tuned[pi] >= 0) return op->tuned[pi];
+  static const int allow_tile = env_int("POLFED_CHAIN_TILE", -1);
+  if (chain_tile_bits(L) == 0 || allow_tile == 0) return op->tuned[pi] = 0;
+  if (allow_tile >= 1 && allow_tile <= 2) return op->tuned[pi] = allow_tile;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPC(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return 0;
+  const size_t n = (size_t)op->D;
+  DevBuf bv(n * sizeof(T)), bb1(n * sizeof(T)), bb2(n * sizeof(T));
+  HIPC(hipMemsetAsync(bv.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(bb1.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(bb2.get(), 0, n * sizeof(T), s));
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int var = 0; var < 3; ++var) {
+    auto go = [&] {
+      return launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(),
+                                  bb2.as<T>(), bb2.as<T>());
+    };
+    if (!go()) continue;
+    go();
+    HIPC(hipEventRecord(e0, s));
+    for (int i = 0; i < 20; ++i) go();
+    HIPC(hipEventRecord(e1, s));
+    HIPC(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    if (verbose())
+      std::fprintf(stderr, "[polfed] chain step L=%d %s variant %d: %.2f us\n", L,
+                   sizeof(T) == 8 ? "fp64" : "fp32", var, 1e3f * ms / 20);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = var;
+    }
+  }
+  HIPC(hipEventDestroy(e0));
+  HIPC(hipEventDestroy(e1));
+  return op->tuned[pi] = best;
+}
+
 template <typename T>
 bool chain_split_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
                       const T* v, const T* b1, const T* b2, T* out) {
   if (op->split_nseg <= 0) return false;
   switch (op->L) {
-#define POLFED_CASE(LL) \
-  case LL: launch_split<T, LL>(s, op, sigma, tau, a, v, b1, b2, out); return true;
+#define POLFED_CASE(LL)                                                                     \
+  case LL:                                                                                  \
+    if (!launch_variant<T, LL>(s, op, tuned_variant<T, LL>(s, op), sigma, tau, a, v, b1, b2, \
+                               out))                                                        \
+      launch_split<T, LL>(s, op, sigma, tau, a, v, b1, b2, out);                            \
+    return true;
     POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
     POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
     POLFED_CASE(14) POLFED_CASE(15) POLFED_CASE(16) POLFED_CASE(17) POLFED_CASE(18)

@@ -127,6 +127,15 @@ constexpr int kChainSegRows = 128;   // rows per wavefront segment
 constexpr int kChainStageRows = 256;  // LDS rows staged per wavefront
 constexpr int kChainBlocksPerCU = 4;  // persistent blocks per compute unit
 constexpr int kBatchMaxCols = 16;     // columns per multi-column launch
+// Tile kernel: a workgroup stages 2^KT consecutive high-part blocks in LDS.
+// KT is chosen so that there are at least 512 tiles; 0 = no tile kernel.
+constexpr int chain_tile_bits(int L) {
+  const int Lb = (L / 2 < 10) ? L / 2 : 10;
+  const int Lh = L - Lb;
+  const int kt = Lh - 9 < 5 ? Lh - 9 : 5;
+  return (L >= 22 && kt >= 2) ? kt : 0;
+}
+constexpr int kTileThreads = 512;
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kChainRecWords = 32;
 constexpr int kChainMaxHighBonds = kChainRecWords - 10;
@@ -220,6 +229,14 @@ struct polfed_op {
   int split_Lb = 0;
   int64_t split_nseg = 0;
   polfed::DevBuf d_blob64, d_blob32, d_rec;
+  // tile-kernel tables for two tile sizes (bits KT and KT - 1)
+  struct Tiles {
+    int bits = 0, max_rows = 0, n = 0;
+    polfed::DevBuf d;  // [n][4]: first row, rows, first segment, segments
+  } tiles[2];
+  // step-kernel variant picked by timing on first use, per precision
+  // (-1: not tuned yet, 0: segment kernel, 1 + i: tile kernel tiles[i])
+  mutable int tuned[2] = {-1, -1};
   std::vector<double> split_dseg;  // uniform diagonal part of each segment
   std::vector<double> split_fab;   // field sums of low bits 0-4 | 5-9
   polfed::ChainSplitDev chain_split() const;

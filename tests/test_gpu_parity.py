@@ -205,6 +205,38 @@ def test_large_chain_sampled_rows(pk, ctx):
     assert np.max(np.abs(y[rows] - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("L", [22, 23, 24])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, prec, variant):
+    """Full-size Clenshaw steps of long chains with each step kernel (the
+    segment kernel; tile kernels with 8/16/32 and 4/8/16 high parts per tile
+    at L = 22, 23, 24): sampled rows of a v + 2 H~ b1 - b2 against the
+    oracle's row-by-row eq. (xxz)."""
+    say(f"L={L} sampled clenshaw step {prec} variant {variant}")
+    N = L // 2
+    h = wl.xxz_fields(L, 3.0, 1)
+    op = pk.Operator.xxz(ctx, L, N, 1.0, 1.0, h, True)
+    assert op.set_kernel(pk.FP64 if prec == "fp64" else pk.FP32, variant) == variant
+    st = basis.sector_states(L, N)
+    rng = np.random.default_rng(5)
+    v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":  # the reference sees the same rounded inputs
+        v, b1, b2 = (x.astype(np.float32).astype(np.float64) for x in (v, b1, b2))
+    E_c, dE, a_i = 0.4, 23.0, 0.0173
+    tb2 = dev(b2, dt)
+    pk.clenshaw_step(op, E_c, dE, a_i, dev(v, dt), dev(b1, dt), tb2,
+                     pk.FP64 if prec == "fp64" else pk.FP32)
+    got = host(tb2).astype(np.float64)
+    rows = np.unique(np.concatenate([rng.integers(0, op.D, 6000), np.arange(300),
+                                     np.arange(op.D - 300, op.D)]))
+    Hb = models.xxz_rows_apply(L, N, 1.0, 1.0, h, True, st, rows, b1)
+    ref = a_i * v[rows] + 2.0 * (Hb - E_c * b1[rows]) / dE - b2[rows]
+    tol = 1e-13 if prec == "fp64" else 3e-6
+    assert np.max(np.abs(got[rows] - ref)) <= tol * np.max(np.abs(ref))
+
+
 # ----------------------------------------------------------------- filter ----
 
 def _ref_step(H, E_c, dE, a_i, v, b1, b2, final):
