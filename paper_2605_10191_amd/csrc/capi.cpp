@@ -339,12 +339,13 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
   return guarded([&]() -> polfed_status {
     REQUIRE(op, "null operator");
     REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
-    REQUIRE(variant >= -1 && variant <= 2, "variant must be -1, 0, 1 or 2");
+    REQUIRE(variant >= -1 && variant <= 3, "variant must be -1, 0, 1, 2 or 3");
     const int pi = precision == POLFED_FP64 ? 0 : 1;
     if (variant > 0) {
       REQUIRE(op->model == Model::Chain && op->split_nseg > 0,
-              "tile kernels exist only for matrix-free chains");
-      REQUIRE(op->tiles[variant - 1].n > 0, "no tile kernel of this size for this chain length");
+              "step-kernel variants exist only for matrix-free chains");
+      if (variant <= 2)
+        REQUIRE(op->tiles[variant - 1].n > 0, "no tile kernel of this size for this chain length");
     }
     op->tuned[pi] = variant;
     if (chosen) *chosen = op->tuned[pi];

@@ -320,6 +320,172 @@ static int env_int(const char* name, int dflt) {
   return (s && *s) ? std::atoi(s) : dflt;
 }
 
+// Paired variant: lane l holds the adjacent rows 2l and 2l + 1 of a segment,
+// so every coalesced access (block staging, high-part gathers, v, b_{i+2}
+// and the store) moves both rows in one 16-byte instruction, halving the
+// vector-memory instructions per row.  Loads past the segment's end read
+// other rows (unused) or fall outside the buffer (read as 0); stores are
+// guarded per row.
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_chain_pair(
+    ChainSplitDev c, T sigma, T tau, T a, const T* __restrict__ v,
+    const T* __restrict__ b1, const T* b2, T* out, int nxcd,
+    const int32_t* __restrict__ recs) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;
+  constexpr int NL = Lb - 1;
+  constexpr int SPL = kChainStageRows / 128;  // staged row pairs per lane
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  {
+    const u4* src = reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blob64 : c.blob32);
+    u4* dst = reinterpret_cast<u4*>(smem);
+    constexpr int PER = (CHUNKS + 255) / 256;
+    u4 tmp[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CHUNKS) tmp[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CHUNKS) dst[i] = tmp[k];
+    }
+  }
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const T* s_dlo = reinterpret_cast<const T*>(smem + 16 * NLO);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(s_dlo + NLO);
+  T* stage = reinterpret_cast<T*>(smem + BLOB) + (threadIdx.x >> 6) * kChainStageRows;
+  __syncthreads();
+
+  const int xcd = blockIdx.x % nxcd;
+  const int blocks_x = gridDim.x / nxcd;
+  const int64_t s_begin = c.nseg * xcd / nxcd, s_end = c.nseg * (xcd + 1) / nxcd;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wstride = (int64_t)blocks_x * wpb;
+  const int lane = threadIdx.x & 63;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t vbytes = (uint32_t)(c.D * TB);
+  const rsrc_t rb1 = make_rsrc(b1, vbytes), rv = make_rsrc(v, v ? vbytes : 0),
+               rb2 = make_rsrc(b2, b2 ? vbytes : 0), rout = make_rsrc(out, vbytes);
+  int64_t si = s_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
+  if (si >= s_end) return;
+  for (; si < s_end; si += wstride) {
+    const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform((int)si) * kChainRecWords);
+    const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+    const int bs = (cur.flags >> 2) & 1023, st = (cur.flags >> 12) & 1023;
+    const int blk0 = cur.row0 - st;
+    const uint32_t so_blk = (uint32_t)blk0 * TB, so_row = (uint32_t)cur.row0 * TB;
+    const uint32_t pair_off = (uint32_t)(2 * lane) * TB;
+    // stage the block: pairs of rows
+    T sg[SPL][2];
+#pragma unroll
+    for (int m = 0; m < SPL; ++m) {
+      if (128 * m < bs)
+        bload2<T>(rb1, pair_off + (uint32_t)(128 * m) * TB, so_blk, sg[m][0], sg[m][1]);
+      else
+        sg[m][0] = sg[m][1] = T(0);
+    }
+    // the lane's two rows, clamped into the segment
+    int jj[2], lo[2];
+    u4 np[2];
+    bool act_j[2], act_p[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      jj[i] = min(2 * lane + i, cur.len - 1);
+      lo[i] = s_lo[cur.lidx + jj[i]];
+      np[i] = s_np[lo[i]];
+      act_j[i] = ((lo[i] >> (Lb - 1)) & 1) != hi0;
+      act_p[i] = c.periodic && ((lo[i] & 1) != hitop);
+    }
+    T g_hi[NH > 0 ? NH : 1][2], g_j[2], g_p[2], vv[2], bt[2];
+#pragma unroll
+    for (int b = 0; b < NH; ++b) {
+      if (cur.dh[b] != 0)
+        bload2<T>(rb1, pair_off, (uint32_t)(cur.row0 + cur.dh[b]) * TB, g_hi[b][0], g_hi[b][1]);
+      else
+        g_hi[b][0] = g_hi[b][1] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int rj = (int)((np[i][2] >> 8) & 255u);
+      const int rp = (int)((np[i][2] >> 16) & 255u);
+      g_j[i] = act_j[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_join + rj) * TB, 0) : T(0);
+      g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_pbc + rp) * TB, 0) : T(0);
+    }
+    if (v)
+      bload2<T, kAuxNT>(rv, pair_off, so_row, vv[0], vv[1]);
+    else
+      vv[0] = vv[1] = T(0);
+    if (b2)
+      bload2<T, kAuxNT>(rb2, pair_off, so_row, bt[0], bt[1]);
+    else
+      bt[0] = bt[1] = T(0);
+    wave_sync();  // the previous segment's LDS reads are done
+#pragma unroll
+    for (int m = 0; m < SPL; ++m) {
+      const int r = 128 * m + 2 * lane;
+      if (r < bs) {
+        stage[r] = sg[m][0];
+        if (r + 1 < bs) stage[r + 1] = sg[m][1];
+      }
+    }
+    wave_sync();
+    T o[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int l = lo[i];
+      const T bo = stage[st + jj[i]];
+      T hop = 0;
+#pragma unroll
+      for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+#pragma unroll
+      for (int b = 0; b < NH; ++b) hop += g_hi[b][i];
+      const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+      hop -= (T)(NL - __popc(xlo)) * bo;
+      hop += act_j[i] ? g_j[i] : T(0);
+      const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
+      const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
+      const T dg = s_dlo[l] + (T)cur.dhi + vzz * (T)n11x;
+      const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+      o[i] = sigma * acc + tau * bo - bt[i];
+      if (v) o[i] += a * vv[i];
+    }
+    const int r0 = 2 * lane;
+    if (r0 + 1 < cur.len)
+      bstore2<kAuxNT>(o[0], o[1], rout, pair_off, so_row);
+    else if (r0 < cur.len)
+      bstore<kAuxNT>(o[0], rout, pair_off, so_row);
+  }
+}
+
+template <typename T, int L>
+static void launch_pair(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v,
+                        const T* b1, const T* b2, T* out) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int NLO = 1 << Lb;
+  const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) + 4 * kChainStageRows * sizeof(T);
+  const int bpc = std::max(1, std::min(kChainBlocksPerCU, (int)(kLdsPerCU / shm)));
+  ChainSplitDev c = op->chain_split();
+  const int64_t blocks_needed = (c.nseg + 3) / 4;
+  int64_t grid = std::min<int64_t>(blocks_needed, (int64_t)op->ctx->n_cu * bpc);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  hipLaunchKernelGGL((k_chain_pair<T, L>), dim3((unsigned)grid), dim3(256), shm, s, c, sigma,
+                     tau, a, v, b1, b2, out, nxcd, c.rec);
+  HIPC(hipGetLastError());
+}
+
 // Tile variant for long chains: a workgroup stages a whole tile of 2^KT
 // consecutive high parts of b_{i+1} in LDS (one coalesced read of its rows),
 // so the low-part hops, the joining bond (high bit 0) and the KT - 1 bonds
@@ -501,6 +667,10 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
     launch_split<T, L>(s, op, sigma, tau, a, v, b1, b2, out);
     return true;
   }
+  if (var == 3) {
+    launch_pair<T, L>(s, op, sigma, tau, a, v, b1, b2, out);
+    return true;
+  }
   if constexpr (KT >= 2) {
     constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
     const auto& tl = op->tiles[var - 1];
@@ -528,8 +698,8 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   const int pi = sizeof(T) == 8 ? 0 : 1;
   if (op->tuned[pi] >= 0) return op->tuned[pi];
   static const int allow_tile = env_int("POLFED_CHAIN_TILE", -1);
-  if (chain_tile_bits(L) == 0 || allow_tile == 0) return op->tuned[pi] = 0;
-  if (allow_tile >= 1 && allow_tile <= 2) return op->tuned[pi] = allow_tile;
+  if (allow_tile == 0) return op->tuned[pi] = 0;
+  if (allow_tile >= 1 && allow_tile <= 3) return op->tuned[pi] = allow_tile;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return 0;
@@ -543,7 +713,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   HIPC(hipEventCreate(&e1));
   int best = 0;
   float best_ms = 1e30f;
-  for (int var = 0; var < 3; ++var) {
+  for (int var = 0; var < 4; ++var) {
     auto go = [&] {
       return launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(),
                                   bb2.as<T>(), bb2.as<T>());

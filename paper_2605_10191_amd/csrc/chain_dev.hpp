@@ -56,6 +56,36 @@ __device__ __forceinline__ T bload(rsrc_t r, uint32_t vo, uint32_t so) {
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, AUX));
 }
+// Two consecutive elements in one 16-byte access (8-byte alignment suffices
+// for buffer accesses).
+template <typename T, int AUX = 0>
+__device__ __forceinline__ void bload2(rsrc_t r, uint32_t vo, uint32_t so, T& x0, T& x1) {
+  if constexpr (sizeof(T) == 8) {
+    using d2 = __attribute__((ext_vector_type(2))) double;
+    const d2 d = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, AUX));
+    x0 = d[0];
+    x1 = d[1];
+  } else {
+    using f2 = __attribute__((ext_vector_type(2))) float;
+    const f2 d = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, AUX));
+    x0 = d[0];
+    x1 = d[1];
+  }
+}
+template <int AUX, typename T>
+__device__ __forceinline__ void bstore2(T x0, T x1, rsrc_t r, uint32_t vo, uint32_t so) {
+  if constexpr (sizeof(T) == 8) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    using d2 = __attribute__((ext_vector_type(2))) double;
+    const d2 d = {x0, x1};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, d), r, vo, so, AUX);
+  } else {
+    using u2 = __attribute__((ext_vector_type(2))) unsigned int;
+    using f2 = __attribute__((ext_vector_type(2))) float;
+    const f2 d = {x0, x1};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, d), r, vo, so, AUX);
+  }
+}
 template <int AUX, typename T>
 __device__ __forceinline__ void bstore(T x, rsrc_t r, uint32_t vo, uint32_t so) {
   using u2 = __attribute__((ext_vector_type(2))) unsigned int;

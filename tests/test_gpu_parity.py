@@ -207,11 +207,11 @@ def test_large_chain_sampled_rows(pk, ctx):
 
 @pytest.mark.parametrize("L", [22, 23, 24])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, prec, variant):
     """Full-size Clenshaw steps of long chains with each step kernel (the
     segment kernel; tile kernels with 8/16/32 and 4/8/16 high parts per tile
-    at L = 22, 23, 24): sampled rows of a v + 2 H~ b1 - b2 against the
+    at L = 22, 23, 24; the paired-row kernel): sampled rows of a v + 2 H~ b1 - b2 against the
     oracle's row-by-row eq. (xxz)."""
     say(f"L={L} sampled clenshaw step {prec} variant {variant}")
     N = L // 2
@@ -262,6 +262,34 @@ def test_clenshaw_step_matches_oracle(pk, ctx, case, prec, final):
     got = host(tb2).astype(np.float64)
     tol = 1e-14 if prec == "fp64" else 2e-6
     assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+CHAIN_OPS = [c for c in OPS if c[0] in ("xxz", "tv")]
+
+
+@pytest.mark.parametrize("case", CHAIN_OPS, ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", [0, 3])
+def test_chain_step_variants_match_oracle(pk, ctx, case, prec, variant):
+    """Every row of a Clenshaw step with the segment kernel and the paired-row
+    kernel (odd segment lengths, ragged blocks, open and periodic chains)."""
+    say(f"chain step variant {variant} {case} {prec}")
+    op, H = make_op(pk, ctx, *case)
+    p = pk.FP64 if prec == "fp64" else pk.FP32
+    assert op.set_kernel(p, variant) == variant
+    rng = np.random.default_rng(17)
+    v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        v, b1, b2 = (x.astype(np.float32).astype(np.float64) for x in (v, b1, b2))
+    E_c, dE, a_i = -0.2, 9.0, 0.031
+    for final in (False, True):
+        tb2 = dev(b2, dt)
+        pk.clenshaw_step(op, E_c, dE, a_i, dev(v, dt), dev(b1, dt), tb2, p, final)
+        ref = _ref_step(H, E_c, dE, a_i, v, b1, b2, final)
+        got = host(tb2).astype(np.float64)
+        tol = 1e-14 if prec == "fp64" else 2e-6
+        assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
 
 
 def _filter_tol(K, prec):
