@@ -23,6 +23,8 @@ Beside it the JSON line carries
   kernels       the same step kernel in FP32, as CSR SpMV, and as the
                 multi-column kernel over 8 realizations (a working set of
                 692 MB per step, larger than the 256 MB last-level cache);
+                XXZ L=20 matrix-free vs CSR; t-V L=26 (D = 10,400,600);
+  qsun          a full solve of the quantum sun workload (D = 65,536);
   eigenpairs_per_s  complete solves of the XXZ L=20 workload (100 pairs),
                 plain FP64 and FP32 bulk + FP64 refinement, with the FP32
                 result's error per eigenpair against the FP64 one;
@@ -60,17 +62,29 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(kernel: str):
     """HBM bytes per launch from committed rocprofv3 counters, or None when
-    they were taken on another version of the kernel source."""
+    they were taken on another kernel or another version of its source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_src_sha") != kernel_source_sha():
+    if t.get("kernel_src_sha") != kernel_source_sha() or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
+
+
+def step_kernel_name(op, prec, tname: str, L: int) -> str:
+    """Name of the step-kernel variant in use for a chain operator."""
+    var = op.set_kernel(prec, -2)
+    Lb = min(10, L // 2)
+    kt = min(5, L - Lb - 9)
+    if var == 3:
+        return f"k_chain_pair<{tname}, {L}>"
+    if var in (1, 2):
+        return f"k_chain_tile<{tname}, {L}, {kt - (var - 1)}>"
+    return f"k_chain_split<{tname}, {L}>"
 
 
 def xxz_setup(pk, wl, ctx, L, W, seed, n_ev):
@@ -148,7 +162,50 @@ def kernel_legs(pk, wl, ctx, L, W, iters):
                        "note": "algorithmic bytes: vectors + nnz (8 B value, 4 B column) "
                                "+ row pointers + diagonal"}
     op.close()
+    # config 2 (L=20): matrix-free vs CSR step
+    h20 = wl.xxz_fields(20, 3.0, 0)
+    op20 = pk.Operator.xxz(ctx, 20, 10, 1.0, 1.0, h20, True)
+    D20 = op20.D
+    mf, _ = pk.profile_step(op20, pk.FP64, iters)
+    op20.materialize_csr().set_storage(pk.CSR)
+    nnz20 = op20.nnz
+    csr, _ = pk.profile_step(op20, pk.FP64, iters)
+    out["xxz_L20_fp64"] = {"matrix_free_us": round(mf * 1e3, 2),
+                           "matrix_free_GBps": round(32 * D20 / (mf * 1e-3) / 1e9, 1),
+                           "csr_us": round(csr * 1e3, 2),
+                           "csr_GBps": round((32 * D20 + nnz20 * 12 + 8 * (D20 + 1) + 8 * D20)
+                                             / (csr * 1e-3) / 1e9, 1), "nnz": nnz20}
+    op20.close()
+    # config 5 (t-V L=26, N=13, D=10,400,600): step kernel in FP64 and FP32
+    eps = wl.tv_onsite(26, 0)
+    op26 = pk.Operator.tv(ctx, 26, 13, 1.0, 1.0, eps, True)
+    D26 = op26.D
+    for prec, w, name in ((pk.FP64, 8, "fp64"), (pk.FP32, 4, "fp32")):
+        avg, _ = pk.profile_step(op26, prec, max(20, iters // 4))
+        out[f"tv_L26_{name}"] = {"GBps": round(4 * w * D26 / (avg * 1e-3) / 1e9, 1),
+                                 "us": round(avg * 1e3, 2), "bytes": 4 * w * D26, "D": D26}
+    op26.close()
     return out
+
+
+def qsun_leg(pk, wl, ctx):
+    """Config 3: quantum sun, GOE dot of N=3 spins + L=13 outer spins
+    (D = 65,536), 50 eigenpairs at normalized energy 0.5, FP64."""
+    import torch
+    q = wl.qsun_draws(3, 13, 0)
+    op = pk.Operator.qsun(ctx, 3, 13, q["A"], 1.0, 1.0, 0.75, q["u"], q["n_of_j"], q["h"])
+    x0 = torch.tensor(wl.start_vector(op.D, 0), device=ctx.torch_device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, U, r, rep, status = pk.solve(op, x0, 50, 0.5, "normalized", allow_partial=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"qsun solve: {dt:.1f}s {status} K={rep['K']} iters={rep['iters']}")
+    return {"eigenpairs_per_s": round(len(ev) / dt, 3) if status == "OK" else None,
+            "solve_s": round(dt, 2), "status": status, "K": rep["K"], "iters": rep["iters"],
+            "max_resid": float(r.max().item()) if len(r) else None, "D": op.D,
+            "workload": "quantum sun N=3 (GOE dot, gamma=1) + L=13, g0=1, alpha=0.75, "
+                        "seed 0, 50 pairs at normalized energy 0.5, FP64"}
 
 
 def solve_legs(pk, wl, ctx, L, n_ev):
@@ -343,14 +400,16 @@ def main():
     step_bytes = 4 * 8 * D
     value = K * step_bytes / (ms_per_step / 1e3) / 1e9
 
-    # roofline of the fused Clenshaw step kernel
+    # roofline of the fused Clenshaw step kernel (the variant the autotuner
+    # picked for this operator)
     avg_ms, min_ms = pk.profile_step(op, pk.FP64, args.profile_iters)
+    kernel_name = step_kernel_name(op, pk.FP64, "double", args.L)
     achieved = step_bytes / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(),
-                "kernel": f"k_chain_split<double, {args.L}>",
+                "traffic": measured_traffic(kernel_name),
+                "kernel": kernel_name,
                 "kernel_ms_avg": round(avg_ms, 5), "kernel_ms_min": round(min_ms, 5),
                 "bytes_per_launch": step_bytes}
     log(f"step kernel {avg_ms * 1e3:.2f} us avg -> {achieved:.0f} GB/s")
@@ -378,6 +437,7 @@ def main():
         sl = solve_legs(pk, wl, ctx, args.solve_L, args.n_ev)
         out["eigenpairs_per_s"] = {"value": sl["fp64"]["eigenpairs_per_s"],
                                    "unit": "eigenpairs/s", **sl}
+        out["qsun"] = qsun_leg(pk, wl, ctx)
     if not args.no_serve:
         sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
                          args.serve_cols, pk.FP64 if args.serve_fp64 else pk.FP32)

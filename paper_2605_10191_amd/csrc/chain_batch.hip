@@ -7,7 +7,9 @@
 //
 // The row decoding of the split layout (low part, neighbour positions,
 // activity of the joining and periodic bonds, the interaction part of the
-// diagonal) is done once per segment and reused by every column.  Only the
+// diagonal) is done once per segment and reused by every column.  Each lane
+// holds two adjacent rows, so the coalesced accesses move both in one
+// 16-byte instruction.  Only the
 // field part of the diagonal is per column: the sum over the low bits comes
 // from two 32-entry LDS tables per column (bits 0-4 and 5-9) and the sum over
 // the high bits plus the constant is one wave-uniform value per segment and
@@ -32,9 +34,7 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
   constexpr int NLO = 1 << Lb;
   constexpr int NH = Lh - 1;
   constexpr int NL = Lb - 1;
-  constexpr int RALL = kChainSegRows / 64;  // rows per lane in a segment
-  constexpr int RPL = 2;                     // rows per lane and pass
-  constexpr int SPL = kChainStageRows / 64;
+  constexpr int SPL2 = kChainStageRows / 128;  // staged row pairs per lane
   constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
   constexpr int CHUNKS = BLOB / 16;
   constexpr uint32_t TB = sizeof(T);
@@ -79,14 +79,15 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
     const int bs = (cur.flags >> 2) & 1023, st = (cur.flags >> 12) & 1023;
     const int blk0 = cur.row0 - st;
     const uint32_t so_blk = (uint32_t)blk0 * TB, so_row = (uint32_t)cur.row0 * TB;
-    // per-row decoding shared by all columns
-    int jj[RALL], lo[RALL], gj[RALL], gp[RALL];
-    u4 np[RALL];
-    bool act_j[RALL], act_p[RALL];
-    T zz[RALL], nidle[RALL];
+    // per-row decoding shared by all columns: lane l holds the adjacent rows
+    // 2l and 2l + 1 (clamped into the segment)
+    int jj[2], lo[2], gj[2], gp[2];
+    u4 np[2];
+    bool act_j[2], act_p[2];
+    T zz[2], nidle[2];
 #pragma unroll
-    for (int i = 0; i < RALL; ++i) {
-      jj[i] = min(lane + 64 * i, cur.len - 1);
+    for (int i = 0; i < 2; ++i) {
+      jj[i] = min(2 * lane + i, cur.len - 1);
       const int l = s_lo[cur.lidx + jj[i]];
       lo[i] = l;
       np[i] = s_np[l];
@@ -94,13 +95,15 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
       act_p[i] = c.periodic && ((l & 1) != hitop);
       const int rj = (int)((np[i][2] >> 8) & 255u);
       const int rp = (int)((np[i][2] >> 16) & 255u);
-      gj[i] = act_j[i] ? blk0 + cur.d_join + rj : cur.row0 + jj[i];
-      gp[i] = act_p[i] ? blk0 + cur.d_pbc + rp : cur.row0 + jj[i];
+      gj[i] = blk0 + cur.d_join + rj;
+      gp[i] = blk0 + cur.d_pbc + rp;
       const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
       nidle[i] = (T)(NL - __popc(xlo));
       const int n11x = ((l >> (Lb - 1)) & 1 & hi0) + (c.periodic ? (hitop & l & 1) : 0);
       zz[i] = vzz * (T)(__popc(l & (l >> 1)) + n11x);
     }
+    const uint32_t pair_off = (uint32_t)(2 * lane) * TB;
+    const int r0 = 2 * lane;
 #pragma unroll 1
     for (int cc = 0; cc < ncols; ++cc) {
       const int col = col0 + cc;
@@ -112,55 +115,67 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
       const rsrc_t rv = make_rsrc(v ? v + coff : nullptr, v ? vbytes : 0);
       const rsrc_t rb2 = make_rsrc(b2 ? b2 + coff : nullptr, b2 ? vbytes : 0);
       const rsrc_t rout = make_rsrc(out + coff, vbytes);
-      T stg[SPL];
+      T sg[SPL2][2];
 #pragma unroll
-      for (int m = 0; m < SPL; ++m)
-        stg[m] = 64 * m < bs ? bload<T>(rb1, (uint32_t)min(lane + 64 * m, bs - 1) * TB, so_blk)
-                             : T(0);
-      const T* fa = s_fab + cc * 64;
-      for (int pass = 0; pass < RALL / RPL; ++pass) {
-        if (pass * 128 >= cur.len) break;
-        T g_hi[RPL][NH > 0 ? NH : 1], g_j[RPL], g_p[RPL], vv[RPL], bt[RPL];
+      for (int m = 0; m < SPL2; ++m) {
+        if (128 * m < bs)
+          bload2<T>(rb1, pair_off + (uint32_t)(128 * m) * TB, so_blk, sg[m][0], sg[m][1]);
+        else
+          sg[m][0] = sg[m][1] = T(0);
+      }
+      T g_hi[NH > 0 ? NH : 1][2], g_j[2], g_p[2], vv[2], bt[2];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const int r = RPL * pass + i;
-          const uint32_t off = (uint32_t)jj[r] * TB;
+      for (int b = 0; b < NH; ++b) {
+        if (cur.dh[b] != 0)
+          bload2<T>(rb1, pair_off, (uint32_t)(cur.row0 + cur.dh[b]) * TB, g_hi[b][0], g_hi[b][1]);
+        else
+          g_hi[b][0] = g_hi[b][1] = T(0);
+      }
 #pragma unroll
-          for (int b = 0; b < NH; ++b)
-            g_hi[i][b] = cur.dh[b] != 0
-                             ? bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB)
-                             : T(0);
-          g_j[i] = act_j[r] ? bload<T>(rb1, (uint32_t)gj[r] * TB, 0) : T(0);
-          g_p[i] = act_p[r] ? bload<T>(rb1, (uint32_t)gp[r] * TB, 0) : T(0);
-          vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
-          bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
-        }
-        if (pass == 0) {
-          wave_sync();
+      for (int i = 0; i < 2; ++i) {
+        g_j[i] = act_j[i] ? bload<T>(rb1, (uint32_t)gj[i] * TB, 0) : T(0);
+        g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)gp[i] * TB, 0) : T(0);
+      }
+      if (v)
+        bload2<T, kAuxNT>(rv, pair_off, so_row, vv[0], vv[1]);
+      else
+        vv[0] = vv[1] = T(0);
+      if (b2)
+        bload2<T, kAuxNT>(rb2, pair_off, so_row, bt[0], bt[1]);
+      else
+        bt[0] = bt[1] = T(0);
+      wave_sync();  // the previous column's (or segment's) LDS reads are done
 #pragma unroll
-          for (int m = 0; m < SPL; ++m)
-            if (64 * m < bs) stage[min(lane + 64 * m, bs - 1)] = stg[m];
-          wave_sync();
-        }
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const int r = RPL * pass + i;
-          const int l = lo[r];
-          const T bo = stage[st + jj[r]];
-          T hop = 0;
-#pragma unroll
-          for (int b = 0; b < NL; ++b) hop += stage[(np[r][b >> 2] >> (8 * (b & 3))) & 255u];
-#pragma unroll
-          for (int b = 0; b < NH; ++b) hop += g_hi[i][b];
-          hop -= nidle[r] * bo;
-          hop += act_j[r] ? g_j[i] : T(0);
-          const T dg = zz[r] + fa[l & 31] + fa[32 + (l >> 5)] + dsg;
-          const T acc = dg * bo + t_in * hop + (act_p[r] ? t_pb * g_p[i] : T(0));
-          T o = sig * acc + ta * bo - bt[i];
-          if (v) o += ac * vv[i];
-          bstore<kAuxNT>(o, rout, (uint32_t)jj[r] * TB, so_row);
+      for (int m = 0; m < SPL2; ++m) {
+        const int r = 128 * m + 2 * lane;
+        if (r < bs) {
+          stage[r] = sg[m][0];
+          if (r + 1 < bs) stage[r + 1] = sg[m][1];
         }
       }
+      wave_sync();
+      const T* fa = s_fab + cc * 64;
+      T o[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int l = lo[i];
+        const T bo = stage[st + jj[i]];
+        T hop = 0;
+#pragma unroll
+        for (int b = 0; b < NL; ++b) hop += stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+#pragma unroll
+        for (int b = 0; b < NH; ++b) hop += g_hi[b][i];
+        hop -= nidle[i] * bo;
+        hop += act_j[i] ? g_j[i] : T(0);
+        const T dg = zz[i] + fa[l & 31] + fa[32 + (l >> 5)] + dsg;
+        const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+        o[i] = sig * acc + ta * bo - bt[i];
+        if (v) o[i] += ac * vv[i];
+      }
+      if (r0 + 1 < cur.len)
+        bstore2<kAuxNT>(o[0], o[1], rout, pair_off, so_row);
+      else if (r0 < cur.len)
+        bstore<kAuxNT>(o[0], rout, pair_off, so_row);
     }
   }
 }
