@@ -491,7 +491,8 @@ static void launch_pair(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
 // so the low-part hops, the joining bond (high bit 0) and the KT - 1 bonds
 // inside the tile's high bits are LDS reads; only the bonds among the
 // remaining high bits and the periodic bond gather from global memory.  The
-// tile's segments are shared among the workgroup's wavefronts.
+// tile's segments are shared among the workgroup's wavefronts; each lane
+// holds two adjacent rows, as in the paired kernel.
 template <typename T, int L, int KT>
 __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
     ChainSplitDev c, T sigma, T tau, T a, const T* __restrict__ v,
@@ -503,7 +504,6 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
   constexpr int NH = Lh - 1;   // bonds inside the high part
   constexpr int NHL = KT - 1;  // of which inside the tile: b < NHL
   constexpr int NL = Lb - 1;
-  constexpr int RPL = kChainSegRows / 64;
   constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
   constexpr int CHUNKS = BLOB / 16;
   constexpr uint32_t TB = sizeof(T);
@@ -534,20 +534,24 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
     const int trow0 = tiles[4 * t], trows = tiles[4 * t + 1];
     const int tseg0 = tiles[4 * t + 2], tnseg = tiles[4 * t + 3];
     __syncthreads();  // the previous tile's LDS reads are done (and the tables)
-    {
+    {  // two rows per thread and access; rows past the tile are not stored
       constexpr int U = 4;
       const uint32_t so = (uint32_t)trow0 * TB;
-      for (int i0 = 0; i0 < trows; i0 += U * kTileThreads) {
-        T x[U];
+      for (int i0 = 0; i0 < trows; i0 += 2 * U * kTileThreads) {
+        T x[U][2];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kTileThreads + (int)threadIdx.x;
-          x[u] = i < trows ? bload<T>(rb1, (uint32_t)i * TB, so) : T(0);
+          const int i = i0 + 2 * (u * kTileThreads + (int)threadIdx.x);
+          if (i < trows)
+            bload2<T>(rb1, (uint32_t)i * TB, so, x[u][0], x[u][1]);
+          else
+            x[u][0] = x[u][1] = T(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kTileThreads + (int)threadIdx.x;
-          if (i < trows) s_tile[i] = x[u];
+          const int i = i0 + 2 * (u * kTileThreads + (int)threadIdx.x);
+          if (i < trows) s_tile[i] = x[u][0];
+          if (i + 1 < trows) s_tile[i + 1] = x[u][1];
         }
       }
     }
@@ -559,31 +563,45 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
       const int blk0 = cur.row0 - st;
       const int lrow0 = cur.row0 - trow0, lblk0 = blk0 - trow0;
       const uint32_t so_row = (uint32_t)cur.row0 * TB;
-      int jj[RPL], lo[RPL];
-      u4 np[RPL];
-      bool act_j[RPL], act_p[RPL];
-      T g_hi[RPL][NH - NHL > 0 ? NH - NHL : 1], g_p[RPL], vv[RPL], bt[RPL];
+      const uint32_t pair_off = (uint32_t)(2 * lane) * TB;
+      // lane l holds the adjacent rows 2l and 2l + 1 (clamped into the segment)
+      int jj[2], lo[2];
+      u4 np[2];
+      bool act_j[2], act_p[2];
+      T g_hi[NH - NHL > 0 ? NH - NHL : 1][2], g_p[2], vv[2], bt[2];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        jj[i] = min(lane + 64 * i, cur.len - 1);
+      for (int i = 0; i < 2; ++i) {
+        jj[i] = min(2 * lane + i, cur.len - 1);
         const int l = s_lo[cur.lidx + jj[i]];
         lo[i] = l;
         np[i] = s_np[l];
         act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
         act_p[i] = c.periodic && ((l & 1) != hitop);
-        const uint32_t off = (uint32_t)jj[i] * TB;
-#pragma unroll
-        for (int b = NHL; b < NH; ++b)
-          g_hi[i][b - NHL] = cur.dh[b] != 0
-                                 ? bload<T>(rb1, off, (uint32_t)(cur.row0 + cur.dh[b]) * TB)
-                                 : T(0);
-        const int rp = (int)((np[i][2] >> 16) & 255u);
-        g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_pbc + rp) * TB, 0) : T(0);
-        vv[i] = v ? bload<T, kAuxNT>(rv, off, so_row) : T(0);
-        bt[i] = b2 ? bload<T, kAuxNT>(rb2, off, so_row) : T(0);
       }
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
+      for (int b = NHL; b < NH; ++b) {
+        if (cur.dh[b] != 0)
+          bload2<T>(rb1, pair_off, (uint32_t)(cur.row0 + cur.dh[b]) * TB, g_hi[b - NHL][0],
+                    g_hi[b - NHL][1]);
+        else
+          g_hi[b - NHL][0] = g_hi[b - NHL][1] = T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int rp = (int)((np[i][2] >> 16) & 255u);
+        g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_pbc + rp) * TB, 0) : T(0);
+      }
+      if (v)
+        bload2<T, kAuxNT>(rv, pair_off, so_row, vv[0], vv[1]);
+      else
+        vv[0] = vv[1] = T(0);
+      if (b2)
+        bload2<T, kAuxNT>(rb2, pair_off, so_row, bt[0], bt[1]);
+      else
+        bt[0] = bt[1] = T(0);
+      T o[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
         const int l = lo[i];
         const int lr = lrow0 + jj[i];
         const T bo = s_tile[lr];
@@ -597,17 +615,21 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
         for (int b = 0; b < NHL; ++b)
           if (cur.dh[b] != 0) hop += s_tile[lr + cur.dh[b]];
 #pragma unroll
-        for (int b = NHL; b < NH; ++b) hop += g_hi[i][b - NHL];
+        for (int b = NHL; b < NH; ++b) hop += g_hi[b - NHL][i];
         const int rj = (int)((np[i][2] >> 8) & 255u);
         if (act_j[i]) hop += s_tile[lblk0 + cur.d_join + rj];
         const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
         const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
         const T dg = s_dlo[l] + (T)cur.dhi + vzz * (T)n11x;
         const T acc = dg * bo + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
-        T o = sigma * acc + tau * bo - bt[i];
-        if (v) o += a * vv[i];
-        bstore<kAuxNT>(o, rout, (uint32_t)jj[i] * TB, so_row);
+        o[i] = sigma * acc + tau * bo - bt[i];
+        if (v) o[i] += a * vv[i];
       }
+      const int r0 = 2 * lane;
+      if (r0 + 1 < cur.len)
+        bstore2<kAuxNT>(o[0], o[1], rout, pair_off, so_row);
+      else if (r0 < cur.len)
+        bstore<kAuxNT>(o[0], rout, pair_off, so_row);
     }
   }
 }
