@@ -29,8 +29,9 @@ Beside it the JSON line carries
                 plain FP64 and FP32 bulk + FP64 refinement, with the FP32
                 result's error per eigenpair against the FP64 one;
   serving       a Poisson stream of XXZ requests (L in 14, 16, 18; W in 1,
-                3, 5; 50 pairs each) through the continuous-batching server:
-                p50 / p99 latency and throughput;
+                3, 5; 50 pairs each) through the continuous-batching server,
+                FP32 bulk (the workload's precision) and the same stream in
+                FP64: p50 / p99 latency and throughput;
   cpu_baseline  the CPU oracle's Clenshaw steps at L=24 on a bounded sample.
 """
 from __future__ import annotations
@@ -243,9 +244,9 @@ def solve_legs(pk, wl, ctx, L, n_ev):
     return res
 
 
-def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7):
-    """A Poisson stream through the server; arrival rate = measured
-    single-stream capacity (mean service time of one request per L)."""
+def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate=1.0):
+    """A Poisson stream through the server; arrival rate = `rate` times the
+    measured single-stream capacity (mean service time of one request per L)."""
     import torch
     n_ev = 50
 
@@ -266,7 +267,7 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7):
         svc.append(time.perf_counter() - t0)
         log(f"serving capacity: L={L} alone {svc[-1]:.2f}s {st} K={rep['K']} iters={rep['iters']}")
     mean_svc = float(np.mean(svc))
-    stream = wl.serving_stream(n_req, seed, mean_svc)
+    stream = wl.serving_stream(n_req, seed, mean_svc / rate)
     reqs = []
     with pk.Server(ctx, int(budget_gb * (1 << 30)), max_cols=max_cols) as srv:
         t_start = time.perf_counter()
@@ -298,10 +299,12 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7):
             "mean_ms": round(1e3 * float(lat.mean()), 1),
             "throughput_req_per_s": round(n_req / (t_end - t_start), 3),
             "single_stream_service_s": [round(x, 3) for x in svc],
-            "arrival_rate_per_s": round(1.0 / mean_svc, 3),
+            "arrival_rate_per_s": round(rate / mean_svc, 3),
+            "max_queue_s": round(max(res[3]["t_queue"] for res in results), 3),
+            "fp32_fallbacks": int(sum(res[3]["fp32_fallback"] for res in results)),
             "hbm_budget_GiB": budget_gb, "max_cols": max_cols,
-            "stream": "L in {14,16,18}, W in {1,3,5} uniform, Poisson arrivals at the "
-                      "single-stream capacity"}
+            "stream": "L in {14,16,18}, W in {1,3,5} uniform, Poisson arrivals at "
+                      f"{rate:g}x the single-stream capacity"}
 
 
 def main():
@@ -319,10 +322,12 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=300)
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     ap.add_argument("--serve-cols", type=int, default=16)
-    ap.add_argument("--serve-fp64", action="store_true")
+    ap.add_argument("--serve-fp32-only", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1.0,
+                    help="arrival rate as a multiple of the single-stream capacity")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the step kernel and a plain copy (counter runs)")
     args = ap.parse_args()
@@ -440,10 +445,15 @@ def main():
         out["qsun"] = qsun_leg(pk, wl, ctx)
     if not args.no_serve:
         sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
-                         args.serve_cols, pk.FP64 if args.serve_fp64 else pk.FP32)
+                         args.serve_cols, pk.FP32, rate=args.serve_rate)
         out["p50_p99_batched_solve_ms"] = [sv["p50_ms"], sv["p99_ms"]]
         out["serving"] = sv
         log(f"serving: {sv}")
+        if not args.serve_fp32_only:
+            sv64 = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
+                               args.serve_cols, pk.FP64, rate=args.serve_rate)
+            out["serving_fp64"] = sv64
+            log(f"serving fp64: {sv64}")
     else:
         out["p50_p99_batched_solve_ms"] = None
 

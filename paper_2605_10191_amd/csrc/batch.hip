@@ -91,7 +91,30 @@ bool BatchFilter::same_members(const std::vector<SolveRun*>& runs) const {
   return true;
 }
 
+void BatchFilter::drain() {
+  for (auto& pd : pending) {
+    HIPC(hipEventSynchronize(pd.e1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, pd.e0, pd.e1));
+    for (auto* r : pd.runs) r->R.t_filter += 1e-3 * ms / (double)pd.runs.size();
+    HIPC(hipEventDestroy(pd.e0));
+    HIPC(hipEventDestroy(pd.e1));
+  }
+  pending.clear();
+}
+
+void BatchFilter::forget() {
+  for (auto& pd : pending) {
+    (void)hipEventDestroy(pd.e0);
+    (void)hipEventDestroy(pd.e1);
+  }
+  pending.clear();
+}
+
+BatchFilter::~BatchFilter() { forget(); }
+
 void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
+  drain();
   ctx = c;
   members = runs;
   ids.clear();
@@ -131,7 +154,9 @@ void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
 
 // One filter application for every member: gather v_k of each member into
 // the block, run the recurrence, scatter P(H~) v_k into each member's w.
-double BatchFilter::run() {
+// Only the two applications that choose between direct launches and a graph
+// wait for the device; the others are timed when drained.
+void BatchFilter::run() {
   hipStream_t s = ctx->stream;
   const int nb = (int)members.size();
   const int64_t D = bt.ops[0]->D;
@@ -172,6 +197,14 @@ double BatchFilter::run() {
                           (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   HIPC(hipEventRecord(e1, s));
+  for (auto* r : members) {
+    r->R.filter_steps += r->pl.K;
+    r->R.filter_bytes += r->pl.K * (fp32 ? 16.0 : 32.0) * (double)D;
+  }
+  if (mode != kTimeDirect && mode != kTimeGraph) {
+    pending.push_back({e0, e1, members});
+    return;
+  }
   HIPC(hipEventSynchronize(e1));
   float ms = 0;
   HIPC(hipEventElapsedTime(&ms, e0, e1));
@@ -188,12 +221,7 @@ double BatchFilter::run() {
       std::fprintf(stderr, "[polfed] batch filter nb=%d K=%d: direct %.3f ms, graph %.3f ms -> %s\n",
                    nb, co.Kmax, t_direct_ms, ms, mode == kGraph ? "graph" : "direct");
   }
-  for (auto* r : members) {
-    r->R.t_filter += t / nb;
-    r->R.filter_steps += r->pl.K;
-    r->R.filter_bytes += r->pl.K * (fp32 ? 16.0 : 32.0) * (double)D;
-  }
-  return t;
+  for (auto* r : members) r->R.t_filter += t / nb;
 }
 
 polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
@@ -228,9 +256,12 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
       for (auto* r : now[g]) r->advance();
     }
   }
+  for (auto& f : bf) f.drain();
   polfed_status st = POLFED_OK;
   for (int i = 0; i < B; ++i) {
-    if (rep) rep[i] = runs[i]->R;
+    polfed_report& R = runs[i]->R;
+    R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
+    if (rep) rep[i] = R;
     if (runs[i]->status != POLFED_OK) st = POLFED_NOT_CONVERGED;
   }
   return st;

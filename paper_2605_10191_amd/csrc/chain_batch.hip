@@ -228,7 +228,7 @@ void ChainBatch::init(polfed_ctx* c, const polfed_op* const* o, int n) {
     REQUIRE(ops[i]->pattern_key == op0->pattern_key,
             "batch: operators must share the off-diagonal pattern (model, L, N, boundary, "
             "couplings)");
-    REQUIRE(ops[i]->ctx == c, "batch: operator belongs to another context");
+    REQUIRE(ops[i]->ctx == op0->ctx, "batch: operators belong to different contexts");
   }
   REQUIRE(op0->split_nseg > 0, "batch: chain length outside 4..28");
   const int64_t nseg = op0->split_nseg;

@@ -60,10 +60,44 @@ struct Server {
     BatchFilter bf;
   };
   std::map<std::string, Group> groups;
+  // one child context (own stream) per chain pattern, so that groups of
+  // different patterns overlap on the device
+  std::map<std::string, polfed_ctx*> children;
+  polfed_ctx* child_for(const polfed_req* r);
+  ~Server();
   void loop();
   void admit();
   void complete(polfed_req* r, polfed_status st, const std::string& err);
 };
+
+static std::string pattern_of(const polfed_op* op) {
+  const bool batchable = op->model == Model::Chain && !op->pattern_key.empty() &&
+                         op->split_nseg > 0;
+  return batchable ? op->pattern_key : std::string("other");
+}
+
+polfed_ctx* Server::child_for(const polfed_req* r) {
+  const std::string key = pattern_of(r->op);
+  auto it = children.find(key);
+  if (it != children.end()) return it->second;
+  auto c = std::make_unique<polfed_ctx>();
+  c->device = ctx->device;
+  c->n_cu = ctx->n_cu;
+  HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  c->own_stream = true;
+  HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  return children[key] = c.release();
+}
+
+Server::~Server() {
+  for (auto& kv : children) {
+    polfed_ctx* c = kv.second;
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamDestroy(c->stream);
+    (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+  }
+}
 
 static std::string group_key(const polfed_req* r) {
   const polfed_op* op = r->op;
@@ -104,8 +138,15 @@ void Server::admit() {
     }
     r->t_admit = now_seconds();
     try {
+      polfed_ctx* cc = child_for(r);
+      // the start vector was written on the caller's stream
+      hipEvent_t ready;
+      HIPC(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      HIPC(hipEventRecord(ready, ctx->stream));
+      HIPC(hipStreamWaitEvent(cc->stream, ready, 0));
+      HIPC(hipEventDestroy(ready));
       r->run.reset(new SolveRun());
-      r->run->setup(ctx, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
+      r->run->setup(cc, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
       active.push_back(r);
     } catch (const Error& e) {
       {
@@ -149,29 +190,35 @@ void Server::loop() {
         } else {
           // rebuilt whenever a member joined or left (a new solve may reuse
           // a finished one's address, so members are compared by uid)
-          if (!g.bf.same_members(runs)) g.bf.form(ctx, runs);
+          if (!g.bf.same_members(runs)) g.bf.form(runs[0]->ctx, runs);
           g.bf.run();
         }
       } catch (const Error& e) {
+        g.bf.forget();
         for (auto* r : kv.second) {
           complete(r, e.code, e.what());
           retired.push_back(r);
         }
         continue;
       }
+      std::vector<std::pair<polfed_req*, std::pair<polfed_status, std::string>>> fin;
       for (auto* r : kv.second) {
         try {
           r->run->advance();
-          if (r->run->done) {
-            complete(r, r->run->status, "");
-            retired.push_back(r);
-          }
+          if (r->run->done) fin.push_back({r, {r->run->status, ""}});
         } catch (const Error& e) {
-          complete(r, e.code, e.what());
-          retired.push_back(r);
+          fin.push_back({r, {e.code, e.what()}});
         } catch (const std::exception& e) {
-          complete(r, POLFED_ERR_INVALID, e.what());
-          retired.push_back(r);
+          fin.push_back({r, {POLFED_ERR_INVALID, e.what()}});
+        }
+      }
+      if (!fin.empty()) {
+        g.bf.drain();  // the filter timings of the leaving members
+        for (auto& f : fin) {
+          polfed_report& R = f.first->run->R;
+          R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
+          complete(f.first, f.second.first, f.second.second);
+          retired.push_back(f.first);
         }
       }
     }
@@ -223,6 +270,9 @@ polfed_status serve_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_pa
   r->evecs = evecs;
   r->resid = resid;
   r->footprint = fp;
+  // the server's loop enqueues for many groups: a filter application is one
+  // graph replay unless the caller asked for direct launches
+  if (r->p.graph == 0) r->p.graph = 1;
   r->t_submit = now_seconds();
   {
     std::lock_guard<std::mutex> lk(s->m);

@@ -162,8 +162,19 @@ struct BatchFilter {
   ChainBatch bt;
   BatchCoef co;
   DevBuf vb, wb, bA, bB;  // D x nb blocks
+  // filter applications whose timing is still to be read: events and the
+  // members they served (alive until drain(), which callers invoke before a
+  // member is retired or the batch is re-formed)
+  struct Pending {
+    hipEvent_t e0, e1;
+    std::vector<SolveRun*> runs;
+  };
+  std::vector<Pending> pending;
   void form(polfed_ctx* c, const std::vector<SolveRun*>& runs);
-  double run();  // filters v_k of every member into its w; seconds
+  void run();    // filters v_k of every member into its w (asynchronous)
+  void drain();   // adds the finished applications' time to the members
+  void forget();  // drops the pending timings (after an error)
+  ~BatchFilter();
 };
 
 }  // namespace polfed
