@@ -357,7 +357,10 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   HIPC(hipStreamSynchronize(s));
   const double tr1 = tr[0] / (double)D, tr2 = tr[1] / (double)D;
   lam = target_energy(p.target_kind, p.target, E_min, E_max);
-  n_want = (int)std::min<int64_t>(D, p.n_ev + buffer_size(p.n_ev));
+  // FP32 bulk keeps twice the buffer: the window edge moves away from the
+  // wanted pairs, whose refinement then converges in about two sweeps (the
+  // wider window also lowers K, so the Lanczos work stays about the same)
+  n_want = (int)std::min<int64_t>(D, p.n_ev + (fp32 ? 2 : 1) * buffer_size(p.n_ev));
   n_want0 = n_want;
   pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega, p.K_override);
   a.assign(pl.K + 1, 0.0);
@@ -394,7 +397,8 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
 
 size_t SolveRun::footprint(const polfed_op* op, const polfed_params& p) {
   const int n_ev = std::max(1, p.n_ev);
-  const int n_want = (int)std::min<int64_t>(op->D, n_ev + buffer_size(n_ev));
+  const int g = (p.precision == POLFED_FP32 ? 2 : 1) * buffer_size(n_ev);
+  const int n_want = (int)std::min<int64_t>(op->D, n_ev + g);
   const int M = expected_krylov_dim(n_want, 1, p.eta > 0 ? p.eta : 1.5);
   const size_t D = (size_t)op->D;
   // basis, the work vectors and the extraction blocks (U, HU, U2, HU2)
@@ -613,6 +617,7 @@ void SolveRun::advance() {
 void SolveRun::fallback_fp64() {
   const int64_t D = op->D;
   fp32 = false;
+  // the FP64 restart keeps the plan (and window) of the FP32 run
   R.fp32_fallback = 1;
   tol_ritz = 1e-10;
   graph.reset();
