@@ -83,6 +83,8 @@ def step_kernel_name(op, prec, tname: str, L: int) -> str:
     kt = min(5, L - Lb - 9)
     if var == 3:
         return f"k_chain_pair<{tname}, {L}>"
+    if var == 4:
+        return f"k_chain_split<{tname}, {L}, 2>"
     if var in (1, 2):
         return f"k_chain_tile<{tname}, {L}, {kt - (var - 1)}>"
     return f"k_chain_split<{tname}, {L}>"

@@ -150,7 +150,8 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage);
 /* Step-kernel variant of a matrix-free chain (XXZ, t-V) in one precision:
  * -1 = pick by timing on the next step (the default), 0 = segment kernel,
  * 1 = tile kernel with the largest tile, 2 = tile kernel with half that tile,
- * 3 = segment kernel with two adjacent rows per lane (16-byte accesses);
+ * 3 = segment kernel with two adjacent rows per lane (16-byte accesses),
+ * 4 = segment kernel with each segment split between two wavefronts;
  * -2 only reports the variant in use.
  * A variant that does not exist for the chain length (tiles need L >= 22)
  * gives POLFED_ERR_INVALID.  *chosen (may be NULL) receives the variant in

@@ -339,7 +339,7 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
   return guarded([&]() -> polfed_status {
     REQUIRE(op, "null operator");
     REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
-    REQUIRE(variant >= -2 && variant <= 3, "variant must be -2, -1, 0, 1, 2 or 3");
+    REQUIRE(variant >= -2 && variant <= 4, "variant must be -2 .. 4");
     const int pi = precision == POLFED_FP64 ? 0 : 1;
     if (variant == -2) {  // query only
       if (chosen) *chosen = op->tuned[pi];

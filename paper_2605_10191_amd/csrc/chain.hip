@@ -181,7 +181,10 @@ void build_chain_split(polfed_op* op) {
   HIPC(hipStreamSynchronize(s));
 }
 
-template <typename T, int L>
+// HALVES = 2 splits every segment between two wavefronts (64 rows each, one
+// row per lane): twice the independent wavefronts, each with half the
+// dependent work, for chains too short to fill the chip.
+template <typename T, int L, int HALVES = 1>
 __global__ __launch_bounds__(256) void k_chain_split(
     ChainSplitDev c, T sigma, T tau, T a, const T* __restrict__ v,
     const T* __restrict__ b1, const T* b2, T* out, int nxcd,
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(256) void k_chain_split(
   constexpr int NLO = 1 << Lb;
   constexpr int NH = Lh - 1;  // bonds inside the high part
   constexpr int NL = Lb - 1;  // bonds inside the low part
-  constexpr int RPL = 2;                      // rows per lane and pass
+  constexpr int RPL = 2 / HALVES;               // rows per lane and pass
   constexpr int kPasses = kChainSegRows / 128;  // passes per segment
   constexpr int SPL = kChainStageRows / 64;  // staged rows per lane
   constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
@@ -224,7 +227,8 @@ __global__ __launch_bounds__(256) void k_chain_split(
   // this XCD's contiguous share of the segments
   const int xcd = blockIdx.x % nxcd;
   const int blocks_x = gridDim.x / nxcd;
-  const int64_t s_begin = c.nseg * xcd / nxcd, s_end = c.nseg * (xcd + 1) / nxcd;
+  const int64_t nvirt = c.nseg * HALVES;  // (segment, half) work items
+  const int64_t s_begin = nvirt * xcd / nxcd, s_end = nvirt * (xcd + 1) / nxcd;
   const int wpb = blockDim.x >> 6;
   const int64_t wstride = (int64_t)blocks_x * wpb;
   const int lane = threadIdx.x & 63;
@@ -232,10 +236,13 @@ __global__ __launch_bounds__(256) void k_chain_split(
   const uint32_t vbytes = (uint32_t)(c.D * TB);
   const rsrc_t rb1 = make_rsrc(b1, vbytes), rv = make_rsrc(v, v ? vbytes : 0),
                rb2 = make_rsrc(b2, b2 ? vbytes : 0), rout = make_rsrc(out, vbytes);
-  int64_t si = s_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
-  if (si >= s_end) return;
-  for (; si < s_end; si += wstride) {
+  int64_t vi = s_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
+  if (vi >= s_end) return;
+  for (; vi < s_end; vi += wstride) {
+    const int64_t si = vi / HALVES;
+    const int half = (int)(vi % HALVES);
     const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform((int)si) * kChainRecWords);
+    if (half * 64 >= cur.len) continue;
     const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
     const int bs = (cur.flags >> 2) & 1023, st = (cur.flags >> 12) & 1023;
     const int blk0 = cur.row0 - st;
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(256) void k_chain_split(
     // the segment's rows in passes of 128 (two rows per lane); the block is
     // staged in LDS by the first pass
     for (int pass = 0; pass < kPasses; ++pass) {
-      const int p0 = pass * 128;
+      const int p0 = pass * 128 + half * 64;
       if (p0 >= cur.len) break;
       // rows of this lane, clamped into the segment (a clamped lane repeats
       // the last row and stores the same value)
@@ -637,7 +644,7 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
 // Launch shape: persistent blocks per CU and the XCD-contiguous mapping can
 // be overridden through POLFED_CHAIN_BPC and POLFED_CHAIN_XCD (0 = off).
 
-template <typename T, int L>
+template <typename T, int L, int HALVES = 1>
 static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
                          const T* v, const T* b1, const T* b2, T* out) {
   constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
@@ -646,7 +653,7 @@ static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a
   static const int xcd_map = env_int("POLFED_CHAIN_XCD", 1);
   const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) + 4 * kChainStageRows * sizeof(T);
   ChainSplitDev c = op->chain_split();
-  const int64_t blocks_needed = (c.nseg + 3) / 4;
+  const int64_t blocks_needed = (c.nseg * HALVES + 3) / 4;
   int64_t grid = std::min<int64_t>(blocks_needed, (int64_t)op->ctx->n_cu * bpc);
   int nxcd = 1;
   if (xcd_map && grid >= 64) {
@@ -654,7 +661,7 @@ static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a
     nxcd = 8;
   }
   grid = std::max<int64_t>(grid, 1);
-  hipLaunchKernelGGL((k_chain_split<T, L>), dim3((unsigned)grid), dim3(256), shm, s, c,
+  hipLaunchKernelGGL((k_chain_split<T, L, HALVES>), dim3((unsigned)grid), dim3(256), shm, s, c,
                      sigma, tau, a, v, b1, b2, out, nxcd, c.rec);
   HIPC(hipGetLastError());
 }
@@ -693,6 +700,10 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
     launch_pair<T, L>(s, op, sigma, tau, a, v, b1, b2, out);
     return true;
   }
+  if (var == 4) {
+    launch_split<T, L, 2>(s, op, sigma, tau, a, v, b1, b2, out);
+    return true;
+  }
   if constexpr (KT >= 2) {
     constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
     const auto& tl = op->tiles[var - 1];
@@ -721,7 +732,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   if (op->tuned[pi] >= 0) return op->tuned[pi];
   static const int allow_tile = env_int("POLFED_CHAIN_TILE", -1);
   if (allow_tile == 0) return op->tuned[pi] = 0;
-  if (allow_tile >= 1 && allow_tile <= 3) return op->tuned[pi] = allow_tile;
+  if (allow_tile >= 1 && allow_tile <= 4) return op->tuned[pi] = allow_tile;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return 0;
@@ -735,7 +746,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   HIPC(hipEventCreate(&e1));
   int best = 0;
   float best_ms = 1e30f;
-  for (int var = 0; var < 4; ++var) {
+  for (int var = 0; var < 5; ++var) {
     auto go = [&] {
       return launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(),
                                   bb2.as<T>(), bb2.as<T>());

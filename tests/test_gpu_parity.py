@@ -207,7 +207,7 @@ def test_large_chain_sampled_rows(pk, ctx):
 
 @pytest.mark.parametrize("L", [22, 23, 24])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, prec, variant):
     """Full-size Clenshaw steps of long chains with each step kernel (the
     segment kernel; tile kernels with 8/16/32 and 4/8/16 high parts per tile
@@ -269,7 +269,7 @@ CHAIN_OPS = [c for c in OPS if c[0] in ("xxz", "tv")]
 
 @pytest.mark.parametrize("case", CHAIN_OPS, ids=lambda c: "-".join(map(str, c)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("variant", [0, 3, 4])
 def test_chain_step_variants_match_oracle(pk, ctx, case, prec, variant):
     """Every row of a Clenshaw step with the segment kernel and the paired-row
     kernel (odd segment lengths, ragged blocks, open and periodic chains)."""
