@@ -3,8 +3,10 @@ with full reorthogonalization, and the eigenpair extraction.
 TEST INFRASTRUCTURE ONLY.
 
 Paper: Sec. 2.1 (eqs. lanczos_recurrence, lan_eigvecs, lan_criterion; full
-reorthogonalization), Sec. 4.3 (filtered Lanczos, extraction u_i = V t_i,
-E_i = <u_i|H|u_i>, residual norms) and Sec. 3.2 (E_min, E_max by Lanczos).
+reorthogonalization), Sec. 2.2 (block Lanczos: eqs.
+block_lanczos_reocurrence, blocklan_criterion), Sec. 4.3 (filtered (block)
+Lanczos, extraction u_i = V t_i, E_i = <u_i|H|u_i>, residual norms) and
+Sec. 3.2 (E_min, E_max by Lanczos).
 """
 from __future__ import annotations
 
@@ -161,6 +163,126 @@ def filtered_lanczos(H, apply_P, x0: np.ndarray, lam: float, n_ev: int,
                     return {"E": E[sel], "U": U2[:, sel], "res": res[sel],
                             "iters": k, "alpha": np.array(alpha),
                             "beta": np.array(beta), "V": V[:, :k + 1]}
+                if len(sel) >= n_ev and not ok:
+                    n_want = min(M_max, n_want + max(10, n_want // 5))
+            next_check = k + check_every
+
+
+# ------------------------------------------------------- block Lanczos ----
+
+def orthonormal_start_block(X0: np.ndarray) -> np.ndarray:
+    """The start block V_1: QR of the D x s matrix X0 (Sec. 2.2), with the
+    signs fixed so that R has a positive diagonal."""
+    Q, R = np.linalg.qr(X0)
+    sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return Q * sgn
+
+
+def block_lanczos_step(apply_op, V: np.ndarray, k: int, s: int):
+    """One block Lanczos step with full reorthogonalization (Sec. 2.2, Sec.
+    4.3).  V[:, :k+s] holds the orthonormal blocks V_1..V_j, the current one
+    being V_j = V[:, k:k+s].  W = A V_j; the diagonal block is the projection
+    A_j = V_j^T W; W is orthogonalized against all stored blocks (classical
+    Gram-Schmidt, two passes); QR of the result gives the next block and the
+    off-diagonal block B_{j+1}.  The QR is taken with a non-negative diagonal
+    of B_{j+1}, which makes it unique for a block of full rank.
+    Returns (A_j, B_next, V_next)."""
+    Vj = V[:, k:k + s]
+    W = apply_op(Vj)
+    A = Vj.T @ W
+    Q = V[:, :k + s]
+    for _ in range(2):
+        W = W - Q @ (Q.T @ W)
+    Vn, Bn = np.linalg.qr(W)
+    sgn = np.where(np.diag(Bn) < 0, -1.0, 1.0)
+    return A, sgn[:, None] * Bn, Vn * sgn
+
+
+def block_lanczos_matrix(As, Bs) -> np.ndarray:
+    """Block tridiagonal H_L (Sec. 2.2): diagonal blocks A_1..A_m
+    (symmetrized: symmetric in exact arithmetic), B_{j+1} below the diagonal
+    block j and B_{j+1}^T above it, for j < m."""
+    m = len(As)
+    s = As[0].shape[0]
+    T = np.zeros((m * s, m * s))
+    for j in range(m):
+        T[j * s:(j + 1) * s, j * s:(j + 1) * s] = 0.5 * (As[j] + As[j].T)
+        if j + 1 < m:
+            T[(j + 1) * s:(j + 2) * s, j * s:(j + 1) * s] = Bs[j]
+            T[j * s:(j + 1) * s, (j + 1) * s:(j + 2) * s] = Bs[j].T
+    return T
+
+
+def block_lanczos(apply_op, X0: np.ndarray, m: int):
+    """m block steps from the start block X0.  Returns (H_L, V, B_last):
+    V holds the m + 1 blocks, B_last = B_{m+1}."""
+    D, s = X0.shape
+    V = np.zeros((D, (m + 1) * s))
+    V[:, :s] = orthonormal_start_block(X0)
+    As, Bs = [], []
+    for j in range(m):
+        A, Bn, Vn = block_lanczos_step(apply_op, V, j * s, s)
+        As.append(A)
+        Bs.append(Bn)
+        V[:, (j + 1) * s:(j + 2) * s] = Vn
+    return block_lanczos_matrix(As, Bs), V, Bs[-1]
+
+
+def block_ritz(T: np.ndarray, B_last: np.ndarray):
+    """Eigenpairs (theta_j, t_j) of H_L and the residual estimates
+    ||B_{m+1} tau_mj|| of eq. blocklan_criterion, tau_mj being the last block
+    of s components of t_j."""
+    s = B_last.shape[0]
+    theta, Y = np.linalg.eigh(T)
+    est = np.linalg.norm(B_last @ Y[-s:, :], axis=0)
+    return theta, Y, est
+
+
+def filtered_block_lanczos(H, apply_P, X0: np.ndarray, lam: float, n_ev: int,
+                           n_want: int, M_alloc: int, P_at, E_c: float,
+                           dE: float, tol_P: float = 1e-10,
+                           tol_resid: float = 1e-8, M_max: int | None = None):
+    """Block Lanczos on the filtered operator P(H~) (Sec. 4.3, block size s =
+    number of columns of X0).  Checks (eq. blocklan_criterion) come at whole
+    blocks; the extraction, selection and completeness test are those of
+    filtered_lanczos.  A block that loses rank stops the iteration with an
+    error (cases that reach it are tested against the dense solver only).
+
+    Returns dict(E, U, res, iters)."""
+    D, s = X0.shape
+    if M_max is None:
+        M_max = min(D, 4 * M_alloc)
+    M_max = (min(M_max, D - s) // s) * s
+    n_want = min(n_want, M_max)
+    V = np.zeros((D, M_max + s))
+    V[:, :s] = orthonormal_start_block(X0)
+    As, Bs = [], []
+    check_every = max(10, int(math.ceil(0.05 * M_alloc)))
+    check_every = -(-check_every // s) * s
+    next_check = min(-(-n_want // s) * s, M_max)
+    k = 0
+    while True:
+        A, Bn, Vn = block_lanczos_step(apply_P, V, k, s)
+        if np.min(np.abs(np.diag(Bn))) <= 1e-13:
+            raise RuntimeError("block Lanczos: the next block lost rank")
+        As.append(A)
+        Bs.append(Bn)
+        V[:, k + s:k + 2 * s] = Vn
+        k += s
+        if k >= next_check or k >= M_max:
+            T = block_lanczos_matrix(As, Bs)
+            theta, Y, est = block_ritz(T, Bs[-1])
+            top = np.argsort(theta)[::-1][:n_want]
+            if np.all(est[top] <= tol_P * max(1.0, float(np.max(np.abs(theta))))) \
+                    or k >= M_max:
+                U = V[:, :k] @ Y[:, top]
+                E, U2, res = rayleigh_ritz(H, U)
+                sel = select_nearest(E, res, lam, n_ev, tol_resid)
+                ok = len(sel) >= n_ev and complete(
+                    E[sel], lam, float(np.min(theta[top])), P_at, E_c, dE)
+                if ok or k >= M_max:
+                    return {"E": E[sel], "U": U2[:, sel], "res": res[sel],
+                            "iters": k}
                 if len(sel) >= n_ev and not ok:
                     n_want = min(M_max, n_want + max(10, n_want // 5))
             next_check = k + check_every

@@ -70,7 +70,9 @@ def polfed(H, x0: np.ndarray, n_ev: int, target: float,
            K: int | None = None, tol_P: float = 1e-10,
            tol_resid: float = 1e-8, bounds=None):
     """N_ev eigenpairs of H nearest the target.  Returns a dict with E (sorted
-    by distance to lambda), U (columns), res, and the plan."""
+    by distance to lambda), U (columns), res, and the plan.  A vector x0
+    runs Lanczos; a D x s matrix x0 runs block Lanczos with block size s (the
+    shape of the start selects the variant)."""
     if bounds is None:
         E_min, E_max = lz.spectral_extremes(H)
     else:
@@ -87,10 +89,16 @@ def polfed(H, x0: np.ndarray, n_ev: int, target: float,
     def P_at(x_t):
         return flt.filter_value(x_t, p["lam_t"], p["K"])
 
-    M_alloc = flt.expected_krylov_dim(n_want, 1, eta)
-    out = lz.filtered_lanczos(H, apply_P, x0, lam, n_ev, n_want, M_alloc,
-                              P_at, p["E_c"], p["dE"],
-                              tol_P=tol_P, tol_resid=tol_resid)
+    s = 1 if x0.ndim == 1 else x0.shape[1]
+    M_alloc = flt.expected_krylov_dim(n_want, s, eta)
+    if x0.ndim == 1:
+        out = lz.filtered_lanczos(H, apply_P, x0, lam, n_ev, n_want, M_alloc,
+                                  P_at, p["E_c"], p["dE"],
+                                  tol_P=tol_P, tol_resid=tol_resid)
+    else:
+        out = lz.filtered_block_lanczos(H, apply_P, x0, lam, n_ev, n_want,
+                                        M_alloc, P_at, p["E_c"], p["dE"],
+                                        tol_P=tol_P, tol_resid=tol_resid)
     out.update({"lam": lam, "E_min": E_min, "E_max": E_max, "plan": p,
                 "M_alloc": M_alloc})
     return out
