@@ -276,6 +276,26 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
                                   double E_c, double dE, const double* a,
                                   int K, double* V, int k, double* alpha,
                                   double* beta, int precision);
+/* One block Lanczos step on the filtered operator (Sec. 2.2, eq.
+ * block_lanczos_reocurrence, with the filter of Sec. 4.3): W = P(H~) V_j
+ * for the current block V_j = columns k..k+s-1 of V (one multi-column
+ * Clenshaw recurrence for chain operators, s single ones otherwise), full
+ * reorthogonalization of W against columns 0..k+s-1 and its QR, which gives
+ * the next block (columns k+s..k+2s-1, written) and B_{j+1}.  Column c of W
+ * is orthogonalized by classical Gram-Schmidt applied twice against columns
+ * 0..k+s+c-1 and normalized (a Gram-Schmidt QR, positive diagonal).
+ * V: device basis, column-major D x (k+2s), columns 0..k+s-1 orthonormal,
+ * k a multiple of s, 1 <= s <= 64 and k + 2s <= D.
+ * A: device s x s column-major, A_j = V_j^T P(H~) V_j (as computed; not
+ * symmetrized).  Bn: device s x s column-major, upper triangular B_{j+1}.
+ * A column of W that has lost rank (norm <= 1e-13) is replaced by a random
+ * unit vector orthogonal to the basis, with a zero diagonal entry in Bn.
+ * precision selects the Clenshaw arithmetic.  Synchronizes (the diagonal of
+ * Bn is inspected on the host). */
+polfed_status polfed_block_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
+                                        double E_c, double dE, const double* a,
+                                        int K, double* V, int k, int s, double* A,
+                                        double* Bn, int precision);
 /* Measurement helper: times `iters` back-to-back launches of the fused
  * Clenshaw step kernel on scratch vectors with one pair of HIP events on the
  * context stream (mean = elapsed / iters, the rate of a running recurrence)
@@ -304,6 +324,8 @@ typedef struct {
   int refine_max;      /* FP32 bulk: at most this many refinement sweeps
                           (0: 16; -1: none); a refinement that stalls or
                           runs out hands the solve to the FP64 filter */
+  int block_size;      /* 0 or 1: Lanczos; s in 2..64: block Lanczos with
+                          blocks of s vectors (Sec. 2.2), polfed_solve only */
 } polfed_params;
 
 typedef struct {
@@ -322,7 +344,9 @@ typedef struct {
 
 polfed_status polfed_params_default(polfed_params* p);
 
-/* Synchronous solve.  x0: device start vector [D].  Outputs are caller
+/* Synchronous solve.  x0: device start vector [D], or with block_size s > 1
+ * the start block, column-major D x s of full rank (orthonormalized by a
+ * Gram-Schmidt QR, Sec. 2.2).  Outputs are caller
  * device buffers: evals[n_ev], evecs[D * n_ev] (column-major, unit norm),
  * resid[n_ev] = ||H u - E u||, ordered by (|E - lambda|, E).  *n_found gets
  * the number of valid pairs (n_ev on POLFED_OK, fewer with
@@ -335,7 +359,8 @@ polfed_status polfed_solve(polfed_ctx* ctx, const polfed_op* op,
 /* Batched solve of B realizations that share the off-diagonal pattern (same
  * model, L, N and couplings, different diagonal fields): the filter runs as
  * one multi-column recurrence.  Arrays of B pointers; each entry as in
- * polfed_solve.  n_found[B], rep[B] (rep may be NULL). */
+ * polfed_solve.  n_found[B], rep[B] (rep may be NULL).  block_size must be
+ * 0 or 1. */
 polfed_status polfed_solve_batch(polfed_ctx* ctx, int B,
                                  const polfed_op* const* ops,
                                  const polfed_params* params,
@@ -353,7 +378,7 @@ polfed_status polfed_serve_start(polfed_ctx* ctx, size_t hbm_budget_bytes,
                                  int max_cols);
 /* Queues a solve; op, x0 and the output buffers must stay alive until
  * polfed_wait returns.  Requests whose footprint exceeds the budget are
- * rejected (POLFED_ERR_REJECTED). */
+ * rejected (POLFED_ERR_REJECTED); block_size must be 0 or 1. */
 polfed_status polfed_submit(polfed_ctx* ctx, const polfed_op* op,
                             const polfed_params* params, const double* x0,
                             double* evals, double* evecs, double* resid,

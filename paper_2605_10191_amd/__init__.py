@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("tol_resid", ctypes.c_double),
                 ("bound_pad", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("E_min", ctypes.c_double), ("E_max", ctypes.c_double),
-                ("graph", ctypes.c_int), ("refine_max", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("refine_max", ctypes.c_int),
+                ("block_size", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -113,6 +114,7 @@ SIGNATURES = {
                                    _P, _P, _P, _I, _I],
     "polfed_bounds": [_P, _P, _P, _D, _I, _DP, _DP],
     "polfed_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _P, _P, _I],
+    "polfed_block_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _I, _P, _P, _I],
     "polfed_profile_step": [_P, _P, _I, _I, _DP, _DP],
     "polfed_params_default": [ctypes.POINTER(Params)],
     "polfed_solve": [_P, _P, ctypes.POINTER(Params), _P, _P, _P, _P,
@@ -472,6 +474,16 @@ def lanczos_step(op: Operator, E_c, dE, a, V, k, alpha, beta, precision=FP64):
                                     _ptr(beta), precision))
 
 
+def block_lanczos_step(op: Operator, E_c, dE, a, V, k, s, A, Bn, precision=FP64):
+    """One filtered block Lanczos step on the device basis V (a (k+2s, D)
+    tensor, rows = basis vectors); A and Bn are (s, s) device tensors that
+    receive A_j and B_{j+1} column-major (so A[c, i] is row i, column c)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    _check(_lib.polfed_block_lanczos_step(op.ctx.handle, op.handle, E_c, dE, _dptr(a),
+                                          len(a) - 1, _ptr(V), int(k), int(s), _ptr(A),
+                                          _ptr(Bn), precision))
+
+
 def profile_step(op: Operator, precision=FP64, iters=200):
     """(mean, min) milliseconds of the fused Clenshaw step kernel."""
     avg, mn = ctypes.c_double(), ctypes.c_double()
@@ -498,7 +510,17 @@ def solve(op: Operator, x0, n_ev, target, target_kind="normalized",
           precision=FP64, allow_partial=False, **kw):
     """N_ev eigenpairs of op nearest the target.  Returns
     (evals, evecs (D x n, column-major as a (n, D) tensor transposed), resid,
-    report dict, status)."""
+    report dict, status).  A start vector x0 of shape (D,) runs Lanczos; a
+    start block of shape (s, D) (rows = columns of the D x s block) runs block
+    Lanczos with block size s."""
+    if hasattr(x0, "dim") and x0.dim() == 2:
+        if kw.get("block_size", x0.shape[0]) != x0.shape[0]:
+            raise ValueError("block_size differs from the rows of the start block")
+        kw["block_size"] = int(x0.shape[0])
+        if not x0.is_contiguous():
+            raise ValueError("the start block must be contiguous")
+    elif kw.get("block_size", 1) > 1:
+        raise ValueError("block_size > 1 needs a start block of shape (s, D)")
     p = make_params(n_ev, target, target_kind, precision, **kw)
     ctx = op.ctx
     evals = ctx.empty(n_ev)

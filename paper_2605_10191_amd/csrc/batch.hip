@@ -139,7 +139,7 @@ void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
   graph.reset();
   graph_pref = runs[0]->p.graph;
   mode = kTimeDirect;
-  if (graph_pref == 2 || co.Kmax < 8) mode = kDirect;
+  if (graph_pref == 2 || co.Kmax < 8 || co.Kmax > kGraphMaxSteps) mode = kDirect;
   if (graph_pref == 1 && mode == kTimeDirect) mode = kGraph;
   const int64_t D = ops[0]->D;
   const size_t tb = fp32 ? sizeof(float) : sizeof(double);
@@ -230,6 +230,7 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
                           int* n_found, polfed_report* rep) {
   REQUIRE(B >= 1, "solve_batch: need B >= 1");
   REQUIRE(ops && x0 && evals && evecs && resid && n_found, "solve_batch: null array");
+  REQUIRE(p.block_size <= 1, "solve_batch: block Lanczos (block_size > 1) runs through polfed_solve only");
   for (int i = 0; i < B; ++i) {
     REQUIRE(ops[i] && ops[i]->ctx == ctx, "solve_batch: operator missing or of another context");
     REQUIRE(ops[i]->model == Model::Chain && !ops[i]->pattern_key.empty() &&

@@ -652,6 +652,24 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E
   });
 }
 
+polfed_status polfed_block_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c,
+                                        double dE, const double* a, int K, double* V, int k,
+                                        int s, double* A, double* Bn, int precision) {
+  return guarded([&]() -> polfed_status {
+    check_step_args(ctx, op, dE, precision);
+    REQUIRE(std::isfinite(E_c), "E_c must be finite");
+    REQUIRE(K >= 0 && a, "need K >= 0 and coefficients a[K+1]");
+    REQUIRE(s >= 1 && s <= 64, "need 1 <= s <= 64");
+    REQUIRE(k >= 0 && k % s == 0 && (int64_t)k + 2 * s <= op->D,
+            "need k >= 0 a multiple of s and k + 2 s <= D");
+    REQUIRE(V && A && Bn, "null buffer");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    block_lanczos_step(ctx, op, E_c, dE, a, K, V, k, s, A, Bn, precision);
+    return POLFED_OK;
+  });
+}
+
 polfed_status polfed_profile_step(polfed_ctx* ctx, const polfed_op* op, int precision,
                                   int iters, double* avg_ms, double* min_ms) {
   return guarded([&]() -> polfed_status {

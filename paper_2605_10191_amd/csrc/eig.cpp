@@ -77,15 +77,16 @@ void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
   Z.swap(Z2);
 }
 
-void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
-             std::vector<double>& Zout) {
-  // Work row-major on a symmetric copy (A is col-major; symmetric anyway).
-  std::vector<double> a((size_t)n * n);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j)
-      a[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
-  std::vector<double> Q((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+namespace {
+
+// Householder reduction of the symmetric row-major a to tridiagonal form,
+// a = Q T Q^T; Q keeps only its rows q0..n-1 ((n - q0) x n, row-major),
+// which start as the matching rows of the identity.
+void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Q, int q0,
+                    std::vector<double>& d, std::vector<double>& e) {
+  const int nq = n - q0;
+  Q.assign((size_t)nq * n, 0.0);
+  for (int i = 0; i < nq; ++i) Q[(size_t)i * n + q0 + i] = 1.0;
   std::vector<double> v(n), p(n), q(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of the column below the diagonal
@@ -123,7 +124,7 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
       a[(size_t)k * n + (k + 1 + i)] = 0.0;
     }
     // Q <- Q H on columns k+1..n-1
-    for (int r = 0; r < n; ++r) {
+    for (int r = 0; r < nq; ++r) {
       double* qr = &Q[(size_t)r * n + (k + 1)];
       double t = 0;
       for (int j = 0; j < m; ++j) t += qr[j] * v[j];
@@ -131,14 +132,41 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
       for (int j = 0; j < m; ++j) qr[j] -= t * v[j];
     }
   }
-  std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
+  d.assign(n, 0.0);
+  e.assign(n > 1 ? n - 1 : 0, 0.0);
   for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
   for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)(i + 1) * n + i];
+}
+
+std::vector<double> symmetric_copy(int n, const std::vector<double>& A) {
+  std::vector<double> a((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      a[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  return a;
+}
+
+}  // namespace
+
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
+             std::vector<double>& Zout) {
+  // Work row-major on a symmetric copy (A is col-major; symmetric anyway).
+  std::vector<double> a = symmetric_copy(n, A), Q, d, e;
+  tridiagonalize(n, a, Q, 0, d, e);
   tridiag_eig(n, d, e, Q, n);  // Q rows: components, columns: eigenvectors
   w = d;
   Zout.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) Zout[(size_t)j * n + i] = Q[(size_t)i * n + j];
+}
+
+void sym_eig_tail(int n, const std::vector<double>& A, int r, std::vector<double>& w,
+                  std::vector<double>& Ztail) {
+  std::vector<double> a = symmetric_copy(n, A), d, e;
+  r = std::min(std::max(r, 1), n);
+  tridiagonalize(n, a, Ztail, n - r, d, e);
+  tridiag_eig(n, d, e, Ztail, r);
+  w = d;
 }
 
 }  // namespace polfed

@@ -127,6 +127,9 @@ constexpr int kChainSegRows = 128;   // rows per wavefront segment
 constexpr int kChainStageRows = 256;  // LDS rows staged per wavefront
 constexpr int kChainBlocksPerCU = 4;  // persistent blocks per compute unit
 constexpr int kBatchMaxCols = 16;     // columns per multi-column launch
+// A filter of more Clenshaw steps than this runs as direct launches: a graph
+// of that many kernel nodes costs more to build than it saves.
+constexpr int kGraphMaxSteps = 65536;
 // Tile kernel: a workgroup stages 2^KT consecutive high-part blocks in LDS.
 // KT is chosen so that there are at least 512 tiles; 0 = no tile kernel.
 constexpr int chain_tile_bits(int L) {
@@ -337,10 +340,15 @@ void dev_resid(hipStream_t s, int64_t D, int n, const double* U,
 // columns permuted alike.
 void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
                  std::vector<double>& Z, int nz);
-// Dense symmetric eigenproblem (n x n col-major A, overwritten): eigenvalues
-// ascending in w, eigenvectors in the columns of Z (col-major).
+// Dense symmetric eigenproblem (n x n col-major A): eigenvalues ascending in
+// w, eigenvectors in the columns of Z (col-major).
 void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
              std::vector<double>& Z);
+// The eigenvalues (ascending) and only the last r rows of the eigenvector
+// matrix: Ztail is r x n row-major, Ztail[i n + j] = component n - r + i of
+// eigenvector j.
+void sym_eig_tail(int n, const std::vector<double>& A, int r, std::vector<double>& w,
+                  std::vector<double>& Ztail);
 
 // ---------------------------------------------------------------- plan ----
 double filter_value_closed(double lambda_t, int K, double x);
@@ -376,6 +384,9 @@ void* ctx_scratch(polfed_ctx* ctx, int slot, size_t bytes);
 void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
                   const double* a, int K, double* V, int k, double* alpha,
                   double* beta, int precision);
+void block_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                        const double* a, int K, double* V, int k, int s, double* A,
+                        double* Bn, int precision);
 void profile_step(polfed_ctx* ctx, const polfed_op* op, int precision, int iters,
                   double* avg_ms, double* min_ms);
 

@@ -254,6 +254,7 @@ polfed_status serve_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_pa
   REQUIRE(p && x0 && evals && evecs && resid && out, "serve: null argument");
   REQUIRE(p->n_ev >= 1 && p->n_ev <= op->D, "serve: need 1 <= n_ev <= D");
   REQUIRE(p->precision == POLFED_FP64 || p->precision == POLFED_FP32, "serve: bad precision");
+  REQUIRE(p->block_size <= 1, "serve: block Lanczos (block_size > 1) runs through polfed_solve only");
   Server* s = ctx->server;
   const size_t tb = p->precision == POLFED_FP32 ? 4 : 8;
   const size_t fp = SolveRun::footprint(op, *p) + 4 * (size_t)op->D * tb;

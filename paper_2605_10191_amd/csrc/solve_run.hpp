@@ -78,6 +78,55 @@ void rayleigh_ritz(hipStream_t s, int64_t D, int n, const double* U, const doubl
 void select_pairs(Extracted& ex, double lam, int n_ev, double tol_resid, double theta_min,
                   const polfed_plan& pl);
 
+double step_bytes(const polfed_op* op, int precision);
+
+// Device coefficient table [(Kmax + 1)][nb] of a multi-column filter; column
+// c is zero above its own order K[c].
+struct BatchCoef {
+  DevBuf d64, d32;
+  int nb = 0, Kmax = 0;
+  void set(hipStream_t s, int nb, const double* const* a, const int* K);
+};
+
+// Device state of the block filter and block orthogonalization (block
+// Lanczos, Sec. 2.2): the filtered block W, a copy of it for the repair of a
+// rank-deficient block, the filter buffers and, for chain operators, the
+// multi-column recurrence with every column on the same operator.
+struct BlockWs {
+  int s = 0;
+  int64_t D = 0;
+  bool fp32 = false, batched = false;
+  DevBuf w, save, vin;     // D x s FP64
+  DevBuf v32, w32;         // D x s FP32 (FP32 filter)
+  DevBuf bA, bB;           // D x s of the filter precision
+  ChainBatch bt;
+  BatchCoef co;
+  void init(polfed_ctx* ctx, const polfed_op* op, int s, bool fp32, const polfed_plan& pl,
+            const double* a);
+};
+
+// W = P(H~) X for the D x s block X (columns contiguous), into W.
+template <typename T>
+void block_filter_on(hipStream_t st, const polfed_op* op, BlockWs& bw, const polfed_plan& pl,
+                     const double* a, const T* X, T* W);
+
+// Orthogonalizes the filtered block W (D x s, overwritten) against basis
+// columns [0, k + s) of V and writes the next block into columns
+// [k + s, k + 2s): column c gets two passes of classical Gram-Schmidt
+// against [0, k + s + c) and is normalized.  The summed projections onto the
+// current block give A (s x s, col-major); those onto the new columns and
+// the norms give the upper triangular Bn.  save: D x s scratch; c, partial:
+// coefficient scratch for k + 2s columns; scal: 8 device doubles.  Returns
+// the number of rank-deficient columns replaced by random directions.
+int block_orth(hipStream_t st, int64_t D, int k, int s, double* V, double* W, double* save,
+               double* c, double* partial, int64_t nseg, int* flag, double* scal, double* A,
+               double* Bn, uint64_t& seed);
+
+// Orthonormal start block: Gram-Schmidt QR (two passes per column) of the
+// D x s block X0 into columns [0, s) of V; fails on a rank-deficient X0.
+void block_start(hipStream_t st, int64_t D, int s, const double* X0, double* V, double* w,
+                 double* c, double* partial, int64_t nseg, int* flag, double* scal);
+
 struct SolveRun {
   // inputs
   polfed_ctx* ctx = nullptr;
@@ -96,6 +145,7 @@ struct SolveRun {
   int n_want = 0, n_want0 = 0, M_alloc = 0, M_max = 0, cap = 0, check_every = 0,
       next_check = 0, k = 0;
   uint64_t restart_seed = 0;
+  int brk_from = 1;  // breakdowns are searched from this Lanczos index on
   Basis B;
   Ws ws;
   polfed_report R{};
@@ -108,6 +158,12 @@ struct SolveRun {
   DevBuf vst;  // FP64: fixed copy of v_k read by the graph
   enum { kTimeDirect, kTimeGraph, kDirect, kGraph } mode = kTimeDirect;
   float t_direct_ms = 0;
+  // block Lanczos (s > 1): band holds [A_j | B_{j+1}] (2 s^2 doubles) for
+  // every block step j; the filtered block lives in bw.w
+  int s = 1;
+  DevBuf band;
+  int band_blocks = 0;
+  BlockWs bw;
 
   SolveRun() = default;
   SolveRun(const SolveRun&) = delete;
@@ -122,6 +178,13 @@ struct SolveRun {
   double* wbuf() const { return ws.w.as<double>(); }  // where P(H~) v_k goes
   void filter_self();  // single-column filter of v_k into wbuf()
   void advance();      // CGS2, k += 1, periodic check; sets done when finished
+  void filter_block();   // block mode: P(H~) of the current block into bw.w
+  void advance_block();  // block mode: orthogonalization, QR, k += s, check
+  // extraction from the Ritz pairs (thf, eigenvectors Y row-major k x k) of
+  // a passed check, refinement, completion test; true when the run finished
+  // or restarted (no further check scheduling)
+  bool conclude(const std::vector<double>& thf, const std::vector<double>& Y);
+  void grow_band(int blocks);
   void emit(const Extracted& ex, polfed_status st);
   void fallback_fp64();  // restart the Lanczos iteration with the FP64 filter
   void finish();
@@ -131,14 +194,6 @@ struct SolveRun {
 // FP64-accurate refinement of the Ritz pairs of an FP32-filtered run (ex is
 // updated in place, selection included).
 void refine(SolveRun& run, Extracted& ex, double theta_min);
-
-// Device coefficient table [(Kmax + 1)][nb] of a multi-column filter; column
-// c is zero above its own order K[c].
-struct BatchCoef {
-  DevBuf d64, d32;
-  int nb = 0, Kmax = 0;
-  void set(hipStream_t s, int nb, const double* const* a, const int* K);
-};
 
 template <typename T>
 void filter_apply_batch(polfed_ctx* ctx, const ChainBatch& bt, const BatchCoef& co,

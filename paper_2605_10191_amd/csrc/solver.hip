@@ -33,6 +33,16 @@ double now_seconds() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Algorithmic HBM bytes of one Clenshaw step on one vector: v, b1, b2 read
+// and out written, plus the matrix stream of CSR storage.
+double step_bytes(const polfed_op* op, int precision) {
+  const double w = precision == POLFED_FP32 ? 4.0 : 8.0;
+  double b = 4.0 * w * (double)op->D;
+  if (op->storage == POLFED_CSR)
+    b += (double)op->nnz * (w + 4.0) + 8.0 * (double)(op->D + 1) + w * (double)op->D;
+  return b;
+}
+
 // ------------------------------------------------------- filter apply ----
 
 template <typename T>
@@ -125,6 +135,37 @@ void normalize_into(hipStream_t s, int64_t D, const double* x, Ws& ws, double* o
   dev_scale_into(s, D, x, nrm, out, ws.flag.as<int>());
 }
 
+// Lanczos breakdown at step k (the Krylov space of the start vector is an
+// invariant subspace): v_k becomes a random unit vector orthogonal to
+// v_0..v_{k-1}, and beta_k = 0 decouples the Lanczos matrix there.
+void restart_random(hipStream_t s, int64_t D, int k, const Basis& B, Ws& ws, uint64_t seed) {
+  double* w = ws.w.as<double>();
+  dev_random(s, D, seed, w);
+  double* junk = ws.scal.as<double>() + 8;
+  for (int pass = 0; pass < 2; ++pass) {
+    dev_gemv_t(s, D, k, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
+               ws.c.as<double>(), junk, 0);
+    dev_gemv_n_sub(s, D, k, B.V.as<double>(), D, ws.c.as<double>(), w);
+  }
+  const double zero = 0.0;
+  HIPC(hipMemcpyAsync(ws.beta.as<double>() + k, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+  normalize_into(s, D, w, ws, B.col(k));
+  HIPC(hipMemsetAsync(ws.flag.get(), 0, sizeof(int), s));
+  HIPC(hipStreamSynchronize(s));
+}
+
+// First breakdown at an index in [from, k]: beta_i below 1e-13 times the
+// largest Lanczos coefficient before it; -1 if none.
+int first_breakdown(int from, int k, const std::vector<double>& al,
+                    const std::vector<double>& be, double floor_scale) {
+  double scale = floor_scale;
+  for (int i = 1; i <= k; ++i) {
+    scale = std::max({scale, std::fabs(al[i - 1]), i > 1 ? be[i - 1] : 0.0});
+    if (i >= from && be[i] <= 1e-13 * scale) return i;
+  }
+  return -1;
+}
+
 void apply_H(hipStream_t s, const polfed_op* op, const double* x, double* y) {
   op_step<double>(s, op, 1.0, 0.0, 0.0, nullptr, x, nullptr, y);
 }
@@ -173,7 +214,7 @@ void bounds(polfed_ctx* ctx, const polfed_op* op, const double* x0, double tol,
   normalize_into(s, D, x0, ws, B.col(0));
   std::vector<double> al(cap + 1), be(cap + 2);
   double lo = 0, hi = 0;
-  int k = 0;
+  int k = 0, restarts = 0, brk_from = 1;
   for (;;) {
     apply_H(s, op, B.col(k), ws.w.as<double>());
     cgs2_normalize(s, D, k + 1, B, ws, ws.alpha.as<double>() + k,
@@ -187,7 +228,18 @@ void bounds(polfed_ctx* ctx, const polfed_op* op, const double* x0, double tol,
                           hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
       for (int i = 0; i < k; ++i)
-        if (!std::isfinite(al[i])) fail(POLFED_ERR_INVALID, "bounds: non-finite Lanczos coefficient");
+        if (!std::isfinite(al[i]) || !std::isfinite(be[i + 1]))
+          fail(POLFED_ERR_INVALID, "bounds: non-finite Lanczos coefficient");
+      // a start vector inside an invariant subspace: continue from a random
+      // direction orthogonal to it, so that the bounds cover the spectrum
+      const int kb = first_breakdown(brk_from, k, al, be, 0.0);
+      if (kb > 0 && kb < cap && restarts < 8) {
+        ++restarts;
+        k = kb;
+        restart_random(s, D, k, B, ws, 0xB0D5ULL + (uint64_t)restarts);
+        brk_from = k + 1;
+        continue;
+      }
       std::vector<double> th, zl;
       ritz_last(k, al, be, th, zl);
       lo = th.front();
@@ -299,13 +351,6 @@ Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, 
   return ex;
 }
 
-double step_bytes(const polfed_op* op, int precision) {
-  const double w = precision == POLFED_FP32 ? 4.0 : 8.0;
-  double b = 4.0 * w * (double)op->D;
-  if (op->storage == POLFED_CSR)
-    b += (double)op->nnz * (w + 4.0) + 8.0 * (double)(op->D + 1) + w * (double)op->D;
-  return b;
-}
 
 }  // namespace
 
@@ -327,6 +372,10 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   REQUIRE(p.n_ev >= 1 && p.n_ev <= D, "solve: need 1 <= n_ev <= D");
   REQUIRE(p.precision == POLFED_FP64 || p.precision == POLFED_FP32, "solve: bad precision");
   REQUIRE(x0 && evals && evecs && resid && n_found, "solve: null buffer");
+  this->s = std::max(1, p.block_size);
+  REQUIRE(this->s <= 64, "solve: block_size must lie in 0..64");
+  REQUIRE(this->s == 1 || D >= 2 * (int64_t)this->s,
+          "solve: block Lanczos needs D >= 2 block_size");
   static std::atomic<uint64_t> next_uid{1};
   uid = next_uid.fetch_add(1);
   fp32 = p.precision == POLFED_FP32;
@@ -378,17 +427,29 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   R.rho = pl.rho;
   R.K = pl.K;
 
-  // 4. filtered Lanczos state
-  M_alloc = expected_krylov_dim(n_want, 1, eta);
-  M_max = (int)std::min<int64_t>(D, p.max_iter > 0 ? p.max_iter : 4 * M_alloc);
+  // 4. filtered (block) Lanczos state; in block mode every count of basis
+  // vectors is a whole number of blocks
+  const int bs = this->s;
+  auto whole = [bs](int64_t n) { return (int)(((n + bs - 1) / bs) * bs); };
+  M_alloc = whole(expected_krylov_dim(n_want, bs, eta));
+  M_max = (int)std::min<int64_t>(D, p.max_iter > 0 ? p.max_iter : 4 * (int64_t)M_alloc);
+  if (bs > 1) M_max = (int)((std::min<int64_t>(M_max, D - bs) / bs) * bs);
   cap = std::min(M_alloc, M_max);
   R.M_alloc = M_alloc;
-  B.ensure(s, D, cap, 0);
-  ws.init(s, D, cap + 1, fp32);
-  normalize_into(s, D, x0, ws, B.col(0));
-  check_every = std::max(10, (int)std::ceil(0.05 * M_alloc));
-  next_check = std::min(n_want, M_max);
+  B.ensure(s, D, cap + 2 * bs - 1, 0);
+  ws.init(s, D, cap + 2 * bs, fp32);
+  if (bs == 1) {
+    normalize_into(s, D, x0, ws, B.col(0));
+  } else {
+    block_start(s, D, bs, x0, B.V.as<double>(), ws.w.as<double>(), ws.c.as<double>(),
+                ws.partial.as<double>(), ws.nseg, ws.flag.as<int>(), ws.scal.as<double>());
+    bw.init(ctx, op, bs, fp32, pl, a.data());
+    grow_band(cap / bs + 1);
+  }
+  check_every = whole(std::max(10, (int)std::ceil(0.05 * M_alloc)));
+  next_check = std::min(whole(n_want), M_max);
   k = 0;
+  brk_from = 1;
   done = false;
   status = POLFED_NOT_CONVERGED;
   restart_seed = 0x5EEDULL;
@@ -406,9 +467,13 @@ size_t SolveRun::footprint(const polfed_op* op, const polfed_params& p) {
 }
 
 void SolveRun::filter_self() {
+  if (this->s > 1) {
+    filter_block();
+    return;
+  }
   hipStream_t s = ctx->stream;
   const int64_t D = op->D;
-  if (mode == kTimeDirect && (p.graph == 2 || pl.K < 8)) mode = kDirect;
+  if (mode == kTimeDirect && (p.graph == 2 || pl.K < 8 || pl.K > kGraphMaxSteps)) mode = kDirect;
   if (mode == kTimeDirect && p.graph == 1) mode = kGraph;
   const bool use_graph = mode == kTimeGraph || mode == kGraph;
   if (use_graph && !graph.ready()) {
@@ -490,6 +555,10 @@ SolveRun::~SolveRun() {
 // the periodic convergence check (eq. lan_criterion), extraction and the
 // completeness test once the check passes.
 void SolveRun::advance() {
+  if (this->s > 1) {
+    advance_block();
+    return;
+  }
   hipStream_t s = ctx->stream;
   const int64_t D = op->D;
   hipEvent_t r0, r1;
@@ -521,29 +590,14 @@ void SolveRun::advance() {
                                   " at step " + std::to_string(i) +
                                   " (spectral bounds too tight?)");
   // breakdown: restart from the first vanishing beta with a random vector
-  int kb = -1;
-  for (int i = 1; i <= k; ++i)
-    if (be[i] <= 1e-13) {
-      kb = i;
-      break;
-    }
+  // (the zero beta of an earlier restart is not one)
+  const int kb = first_breakdown(brk_from, k, al, be, 1.0);
   if (kb > 0 && kb < M_max) {
     if (R.restarts >= 8) fail(POLFED_ERR_BREAKDOWN, "Lanczos breakdown: too many restarts");
     ++R.restarts;
     k = kb;
-    double* w = ws.w.as<double>();
-    dev_random(s, D, restart_seed++, w);
-    double* junk = ws.scal.as<double>() + 8;
-    for (int pass = 0; pass < 2; ++pass) {
-      dev_gemv_t(s, D, k, B.V.as<double>(), D, w, ws.partial.as<double>(), ws.nseg,
-                 ws.c.as<double>(), junk, 0);
-      dev_gemv_n_sub(s, D, k, B.V.as<double>(), D, ws.c.as<double>(), w);
-    }
-    double zero = 0.0;
-    HIPC(hipMemcpyAsync(ws.beta.as<double>() + k, &zero, sizeof(double), hipMemcpyHostToDevice, s));
-    normalize_into(s, D, w, ws, B.col(k));
-    HIPC(hipMemsetAsync(ws.flag.get(), 0, sizeof(int), s));
-    HIPC(hipStreamSynchronize(s));
+    restart_random(s, D, k, B, ws, restart_seed++);
+    brk_from = k + 1;
     next_check = k + 1;
     R.t_check += now_seconds() - tc;
     return;
@@ -569,47 +623,56 @@ void SolveRun::advance() {
                  n_want, est_max, tol_ritz, (int)conv);
   R.t_check += now_seconds() - tc;
   if (conv || k >= M_max) {
-    const double tx = now_seconds();
     std::vector<double> thf, Y;
     ritz_full(k, al, be, thf, Y);
-    // the full solve orders eigenvalues alike; pick the n_want largest
-    std::vector<int> ord(k);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return thf[x] > thf[y]; });
-    std::vector<double> Ysel((size_t)k * nw);
-    for (int j = 0; j < nw; ++j)
-      for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
-    const double theta_min = thf[ord[nw - 1]];
-    Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw);
-    select_pairs(ex, lam, p.n_ev, tol_resid, theta_min, pl);
-    R.t_extract += now_seconds() - tx;
-    if (verbose()) {
-      int acc = 0;
-      for (double r : ex.res) acc += r <= tol_resid;
-      std::fprintf(stderr, "[polfed] extract k=%d accepted=%d selected=%d complete=%d theta_min=%.4f\n",
-                   k, acc, (int)ex.sel.size(), (int)ex.complete, theta_min);
-    }
-    if (fp32 && !((int)ex.sel.size() == p.n_ev && ex.complete)) {
-      const double tr = now_seconds();
-      refine(*this, ex, theta_min);
-      R.t_refine += now_seconds() - tr;
-    }
-    const bool ok = (int)ex.sel.size() == p.n_ev && ex.complete;
-    if (ok || k >= M_max) {
-      emit(ex, ok ? POLFED_OK : POLFED_NOT_CONVERGED);
-      return;
-    }
-    // The Ritz vectors of an FP32-filtered run stop improving once Lanczos
-    // has reached the FP32 noise level, so a refinement that did not finish
-    // will not finish later either: the solve is completed in FP64.
-    if (fp32 && !ok) {
-      fallback_fp64();
-      return;
-    }
-    if ((int)ex.sel.size() == p.n_ev && !ex.complete)
-      n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
+    if (conclude(thf, Y)) return;
   }
   next_check = k + check_every;
+}
+
+// After a passed check (or at the Krylov limit): the n_want largest Ritz
+// values of P(H~) and their vectors u = V t, Rayleigh-Ritz with H, the
+// selection and the completeness test; refinement of an FP32-filtered run.
+bool SolveRun::conclude(const std::vector<double>& thf, const std::vector<double>& Y) {
+  const double tx = now_seconds();
+  const int nw = std::min(n_want, k);
+  // pick the n_want largest
+  std::vector<int> ord(k);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return thf[x] > thf[y]; });
+  std::vector<double> Ysel((size_t)k * nw);
+  for (int j = 0; j < nw; ++j)
+    for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
+  const double theta_min = thf[ord[nw - 1]];
+  Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw);
+  select_pairs(ex, lam, p.n_ev, tol_resid, theta_min, pl);
+  R.t_extract += now_seconds() - tx;
+  if (verbose()) {
+    int acc = 0;
+    for (double r : ex.res) acc += r <= tol_resid;
+    std::fprintf(stderr, "[polfed] extract k=%d accepted=%d selected=%d complete=%d theta_min=%.4f\n",
+                 k, acc, (int)ex.sel.size(), (int)ex.complete, theta_min);
+  }
+  if (fp32 && !((int)ex.sel.size() == p.n_ev && ex.complete)) {
+    const double tr = now_seconds();
+    refine(*this, ex, theta_min);
+    R.t_refine += now_seconds() - tr;
+  }
+  const bool ok = (int)ex.sel.size() == p.n_ev && ex.complete;
+  if (ok || k >= M_max) {
+    emit(ex, ok ? POLFED_OK : POLFED_NOT_CONVERGED);
+    return true;
+  }
+  // The Ritz vectors of an FP32-filtered run stop improving once Lanczos
+  // has reached the FP32 noise level, so a refinement that did not finish
+  // will not finish later either: the solve is completed in FP64.
+  if (fp32 && !ok) {
+    fallback_fp64();
+    return true;
+  }
+  if ((int)ex.sel.size() == p.n_ev && !ex.complete)
+    n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
+  return false;
 }
 
 // Restarts the filtered Lanczos iteration from v_0 with the FP64 filter (the
@@ -621,12 +684,17 @@ void SolveRun::fallback_fp64() {
   R.fp32_fallback = 1;
   tol_ritz = 1e-10;
   graph.reset();
-  mode = (p.graph == 2 || pl.K < 8) ? kDirect : (p.graph == 1 ? kGraph : kTimeDirect);
+  mode = (p.graph == 2 || pl.K < 8 || pl.K > kGraphMaxSteps) ? kDirect
+                                                             : (p.graph == 1 ? kGraph : kTimeDirect);
   ws.bA.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
   ws.bB.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
   k = 0;
+  brk_from = 1;
   n_want = n_want0;
-  next_check = std::min(n_want, M_max);
+  next_check = std::min(((n_want + s - 1) / s) * s, M_max);
+  // block mode: the start block (columns 0..s-1) is kept; the filter
+  // buffers change precision
+  if (s > 1) bw.init(ctx, op, s, false, pl, a.data());
   if (verbose()) std::fprintf(stderr, "[polfed] FP32 refinement stalled: restarting in FP64\n");
 }
 
@@ -661,6 +729,9 @@ void SolveRun::finish() {
   // the basis and work vectors are not needed any more
   B = Basis{};
   ws = Ws{};
+  bw = BlockWs{};
+  band = DevBuf{};
+  band_blocks = 0;
 }
 
 polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p,
