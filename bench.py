@@ -211,8 +211,9 @@ def qsun_leg(pk, wl, ctx):
                         "seed 0, 50 pairs at normalized energy 0.5, FP64"}
 
 
-def solve_legs(pk, wl, ctx, L, n_ev):
-    """Full solves of the XXZ workload in FP64 and FP32 bulk + FP64 refinement."""
+def solve_legs(pk, wl, ctx, L, n_ev, block_sizes=(4, 8)):
+    """Full solves of the XXZ workload: Lanczos in FP64 and in FP32 bulk +
+    FP64 refinement, and block Lanczos in FP64 for each block size."""
     import torch
     res = {}
     op, x0, (_, _, lam, _, _) = xxz_setup(pk, wl, ctx, L, 3.0, 0, n_ev)
@@ -236,6 +237,34 @@ def solve_legs(pk, wl, ctx, L, n_ev):
             f"iters={rep['iters']} sweeps={rep['refine_sweeps']} t_filter={rep['t_filter']:.1f} "
             f"t_reorth={rep['t_reorth']:.1f} t_refine={rep['t_refine']:.1f} "
             f"t_check={rep['t_check']:.1f} t_extract={rep['t_extract']:.1f}")
+    # block Lanczos (Sec. 2.2): the same workload with a start block of s
+    # seeded columns; the filter runs as one s-column recurrence
+    for s in block_sizes:
+        X0 = torch.tensor(np.stack([wl.start_vector(op.D, c) for c in range(s)]),
+                          device=ctx.torch_device)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ev, U, r, rep, status = pk.solve(op, X0, n_ev, lam, "absolute", allow_partial=True)
+        torch.cuda.synchronize()
+        tsolve = time.perf_counter() - ts
+        eb = ev.cpu().numpy()
+        name = f"fp64_block{s}"
+        runs[name] = eb
+        err = None
+        if len(eb) == len(runs["fp64"]) == n_ev:
+            e64s = np.sort(runs["fp64"])
+            err = float(np.max(np.abs(np.sort(eb) - e64s) / np.maximum(np.abs(e64s), 1.0)))
+        res[name] = {"eigenpairs_per_s": round(len(eb) / tsolve, 3) if status == "OK" else None,
+                     "solve_s": round(tsolve, 2), "status": status, "K": rep["K"],
+                     "block_size": s, "krylov_dim": rep["iters"],
+                     "max_resid": float(r.max().item()) if len(r) else None,
+                     "max_rel_err_vs_fp64_lanczos": err,
+                     "filter_GBps": round(rep["filter_GBps"], 1),
+                     "t_filter": round(rep["t_filter"], 2), "t_reorth": round(rep["t_reorth"], 2),
+                     "t_check": round(rep["t_check"], 2), "t_extract": round(rep["t_extract"], 2)}
+        log(f"solve L={L} block s={s}: {tsolve:.1f}s status={status} K={rep['K']} "
+            f"M={rep['iters']} t_filter={rep['t_filter']:.1f} t_reorth={rep['t_reorth']:.1f} "
+            f"t_check={rep['t_check']:.1f} t_extract={rep['t_extract']:.1f} err={err}")
     e64, e32 = runs["fp64"], runs["fp32_bulk"]
     if len(e64) == len(e32) == n_ev:
         err = np.abs(np.sort(e32) - np.sort(e64)) / np.maximum(np.abs(np.sort(e64)), 1.0)
@@ -318,6 +347,8 @@ def main():
     ap.add_argument("--W", type=float, default=3.0)
     ap.add_argument("--n-ev", type=int, default=100)
     ap.add_argument("--solve-L", type=int, default=20)
+    ap.add_argument("--block-sizes", default="4,8",
+                    help="block Lanczos legs of the solve benchmark (comma list)")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
@@ -441,7 +472,8 @@ def main():
         out["kernels"] = kernel_legs(pk, wl, ctx, args.L, args.W, args.profile_iters)
         log(f"kernel legs: {out['kernels']}")
     if not args.no_solve:
-        sl = solve_legs(pk, wl, ctx, args.solve_L, args.n_ev)
+        sl = solve_legs(pk, wl, ctx, args.solve_L, args.n_ev,
+                        tuple(int(x) for x in args.block_sizes.split(",") if x))
         out["eigenpairs_per_s"] = {"value": sl["fp64"]["eigenpairs_per_s"],
                                    "unit": "eigenpairs/s", **sl}
         out["qsun"] = qsun_leg(pk, wl, ctx)
