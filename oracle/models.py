@@ -155,6 +155,27 @@ def qsun(N: int, L: int, A, gamma: float, g0: float, alpha: float, u, n_of_j,
     return H
 
 
+def qrem(L: int, E, Gamma: float):
+    """Quantum random energy model, eq. (qrem) of App. A, full 2^L space:
+        H = sum_alpha E_alpha |alpha><alpha| - Gamma sum_i sigma^x_i,
+    sigma^x_i flipping bit i of the state index.  Returns H_csr."""
+    E = np.asarray(E, dtype=np.float64)
+    D = 1 << L
+    assert E.shape == (D,)
+    idx = np.arange(D, dtype=np.int64)
+    rows = [idx]
+    cols = [idx]
+    vals = [E]
+    for i in range(L):
+        rows.append(idx)
+        cols.append(idx ^ (1 << i))
+        vals.append(np.full(D, -float(Gamma)))
+    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(D, D)).tocsr()
+    H.sum_duplicates()
+    return H
+
+
 def xxz_rows_apply(L: int, N: int, J: float, Delta: float, h, periodic: bool,
                    states: np.ndarray, rows: np.ndarray, x: np.ndarray):
     """(H x)[r] for the listed rows only, straight from eq. (xxz), for checks

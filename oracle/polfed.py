@@ -19,13 +19,21 @@ from . import filter as flt
 from . import lanczos as lz
 
 
-def target_energy(kind: str, target: float, E_min: float, E_max: float):
+def target_energy(kind: str, target: float, E_min: float, E_max: float,
+                  mean: float | None = None):
     """Absolute target energy lambda.
     'absolute'  : lambda = target;
     'rescaled'  : target is lambda~ in the rescaled coordinates of the
                   (unpadded) bounds (Sec. 5.4, the (:rescaled, eps) mode);
     'normalized': target = (lambda - E_min)/(E_max - E_min) in [0, 1] (the
-                  convention of the workload definitions; 0.5 is the middle)."""
+                  convention of the workload definitions; 0.5 is the middle);
+    'maxdos'    : the maximum of the estimated density of states (Sec. 5.4,
+                  :maxdos); for the Gaussian estimate of eq. dos_gaussian that
+                  is its mean, mean = Tr H / D (target is ignored);
+    'offset'    : target = eta in [-1, 1] moves from the maxdos point toward
+                  the upper (eta > 0) or lower (eta < 0) spectral edge,
+                  linearly in the rescaled coordinates (Sec. 5.4,
+                  (:offset, eta))."""
     if kind == "absolute":
         return float(target)
     if kind == "rescaled":
@@ -33,6 +41,16 @@ def target_energy(kind: str, target: float, E_min: float, E_max: float):
         return E_c + target * dE
     if kind == "normalized":
         return E_min + target * (E_max - E_min)
+    if kind in ("maxdos", "offset"):
+        if mean is None:
+            raise ValueError("maxdos/offset targets need the mean energy")
+        if kind == "maxdos":
+            return float(mean)
+        E_c, dE = flt.rescale(E_min, E_max)
+        em = (mean - E_c) / dE
+        eta = float(target)
+        e = em + eta * (1.0 - em) if eta >= 0 else em + eta * (1.0 + em)
+        return E_c + e * dE
     raise ValueError(kind)
 
 
@@ -77,7 +95,8 @@ def polfed(H, x0: np.ndarray, n_ev: int, target: float,
         E_min, E_max = lz.spectral_extremes(H)
     else:
         E_min, E_max = bounds
-    lam = target_energy(target_kind, target, E_min, E_max)
+    tr1, _ = flt.trace_moments(H)
+    lam = target_energy(target_kind, target, E_min, E_max, tr1)
     n_want = n_ev + buffer_size(n_ev)
     # the window is sized for all n_want pairs, so that the n_ev nearest sit
     # well inside the main lobe of the filter

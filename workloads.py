@@ -10,6 +10,8 @@ Distributions follow the models of the paper's Appendix A:
   entries, exponents u_j = j + U[-zeta, zeta] (j counted from 0), dot spin n(j)
   uniform over the N dot spins, fields h_j ~ U[h - w, h + w];
 * spinless t-V fermions (not in the paper): on-site energies eps_i ~ U[-2, 2];
+* quantum random energy model, eq. (qrem): one Gaussian energy per basis state,
+  mean 0 and standard deviation sqrt(L/2);
 * start vector: U[0, 1) entries, as in the paper's usage example (Sec. 5.2).
 """
 from __future__ import annotations
@@ -40,6 +42,11 @@ def qsun_draws(N: int, L: int, seed: int, zeta: float = 0.2,
     n_of_j = rng.integers(0, N, L).astype(np.int32)
     hj = rng.uniform(h - w, h + w, L)
     return {"A": A, "u": u, "n_of_j": n_of_j, "h": hj}
+
+
+def qrem_energies(L: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, np.sqrt(L / 2.0), 1 << L)
 
 
 def start_vector(D: int, seed: int) -> np.ndarray:
