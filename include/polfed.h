@@ -58,7 +58,13 @@ enum { POLFED_MATRIX_FREE = 0, POLFED_CSR = 1 };  /* operator storage */
 enum {
   POLFED_TARGET_ABSOLUTE = 0,   /* target is lambda itself */
   POLFED_TARGET_RESCALED = 1,   /* target is lambda~ in [-1, 1] of [E_min, E_max] */
-  POLFED_TARGET_NORMALIZED = 2  /* target is (lambda - E_min)/(E_max - E_min) */
+  POLFED_TARGET_NORMALIZED = 2, /* target is (lambda - E_min)/(E_max - E_min) */
+  POLFED_TARGET_MAXDOS = 3,     /* the maximum of the density-of-states estimate
+                                   (Sec. 5.4): the mean Tr H / D for the
+                                   Gaussian estimate; target is ignored */
+  POLFED_TARGET_OFFSET = 4      /* target = eta in [-1, 1]: from the maxdos point
+                                   toward the upper (eta > 0) or lower edge,
+                                   linearly in rescaled coordinates (Sec. 5.4) */
 };
 
 typedef struct polfed_ctx polfed_ctx;
@@ -133,6 +139,12 @@ polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L,
                              const double* A, double gamma, double g0,
                              double alpha, const double* u,
                              const int32_t* n_of_j, const double* h,
+                             polfed_op** out);
+/* Quantum random energy model, eq. (qrem) of App. A, on the full 2^L space:
+ * H = sum_a E[a] |a><a| - Gamma sum_i sigma^x_i, sigma^x_i flipping bit i
+ * of the state index a.  E: host array [2^L], copied.  2 <= L <= 28.
+ * Matrix-free only (no CSR copy). */
+polfed_status polfed_op_qrem(polfed_ctx* ctx, int L, const double* E, double Gamma,
                              polfed_op** out);
 /* Generic symmetric sparse matrix in CSR (host arrays, copied): rowptr[D+1]
  * (int64), col[nnz] (int32, any order within a row), val[nnz].  Diagonal

@@ -176,6 +176,16 @@ def qrem(L: int, E, Gamma: float):
     return H
 
 
+def qrem_rows_apply(L: int, E, Gamma: float, rows: np.ndarray, x: np.ndarray):
+    """(H x)[r] of eq. (qrem) for the listed rows only, for checks at sizes
+    where the whole matrix is not built."""
+    rows = np.asarray(rows, dtype=np.int64)
+    out = np.asarray(E, dtype=np.float64)[rows] * x[rows]
+    for i in range(L):
+        out -= float(Gamma) * x[rows ^ (1 << i)]
+    return out
+
+
 def xxz_rows_apply(L: int, N: int, J: float, Delta: float, h, periodic: bool,
                    states: np.ndarray, rows: np.ndarray, x: np.ndarray):
     """(H x)[r] for the listed rows only, straight from eq. (xxz), for checks

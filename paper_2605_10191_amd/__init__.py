@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpolfed.so")
 FP64, FP32 = 0, 1
 MATRIX_FREE, CSR = 0, 1
 TARGET_ABSOLUTE, TARGET_RESCALED, TARGET_NORMALIZED = 0, 1, 2
-_TARGETS = {"absolute": 0, "rescaled": 1, "normalized": 2}
+_TARGETS = {"absolute": 0, "rescaled": 1, "normalized": 2, "maxdos": 3, "offset": 4}
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
           -3: "ERR_HIP", -4: "ERR_BOUNDS", -5: "ERR_BREAKDOWN", -6: "ERR_BUSY",
@@ -92,6 +92,7 @@ SIGNATURES = {
     "polfed_op_qsun": [_P, _I, _I, _DP, _D, _D, _D, _DP, _I32P, _DP,
                        ctypes.POINTER(_P)],
     "polfed_op_csr": [_P, _I64, _I64P, _I32P, _DP, ctypes.POINTER(_P)],
+    "polfed_op_qrem": [_P, _I, _DP, _D, ctypes.POINTER(_P)],
     "polfed_op_materialize_csr": [_P, _P],
     "polfed_op_set_storage": [_P, _I],
     "polfed_op_set_kernel": [_P, _I, _I, ctypes.POINTER(_I)],
@@ -326,6 +327,18 @@ class Operator:
         _check(_lib.polfed_op_qsun(ctx.handle, N_dot, L, _dptr(A), gamma, g0,
                                    alpha, _dptr(u), _dptr(n_of_j, ctypes.c_int32),
                                    _dptr(h), ctypes.byref(out)))
+        return cls(ctx, out)
+
+    @classmethod
+    def qrem(cls, ctx, L, E, Gamma):
+        """Quantum random energy model on the full 2^L space (E: 2^L
+        energies, copied)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        if E.shape != (1 << L,):
+            raise ValueError("E must hold 2^L energies")
+        out = ctypes.c_void_p()
+        _check(_lib.polfed_op_qrem(ctx.handle, int(L), _dptr(E), float(Gamma),
+                                   ctypes.byref(out)))
         return cls(ctx, out)
 
     @classmethod

@@ -13,6 +13,7 @@ polfed_op* make_tv(polfed_ctx*, int, int, double, double, const double*, int);
 polfed_op* make_qsun(polfed_ctx*, int, int, const double*, double, double, double,
                      const double*, const int32_t*, const double*);
 polfed_op* make_csr(polfed_ctx*, int64_t, const int64_t*, const int32_t*, const double*);
+polfed_op* make_qrem(polfed_ctx*, int, const double*, double);
 polfed_status serve_start(polfed_ctx*, size_t, int);
 polfed_status serve_submit(polfed_ctx*, const polfed_op*, const polfed_params*,
                            const double*, double*, double*, double*, polfed_req**);
@@ -293,6 +294,19 @@ polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L, const double* A,
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     *out = make_qsun(ctx, N_dot, L, A, gamma, g0, alpha, u, n_of_j, h);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_qrem(polfed_ctx* ctx, int L, const double* E, double Gamma,
+                             polfed_op** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(out, "null output handle");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = make_qrem(ctx, L, E, Gamma);
     return POLFED_OK;
   });
 }

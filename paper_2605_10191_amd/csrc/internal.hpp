@@ -187,7 +187,7 @@ struct CsrDev {
   int64_t nblk;
 };
 
-enum class Model { Chain, Qsun, Csr };
+enum class Model { Chain, Qsun, Csr, Qrem };
 
 }  // namespace polfed
 
@@ -225,6 +225,10 @@ struct polfed_op {
   std::vector<double> hdot;
   std::vector<uint32_t> ray_mask;
   std::vector<double> ray_amp;
+  // quantum random energy model: transverse field and exact trace moments
+  // (sums over the space); the energies are the diagonal d_diag / d_diag32
+  double qrem_gamma = 0;
+  double qrem_tr[2] = {0, 0};
   // pattern key: operators with equal keys share the off-diagonal pattern
   std::string pattern_key;
   polfed::DevBuf d_ftab, d_ftab32, d_binom, d_hi_off, d_lo_rank, d_hdot;
@@ -301,6 +305,11 @@ template <typename T>
 bool chain_split_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
                       const T* v, const T* b1, const T* b2, T* out);
 void build_chain_split(polfed_op* op);
+// Fused Clenshaw step of the quantum random energy model (hypercube stencil).
+template <typename T>
+void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v, const T* b1,
+               const T* b2, T* out);
+int qrem_tile_bits(int L);
 void materialize_csr(polfed_ctx* ctx, polfed_op* op);
 
 // ---------------------------------------------------------------- blas ----

@@ -339,6 +339,9 @@ void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
     if (chain_split_step<T>(s, op, sigma, tau, a, v, b1, b2, out)) return;
     hipLaunchKernelGGL((k_chain_step<T, ROWS>), dim3(grid), dim3(256), 0, s,
                        op->chain(), sigma, tau, a, v, b1, b2, out, vec_ok);
+  } else if (op->model == Model::Qrem) {
+    qrem_step<T>(s, op, sigma, tau, a, v, b1, b2, out);
+    return;
   } else if (op->model == Model::Qsun) {
     constexpr int QROWS = sizeof(T) == 8 ? 2 : 4;
     const int64_t qt = (op->D + 256 * QROWS - 1) / (256 * QROWS);
@@ -469,6 +472,11 @@ void op_moments(hipStream_t s, const polfed_op* op, double* d_two, double* parti
                 int64_t npart) {
   const unsigned g = (unsigned)std::max<int64_t>(
       1, std::min<int64_t>(npart, (op->D + 255) / 256));
+  if (op->model == Model::Qrem) {
+    // exact moments, summed on the host when the energies were uploaded
+    HIPC(hipMemcpyAsync(d_two, op->qrem_tr, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    return;
+  }
   if (op->storage == POLFED_CSR || op->model == Model::Csr) {
     hipLaunchKernelGGL(k_moments_csr, dim3(g), dim3(256), 0, s, op->csr(), partial);
   } else if (op->model == Model::Chain) {
@@ -620,6 +628,7 @@ static void finish_csr(polfed_ctx* ctx, polfed_op* op,
 
 void materialize_csr(polfed_ctx* ctx, polfed_op* op) {
   if (op->model == Model::Csr || op->has_csr) return;
+  REQUIRE(op->model != Model::Qrem, "qrem: no CSR copy is offered (the operator is matrix-free)");
   hipStream_t s = ctx->stream;
   const int64_t D = op->D;
   std::vector<int64_t> rp(D + 1, 0);

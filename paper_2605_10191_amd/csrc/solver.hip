@@ -38,6 +38,7 @@ double now_seconds() {
 double step_bytes(const polfed_op* op, int precision) {
   const double w = precision == POLFED_FP32 ? 4.0 : 8.0;
   double b = 4.0 * w * (double)op->D;
+  if (op->model == Model::Qrem) b += w * (double)op->D;  // the energies E_a
   if (op->storage == POLFED_CSR)
     b += (double)op->nnz * (w + 4.0) + 8.0 * (double)(op->D + 1) + w * (double)op->D;
   return b;
@@ -261,11 +262,20 @@ namespace {
 
 int buffer_size(int n_ev) { return std::max(10, (int)std::ceil(0.2 * n_ev)); }
 
-double target_energy(int kind, double target, double E_min, double E_max) {
+double target_energy(int kind, double target, double E_min, double E_max, double mean) {
   switch (kind) {
     case POLFED_TARGET_ABSOLUTE: return target;
     case POLFED_TARGET_RESCALED: return 0.5 * (E_max + E_min) + target * 0.5 * (E_max - E_min);
     case POLFED_TARGET_NORMALIZED: return E_min + target * (E_max - E_min);
+    case POLFED_TARGET_MAXDOS: return mean;  // peak of the Gaussian DOS estimate
+    case POLFED_TARGET_OFFSET: {
+      // from the DOS peak toward an edge, linearly in rescaled coordinates
+      REQUIRE(target >= -1.0 && target <= 1.0, "offset target must lie in [-1, 1]");
+      const double c = 0.5 * (E_max + E_min), h = 0.5 * (E_max - E_min);
+      const double em = (mean - c) / h;
+      const double e = target >= 0 ? em + target * (1.0 - em) : em + target * (1.0 + em);
+      return c + e * h;
+    }
   }
   fail(POLFED_ERR_INVALID, "unknown target kind");
 }
@@ -405,7 +415,7 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   HIPC(hipMemcpyAsync(tr, two.get(), sizeof tr, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   const double tr1 = tr[0] / (double)D, tr2 = tr[1] / (double)D;
-  lam = target_energy(p.target_kind, p.target, E_min, E_max);
+  lam = target_energy(p.target_kind, p.target, E_min, E_max, tr1);
   // FP32 bulk keeps twice the buffer: the window edge moves away from the
   // wanted pairs, whose refinement then converges in about two sweeps (the
   // wider window also lowers K, so the Lanczos work stays about the same)
