@@ -166,8 +166,11 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage);
  * 4 = segment kernel with each segment split between two wavefronts;
  * -2 only reports the variant in use.
  * A variant that does not exist for the chain length (tiles need L >= 22)
- * gives POLFED_ERR_INVALID.  *chosen (may be NULL) receives the variant in
- * use after the call (-1 while not tuned yet). */
+ * gives POLFED_ERR_INVALID.  For a quantum random energy model the variant is
+ * the tile size in bits (rows per LDS tile = 2^variant), 1 .. min(L, 12), or
+ * -1 to pick among the default and its neighbours by timing.  *chosen (may
+ * be NULL) receives the variant in use after the call (-1 while not tuned
+ * yet). */
 polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, int* chosen);
 polfed_status polfed_op_dim(const polfed_op* op, int64_t* D);
 /* Off-diagonal nnz of the CSR copy (-1 if there is none). */

@@ -234,42 +234,6 @@ void dev_random(hipStream_t s, int64_t n, uint64_t seed, double* y) {
   HIPC(hipGetLastError());
 }
 
-// ---- C (D x n) = A (D x m) B (m x n) ----
-__global__ __launch_bounds__(kTB) void k_gemm_nn(int64_t D, int m, int n, const double* A,
-                                                 int64_t lda, const double* B,
-                                                 double* C, int64_t ldc) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = blockIdx.y * kCols;
-  if (r >= D) return;
-  double acc[kCols];
-#pragma unroll
-  for (int q = 0; q < kCols; ++q) acc[q] = 0;
-  for (int i = 0; i < m; ++i) {
-    const double a = A[r + (int64_t)i * lda];
-#pragma unroll
-    for (int q = 0; q < kCols; ++q)
-      if (j0 + q < n) acc[q] += a * B[i + (int64_t)(j0 + q) * m];
-  }
-#pragma unroll
-  for (int q = 0; q < kCols; ++q)
-    if (j0 + q < n) C[r + (int64_t)(j0 + q) * ldc] = acc[q];
-}
-
-void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A, int64_t lda,
-                 const double* B, double* C, int64_t ldc) {
-  if (!D || !n) return;
-  dim3 grid((unsigned)((D + kTB - 1) / kTB), (unsigned)((n + kCols - 1) / kCols));
-  hipLaunchKernelGGL(k_gemm_nn, grid, dim3(kTB), 0, s, D, m, n, A, lda, B, C, ldc);
-  HIPC(hipGetLastError());
-}
-
-void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A, const double* B,
-                 double* partial, int64_t nseg, double* G) {
-  for (int j = 0; j < n; ++j)
-    dev_gemv_t(s, D, n, A, D, B + (int64_t)j * D, partial, nseg, G + (int64_t)j * n,
-               nullptr, 0);
-}
-
 // ---- residual norms ----
 __global__ __launch_bounds__(kTB) void k_resid(int64_t D, int n, const double* U,
                                                const double* HU, const double* E,

@@ -353,12 +353,19 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
   return guarded([&]() -> polfed_status {
     REQUIRE(op, "null operator");
     REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
-    REQUIRE(variant >= -2 && variant <= 4, "variant must be -2 .. 4");
     const int pi = precision == POLFED_FP64 ? 0 : 1;
     if (variant == -2) {  // query only
       if (chosen) *chosen = op->tuned[pi];
       return POLFED_OK;
     }
+    if (op->model == Model::Qrem) {
+      REQUIRE(variant == -1 || (variant >= 1 && variant <= std::min(op->L, 12)),
+              "qrem: tile bits must be -1 or 1 .. min(L, 12)");
+      op->tuned[pi] = variant;
+      if (chosen) *chosen = op->tuned[pi];
+      return POLFED_OK;
+    }
+    REQUIRE(variant >= -1 && variant <= 4, "variant must be -2 .. 4");
     if (variant > 0) {
       REQUIRE(op->model == Model::Chain && op->split_nseg > 0,
               "step-kernel variants exist only for matrix-free chains");

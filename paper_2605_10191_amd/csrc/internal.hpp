@@ -330,12 +330,21 @@ void dev_copy_f2d(hipStream_t s, int64_t n, const float* x, double* y);
 void dev_fill(hipStream_t s, int64_t n, double v, double* y);
 void dev_fillf(hipStream_t s, int64_t n, float v, float* y);
 void dev_random(hipStream_t s, int64_t n, uint64_t seed, double* y);
-// C (D x n) = A (D x m, ld lda) * B (m x n, host-uploaded, col-major, ld m)
+// Dense products through rocBLAS (dense_la.cpp):
+// C (D x n) = A (D x m, ld lda) * B (m x n, device, col-major, ld m)
 void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A,
                  int64_t lda, const double* B, double* C, int64_t ldc);
 // G (n x n) = A^T B for A, B of D x n (ld D); G on device, col-major.
 void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A,
                  const double* B, double* partial, int64_t nseg, double* G);
+// Device eigensolvers through rocSOLVER: symmetric A (n x n col-major, lower
+// triangle read) -> eigenvalues w ascending, eigenvectors over A; symmetric
+// tridiagonal (d[n], e[n-1], both overwritten) -> eigenvalues ascending in d,
+// eigenvectors in C (n x n col-major).  All pointers are device memory.
+void dev_syevd(hipStream_t s, int n, double* A, double* w);
+void dev_stedc(hipStream_t s, int n, double* d, double* e, double* C);
+// Sizes from which the device eigensolvers replace the host ones.
+constexpr int kDeviceEigMin = 256;
 // res[j] = || HU[:, j] - E[j] U[:, j] ||
 void dev_resid(hipStream_t s, int64_t D, int n, const double* U,
                const double* HU, const double* E, double* partial, int64_t nseg,

@@ -14,6 +14,7 @@
 // bits stay inside one XCD's L2.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "chain_dev.hpp"
 #include "internal.hpp"
@@ -107,14 +108,14 @@ static void launch_qrem(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
   HIPC(hipGetLastError());
 }
 
-// Tile bits: up to 2^12 rows per tile, keeping at least 512 tiles (two per
-// CU) from L = 15 on; short chains use tiles of 64 rows.
+// Default tile bits: up to 2^12 rows per tile, keeping at least 512 tiles
+// (two per CU) from L = 15 on; short chains use tiles of 64 rows.
 int qrem_tile_bits(int L) { return std::min({L, kQremMaxTileBits, std::max(L - 9, 6)}); }
 
 template <typename T>
-void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v, const T* b1,
-               const T* b2, T* out) {
-  switch (qrem_tile_bits(op->L)) {
+static void launch_tb(hipStream_t s, const polfed_op* op, int tb, T sigma, T tau, T a, const T* v,
+                      const T* b1, const T* b2, T* out) {
+  switch (tb) {
 #define POLFED_CASE(TB)                                           \
   case TB:                                                        \
     launch_qrem<T, TB>(s, op, sigma, tau, a, v, b1, b2, out); \
@@ -125,6 +126,59 @@ void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T*
 #undef POLFED_CASE
     default: fail(POLFED_ERR_INVALID, "qrem: bad tile size");
   }
+}
+
+// Tile size picked by timing: the default and its two neighbours, 20
+// launches each on scratch vectors, at the first step of an operator in each
+// precision (not while the stream is being captured).
+template <typename T>
+static int tuned_tile_bits(hipStream_t s, const polfed_op* op) {
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  if (op->tuned[pi] >= 1) return op->tuned[pi];
+  const int t0 = qrem_tile_bits(op->L);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPC(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone || op->L < 12) return t0;
+  const size_t n = (size_t)op->D;
+  DevBuf bv(n * sizeof(T)), bb1(n * sizeof(T)), bb2(n * sizeof(T));
+  HIPC(hipMemsetAsync(bv.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(bb1.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(bb2.get(), 0, n * sizeof(T), s));
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  int best = t0;
+  float best_ms = 1e30f;
+  for (int tb = t0 - 1; tb <= t0 + 1; ++tb) {
+    if (tb < 1 || tb > std::min(op->L, kQremMaxTileBits)) continue;
+    auto go = [&] {
+      launch_tb<T>(s, op, tb, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(), bb2.as<T>(),
+                   bb2.as<T>());
+    };
+    go();
+    HIPC(hipEventRecord(e0, s));
+    for (int i = 0; i < 20; ++i) go();
+    HIPC(hipEventRecord(e1, s));
+    HIPC(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    if (verbose())
+      std::fprintf(stderr, "[polfed] qrem step L=%d %s tile bits %d: %.2f us\n", op->L,
+                   sizeof(T) == 8 ? "fp64" : "fp32", tb, 1e3f * ms / 20);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = tb;
+    }
+  }
+  HIPC(hipEventDestroy(e0));
+  HIPC(hipEventDestroy(e1));
+  return op->tuned[pi] = best;
+}
+
+template <typename T>
+void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v, const T* b1,
+               const T* b2, T* out) {
+  launch_tb<T>(s, op, tuned_tile_bits<T>(s, op), sigma, tau, a, v, b1, b2, out);
 }
 
 template void qrem_step<double>(hipStream_t, const polfed_op*, double, double, double,

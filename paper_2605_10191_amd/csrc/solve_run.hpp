@@ -180,10 +180,11 @@ struct SolveRun {
   void advance();      // CGS2, k += 1, periodic check; sets done when finished
   void filter_block();   // block mode: P(H~) of the current block into bw.w
   void advance_block();  // block mode: orthogonalization, QR, k += s, check
-  // extraction from the Ritz pairs (thf, eigenvectors Y row-major k x k) of
-  // a passed check, refinement, completion test; true when the run finished
-  // or restarted (no further check scheduling)
-  bool conclude(const std::vector<double>& thf, const std::vector<double>& Y);
+  // extraction from the Ritz pairs of a passed check (values thf, vectors
+  // in the columns of the device k x k matrix dC), refinement, completion
+  // test; true when the run finished or restarted (no further check
+  // scheduling)
+  bool conclude(const std::vector<double>& thf, const DevBuf& dC);
   void grow_band(int blocks);
   void emit(const Extracted& ex, polfed_status st);
   void fallback_fp64();  // restart the Lanczos iteration with the FP64 filter

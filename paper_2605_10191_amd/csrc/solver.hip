@@ -287,21 +287,30 @@ void rayleigh_ritz(hipStream_t s, int64_t D, int n, const double* U, const doubl
   DevBuf dG((size_t)n * n * sizeof(double));
   DevBuf part((size_t)nseg * n * sizeof(double) + 8192 * sizeof(double));
   dev_gemm_tn(s, D, n, U, HU, part.as<double>(), nseg, dG.as<double>());
-  std::vector<double> G((size_t)n * n);
-  dcopy_async(s, G.data(), dG.as<double>(), G.size(), hipMemcpyDeviceToHost);
-  HIPC(hipStreamSynchronize(s));
-  // symmetrize: G is symmetric up to rounding
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < i; ++j) {
-      const double m = 0.5 * (G[(size_t)i * n + j] + G[(size_t)j * n + i]);
-      G[(size_t)i * n + j] = G[(size_t)j * n + i] = m;
-    }
-  std::vector<double> w, Z;
-  sym_eig(n, G, w, Z);
-  DevBuf dZ((size_t)n * n * sizeof(double)), dE((size_t)n * sizeof(double)),
-      dR((size_t)n * sizeof(double));
-  dcopy_async(s, dZ.as<double>(), Z.data(), Z.size(), hipMemcpyHostToDevice);
-  dcopy_async(s, dE.as<double>(), w.data(), w.size(), hipMemcpyHostToDevice);
+  std::vector<double> w;
+  DevBuf dZ, dE((size_t)n * sizeof(double)), dR((size_t)n * sizeof(double));
+  if (n >= kDeviceEigMin) {
+    // G is symmetric up to rounding; the device solver reads its lower part
+    dev_syevd(s, n, dG.as<double>(), dE.as<double>());
+    w.resize(n);
+    dcopy_async(s, w.data(), dE.as<double>(), (size_t)n, hipMemcpyDeviceToHost);
+    dZ = std::move(dG);
+  } else {
+    std::vector<double> G((size_t)n * n);
+    dcopy_async(s, G.data(), dG.as<double>(), G.size(), hipMemcpyDeviceToHost);
+    HIPC(hipStreamSynchronize(s));
+    // symmetrize: G is symmetric up to rounding
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j) {
+        const double m = 0.5 * (G[(size_t)i * n + j] + G[(size_t)j * n + i]);
+        G[(size_t)i * n + j] = G[(size_t)j * n + i] = m;
+      }
+    std::vector<double> Z;
+    sym_eig(n, G, w, Z);
+    dZ.alloc((size_t)n * n * sizeof(double));
+    dcopy_async(s, dZ.as<double>(), Z.data(), Z.size(), hipMemcpyHostToDevice);
+    dcopy_async(s, dE.as<double>(), w.data(), w.size(), hipMemcpyHostToDevice);
+  }
   DevBuf U2((size_t)D * n * sizeof(double)), HU2((size_t)D * n * sizeof(double));
   dev_gemm_nn(s, D, n, n, U, D, dZ.as<double>(), U2.as<double>(), D);
   dev_gemm_nn(s, D, n, n, HU, D, dZ.as<double>(), HU2.as<double>(), D);
@@ -348,12 +357,10 @@ namespace {
 // u = V t for the selected Ritz vectors, Rayleigh-Ritz with H on their span
 // and residual norms.
 Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, int m,
-                  const std::vector<double>& Ysel /* m x n col-major */, int n) {
+                  const DevBuf& dY /* m x n col-major, device */, int n) {
   hipStream_t s = ctx->stream;
   const int64_t D = op->D;
   Extracted ex;
-  DevBuf dY((size_t)m * n * sizeof(double));
-  dcopy_async(s, dY.as<double>(), Ysel.data(), (size_t)m * n, hipMemcpyHostToDevice);
   DevBuf U((size_t)D * n * sizeof(double)), HU((size_t)D * n * sizeof(double));
   dev_gemm_nn(s, D, m, n, B.V.as<double>(), D, dY.as<double>(), U.as<double>(), D);
   for (int j = 0; j < n; ++j) apply_H(s, op, U.as<double>() + (size_t)j * D, HU.as<double>() + (size_t)j * D);
@@ -633,9 +640,27 @@ void SolveRun::advance() {
                  n_want, est_max, tol_ritz, (int)conv);
   R.t_check += now_seconds() - tc;
   if (conv || k >= M_max) {
-    std::vector<double> thf, Y;
-    ritz_full(k, al, be, thf, Y);
-    if (conclude(thf, Y)) return;
+    std::vector<double> thf;
+    DevBuf dC;  // eigenvectors of the tridiagonal matrix, k x k col-major
+    if (k >= kDeviceEigMin) {
+      DevBuf dd((size_t)k * sizeof(double)), de((size_t)k * sizeof(double));
+      dC.alloc((size_t)k * k * sizeof(double));
+      dcopy_async(s, dd.as<double>(), al.data(), (size_t)k, hipMemcpyHostToDevice);
+      if (k > 1)
+        dcopy_async(s, de.as<double>(), be.data() + 1, (size_t)(k - 1), hipMemcpyHostToDevice);
+      dev_stedc(s, k, dd.as<double>(), de.as<double>(), dC.as<double>());
+      thf.resize(k);
+      dcopy_async(s, thf.data(), dd.as<double>(), (size_t)k, hipMemcpyDeviceToHost);
+      HIPC(hipStreamSynchronize(s));
+    } else {
+      std::vector<double> Y;
+      ritz_full(k, al, be, thf, Y);
+      std::vector<double> Yc((size_t)k * k);
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) Yc[(size_t)j * k + i] = Y[(size_t)i * k + j];
+      upload(dC, Yc.data(), Yc.size(), s);
+    }
+    if (conclude(thf, dC)) return;
   }
   next_check = k + check_every;
 }
@@ -643,18 +668,20 @@ void SolveRun::advance() {
 // After a passed check (or at the Krylov limit): the n_want largest Ritz
 // values of P(H~) and their vectors u = V t, Rayleigh-Ritz with H, the
 // selection and the completeness test; refinement of an FP32-filtered run.
-bool SolveRun::conclude(const std::vector<double>& thf, const std::vector<double>& Y) {
+bool SolveRun::conclude(const std::vector<double>& thf, const DevBuf& dC) {
+  hipStream_t s = ctx->stream;
   const double tx = now_seconds();
   const int nw = std::min(n_want, k);
   // pick the n_want largest
   std::vector<int> ord(k);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return thf[x] > thf[y]; });
-  std::vector<double> Ysel((size_t)k * nw);
+  DevBuf dY((size_t)k * nw * sizeof(double));
   for (int j = 0; j < nw; ++j)
-    for (int i = 0; i < k; ++i) Ysel[(size_t)j * k + i] = Y[(size_t)i * k + ord[j]];
+    dcopy_async(s, dY.as<double>() + (size_t)j * k, dC.as<double>() + (size_t)ord[j] * k,
+                (size_t)k, hipMemcpyDeviceToDevice);
   const double theta_min = thf[ord[nw - 1]];
-  Extracted ex = extract(ctx, op, B, ws, k, Ysel, nw);
+  Extracted ex = extract(ctx, op, B, ws, k, dY, nw);
   select_pairs(ex, lam, p.n_ev, tol_resid, theta_min, pl);
   R.t_extract += now_seconds() - tx;
   if (verbose()) {

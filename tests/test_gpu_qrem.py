@@ -54,13 +54,14 @@ def test_qrem_clenshaw_step_matches_oracle(pk, ctx, L, prec, final):
     assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("L", [20, 21, 24])
+@pytest.mark.parametrize("L,tb", [(20, 10), (20, 11), (20, 12), (21, 12), (24, 11), (24, 12)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_qrem_full_size_step_sampled_rows(pk, ctx, L, prec):
-    """Tiles of 2^11 (L = 20) and 2^12 rows (L = 21, 24): sampled rows of
+def test_qrem_full_size_step_sampled_rows(pk, ctx, L, tb, prec):
+    """Full-size steps with tiles of 2^10 to 2^12 rows: sampled rows of
     a v + 2 H~ b1 - b2 against the oracle's row-by-row eq. (qrem)."""
-    say(f"qrem sampled step L={L} {prec}")
+    say(f"qrem sampled step L={L} tile bits {tb} {prec}")
     op, E = qrem_case(pk, ctx, L, 3)
+    assert op.set_kernel(pk.FP64 if prec == "fp64" else pk.FP32, tb) == tb
     rng = np.random.default_rng(5)
     v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
     dt = torch.float64 if prec == "fp64" else torch.float32
@@ -149,3 +150,24 @@ def test_qrem_invalid(pk, ctx):
     op, _ = qrem_case(pk, ctx, 6, 0)
     with pytest.raises(pk.PolfedError):
         op.materialize_csr()
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_qrem_many_pairs_device_eigensolvers(pk, ctx, s):
+    """300 pairs of QREM L=11: the Rayleigh-Ritz matrix (n = 360) and the
+    Lanczos matrix (M > 256) go through the device eigensolvers."""
+    say(f"qrem L=11 300 pairs s={s}")
+    op, E = qrem_case(pk, ctx, 11, 9)
+    H = models.qrem(11, E, 1.0)
+    X0 = np.stack([wl.start_vector(op.D, c) for c in range(s)])
+    x0 = dev(X0[0]) if s == 1 else dev(X0)
+    evals, evecs, res, rep, status = pk.solve(op, x0, 300, 0.0, "maxdos")
+    assert status == "OK"
+    assert rep["iters"] >= 256 and rep["n_want"] >= 256
+    Ev, U, R = host(evals), host(evecs), host(res)
+    Er, Ur = dense.nearest_eigenpairs(H, rep["lambda"], 300)
+    rel = np.abs(Ev - Er) / np.maximum(np.abs(Er), 1.0)
+    say(f"   K={rep['K']} iters={rep['iters']} rel={rel.max():.1e} res={R.max():.1e}")
+    assert rel.max() <= 1e-10 and R.max() <= 1e-8
+    assert np.linalg.norm(H @ U - U * Ev, axis=0).max() <= 1e-8
+    assert np.min(np.abs(np.sum(U * Ur, axis=0))) >= 1 - 1e-8
