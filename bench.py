@@ -188,7 +188,52 @@ def kernel_legs(pk, wl, ctx, L, W, iters):
         out[f"tv_L26_{name}"] = {"GBps": round(4 * w * D26 / (avg * 1e-3) / 1e9, 1),
                                  "us": round(avg * 1e3, 2), "bytes": 4 * w * D26, "D": D26}
     op26.close()
+    # quantum random energy model, full 2^L space: the hypercube step kernel
+    for Lq in (20, 24):
+        opq = pk.Operator.qrem(ctx, Lq, wl.qrem_energies(Lq, 0), 1.0)
+        for prec, w, name in ((pk.FP64, 8, "fp64"), (pk.FP32, 4, "fp32")):
+            avg, _ = pk.profile_step(opq, prec, max(20, iters // 4))
+            b = 5 * w * opq.D  # v, b1, b2 and the energies read, out written
+            out[f"qrem_L{Lq}_{name}"] = {"GBps": round(b / (avg * 1e-3) / 1e9, 1),
+                                         "us": round(avg * 1e3, 2), "bytes": b,
+                                         "tile_bits": opq.set_kernel(prec, -2)}
+        opq.close()
     return out
+
+
+def qrem_leg(pk, wl, ctx, L, n_ev, block_size=1):
+    """The paper's GPU benchmark shape (Sec. 6, CPU vs GPU): quantum random
+    energy model L = 20 (D = 2^20), Gamma = 1, n_ev pairs at the maximum of
+    the density of states, FP64."""
+    import torch
+    op = pk.Operator.qrem(ctx, L, wl.qrem_energies(L, 0), 1.0)
+    if block_size > 1:
+        x0 = torch.tensor(np.stack([wl.start_vector(op.D, c) for c in range(block_size)]),
+                          device=ctx.torch_device)
+    else:
+        x0 = torch.tensor(wl.start_vector(op.D, 0), device=ctx.torch_device)
+    log(f"qrem solve L={L} n_ev={n_ev} s={block_size}: start")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, U, r, rep, status = pk.solve(op, x0, n_ev, 0.0, "maxdos", allow_partial=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"qrem solve L={L} n_ev={n_ev} s={block_size}: {dt:.1f}s {status} K={rep['K']} "
+        f"M={rep['iters']} t_filter={rep['t_filter']:.1f} t_reorth={rep['t_reorth']:.1f} "
+        f"t_check={rep['t_check']:.1f} t_extract={rep['t_extract']:.1f}")
+    res = {"solve_s": round(dt, 1), "status": status, "n_found": len(ev), "K": rep["K"],
+           "krylov_dim": rep["iters"], "block_size": block_size,
+           "max_resid": float(r.max().item()) if len(r) else None,
+           "t_bounds": round(rep["t_bounds"], 2), "t_filter": round(rep["t_filter"], 1),
+           "t_reorth": round(rep["t_reorth"], 1), "t_check": round(rep["t_check"], 1),
+           "t_extract": round(rep["t_extract"], 1), "filter_GBps": round(rep["filter_GBps"], 1),
+           "lambda": rep["lambda"], "D": op.D,
+           "workload": f"QREM L={L}, Gamma=1, energies N(0, L/2) seed 0, {n_ev} pairs at the "
+                       "DOS maximum, FP64 (the paper's GPU benchmark shape: about 6 min on "
+                       "one GPU of unnamed model)"}
+    del U
+    op.close()
+    return res
 
 
 def qsun_leg(pk, wl, ctx):
@@ -347,6 +392,11 @@ def main():
     ap.add_argument("--W", type=float, default=3.0)
     ap.add_argument("--n-ev", type=int, default=100)
     ap.add_argument("--solve-L", type=int, default=20)
+    ap.add_argument("--qrem-pairs", type=int, default=0,
+                    help="also solve QREM for this many pairs at the DOS maximum "
+                         "(the paper's GPU benchmark uses 1500 at L=20; several minutes)")
+    ap.add_argument("--qrem-L", type=int, default=20)
+    ap.add_argument("--qrem-block", type=int, default=1)
     ap.add_argument("--block-sizes", default="4,8",
                     help="block Lanczos legs of the solve benchmark (comma list)")
     ap.add_argument("--no-solve", action="store_true")
@@ -477,6 +527,9 @@ def main():
         out["eigenpairs_per_s"] = {"value": sl["fp64"]["eigenpairs_per_s"],
                                    "unit": "eigenpairs/s", **sl}
         out["qsun"] = qsun_leg(pk, wl, ctx)
+    if args.qrem_pairs > 0:
+        out["qrem_paper_shape"] = qrem_leg(pk, wl, ctx, args.qrem_L, args.qrem_pairs,
+                                           args.qrem_block)
     if not args.no_serve:
         sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
                          args.serve_cols, pk.FP32, rate=args.serve_rate)

@@ -350,7 +350,8 @@ void SolveRun::advance_block() {
   for (double t : th) thmax = std::max(thmax, std::fabs(t));
   bool conv = true;
   double est_max = 0;
-  for (int q = 0; q < nw; ++q) {
+  int lead = 0;  // leading run of converged Ritz values, from the largest
+  for (int q = 0; q < k; ++q) {
     const int jj = order[q];
     double e2 = 0;
     for (int i = 0; i < s; ++i) {
@@ -359,22 +360,32 @@ void SolveRun::advance_block() {
       e2 += acc * acc;
     }
     const double e = std::sqrt(e2);
-    est_max = std::max(est_max, e);
-    if (e > tol_ritz * std::max(1.0, thmax)) conv = false;
+    const bool ok_q = e <= tol_ritz * std::max(1.0, thmax);
+    if (q < nw) {
+      est_max = std::max(est_max, e);
+      if (!ok_q) conv = false;
+    }
+    if (ok_q && lead == q) ++lead;
+    if (!ok_q && q >= nw) break;
   }
+  const bool early = !conv && early_ready(lead);
   if (verbose())
-    std::fprintf(stderr, "[polfed] block check k=%d s=%d n_want=%d max |B tau|=%.2e tol=%.1e conv=%d\n",
-                 k, s, n_want, est_max, tol_ritz, (int)conv);
+    std::fprintf(stderr,
+                 "[polfed] block check k=%d s=%d n_want=%d max |B tau|=%.2e tol=%.1e conv=%d "
+                 "lead=%d\n",
+                 k, s, n_want, est_max, tol_ritz, (int)conv, lead);
   R.t_check += now_seconds() - tc;
-  if (conv || k >= M_max) {
+  if (conv || k >= M_max || early) {
+    const bool full = conv || k >= M_max;
+    const int take = full ? nw : lead;
     if (k >= kDeviceEigMin) {
-      if (conclude(th, dA)) return;
+      if (conclude(th, dA, take, !full)) return;
     } else {
       std::vector<double> thf, Z;
       sym_eig(k, H, thf, Z);
       DevBuf dZ;
       upload(dZ, Z.data(), Z.size(), st);
-      if (conclude(thf, dZ)) return;
+      if (conclude(thf, dZ, take, !full)) return;
     }
   }
   next_check = k + check_every;

@@ -184,7 +184,11 @@ struct SolveRun {
   // in the columns of the device k x k matrix dC), refinement, completion
   // test; true when the run finished or restarted (no further check
   // scheduling)
-  bool conclude(const std::vector<double>& thf, const DevBuf& dC);
+  // the nw Ritz vectors of the largest values are extracted; early: the
+  // check has not passed yet, so a failure only returns false
+  bool conclude(const std::vector<double>& thf, const DevBuf& dC, int nw, bool early);
+  bool early_ready(int lead);  // whether to try an early extraction now
+  int early_lead = 0;          // leading converged run at the last early try
   void grow_band(int blocks);
   void emit(const Extracted& ex, polfed_status st);
   void fallback_fp64();  // restart the Lanczos iteration with the FP64 filter

@@ -467,6 +467,7 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   next_check = std::min(whole(n_want), M_max);
   k = 0;
   brk_from = 1;
+  early_lead = 0;
   done = false;
   status = POLFED_NOT_CONVERGED;
   restart_seed = 0x5EEDULL;
@@ -630,16 +631,23 @@ void SolveRun::advance() {
   for (double t : th) thmax = std::max(thmax, std::fabs(t));
   bool conv = true;
   double est_max = 0;
-  for (int j = 0; j < nw; ++j) {
+  int lead = 0;  // leading run of converged Ritz values, from the largest
+  for (int j = 0; j < k; ++j) {
     const double e = std::fabs(be[k] * zl[order[j]]);
-    est_max = std::max(est_max, e);
-    if (e > tol_ritz * std::max(1.0, thmax)) conv = false;
+    const bool ok_j = e <= tol_ritz * std::max(1.0, thmax);
+    if (j < nw) {
+      est_max = std::max(est_max, e);
+      if (!ok_j) conv = false;
+    }
+    if (ok_j && lead == j) ++lead;
+    if (!ok_j && j >= nw) break;
   }
+  const bool early = !conv && early_ready(lead);
   if (verbose())
-    std::fprintf(stderr, "[polfed] check k=%d n_want=%d max |beta z|=%.2e tol=%.1e conv=%d\n", k,
-                 n_want, est_max, tol_ritz, (int)conv);
+    std::fprintf(stderr, "[polfed] check k=%d n_want=%d max |beta z|=%.2e tol=%.1e conv=%d lead=%d\n",
+                 k, n_want, est_max, tol_ritz, (int)conv, lead);
   R.t_check += now_seconds() - tc;
-  if (conv || k >= M_max) {
+  if (conv || k >= M_max || early) {
     std::vector<double> thf;
     DevBuf dC;  // eigenvectors of the tridiagonal matrix, k x k col-major
     if (k >= kDeviceEigMin) {
@@ -660,18 +668,37 @@ void SolveRun::advance() {
         for (int j = 0; j < k; ++j) Yc[(size_t)j * k + i] = Y[(size_t)i * k + j];
       upload(dC, Yc.data(), Yc.size(), s);
     }
-    if (conclude(thf, dC)) return;
+    if (conv || k >= M_max) {
+      if (conclude(thf, dC, nw, false)) return;
+    } else if (conclude(thf, dC, lead, true)) {
+      return;
+    }
   }
   next_check = k + check_every;
+}
+
+// An extraction before all n_want leading Ritz values have converged: once
+// a leading run of converged values covers N_ev plus half the buffer, their
+// pairs may already hold the N_ev nearest the target and pass the
+// completeness test.  Tried again only after the run has grown by a
+// twentieth of N_ev (at least 5).  FP64 filter only: an FP32 run refines at
+// its extraction instead.
+bool SolveRun::early_ready(int lead) {
+  if (fp32) return false;
+  const int need = p.n_ev + (n_want0 - p.n_ev + 1) / 2;
+  if (lead < need || lead >= std::min(n_want, k)) return false;
+  if (lead < early_lead + std::max(5, p.n_ev / 20)) return false;
+  early_lead = lead;
+  return true;
 }
 
 // After a passed check (or at the Krylov limit): the n_want largest Ritz
 // values of P(H~) and their vectors u = V t, Rayleigh-Ritz with H, the
 // selection and the completeness test; refinement of an FP32-filtered run.
-bool SolveRun::conclude(const std::vector<double>& thf, const DevBuf& dC) {
+bool SolveRun::conclude(const std::vector<double>& thf, const DevBuf& dC, int nw, bool early) {
   hipStream_t s = ctx->stream;
   const double tx = now_seconds();
-  const int nw = std::min(n_want, k);
+  nw = std::min(nw, k);
   // pick the n_want largest
   std::vector<int> ord(k);
   std::iota(ord.begin(), ord.end(), 0);
@@ -687,8 +714,19 @@ bool SolveRun::conclude(const std::vector<double>& thf, const DevBuf& dC) {
   if (verbose()) {
     int acc = 0;
     for (double r : ex.res) acc += r <= tol_resid;
-    std::fprintf(stderr, "[polfed] extract k=%d accepted=%d selected=%d complete=%d theta_min=%.4f\n",
-                 k, acc, (int)ex.sel.size(), (int)ex.complete, theta_min);
+    std::fprintf(stderr,
+                 "[polfed] extract k=%d vectors=%d%s accepted=%d selected=%d complete=%d "
+                 "theta_min=%.4f\n",
+                 k, nw, early ? " (early)" : "", acc, (int)ex.sel.size(), (int)ex.complete,
+                 theta_min);
+  }
+  if (early) {
+    // not finished yet: the iteration goes on to the regular check
+    if ((int)ex.sel.size() == p.n_ev && ex.complete) {
+      emit(ex, POLFED_OK);
+      return true;
+    }
+    return false;
   }
   if (fp32 && !((int)ex.sel.size() == p.n_ev && ex.complete)) {
     const double tr = now_seconds();
@@ -727,6 +765,7 @@ void SolveRun::fallback_fp64() {
   ws.bB.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
   k = 0;
   brk_from = 1;
+  early_lead = 0;
   n_want = n_want0;
   next_check = std::min(((n_want + s - 1) / s) * s, M_max);
   // block mode: the start block (columns 0..s-1) is kept; the filter
