@@ -16,6 +16,7 @@ import math
 import numpy as np
 
 from . import filter as flt
+from . import kpm
 from . import lanczos as lz
 
 
@@ -62,9 +63,10 @@ def buffer_size(n_ev: int) -> int:
 
 def plan(H, lam: float, n_window: int, E_min: float, E_max: float,
          pad: float = 1e-3, omega: float = flt.OMEGA_DEFAULT,
-         K: int | None = None):
-    """Steps 1-3: rescaling, Gaussian DOS, window half-width delta for
-    n_window eigenvalues, order K and the filter coefficients."""
+         K: int | None = None, kpm_mu=None):
+    """Steps 1-3: rescaling, the DOS at the target (Gaussian, or KPM from the
+    moments kpm_mu of H~ when given), window half-width delta for n_window
+    eigenvalues, order K and the filter coefficients."""
     D = H.shape[0]
     lo, hi = lz.padded_bounds(E_min, E_max, pad)
     E_c, dE = flt.rescale(lo, hi)
@@ -72,7 +74,10 @@ def plan(H, lam: float, n_window: int, E_min: float, E_max: float,
     m1, m2 = flt.trace_moments(H)
     mu_t = (m1 - E_c) / dE
     Gamma_t = math.sqrt(max(m2 - m1 * m1, 0.0)) / dE
-    rho = float(flt.gaussian_dos(lam_t, D, mu_t, Gamma_t))
+    if kpm_mu is None:
+        rho = float(flt.gaussian_dos(lam_t, D, mu_t, Gamma_t))
+    else:
+        rho = float(kpm.density(kpm_mu, np.array([lam_t]))[0])
     delta = flt.window_halfwidth(n_window, rho)
     if K is None:
         K = flt.choose_K(lam_t, delta, omega)
@@ -86,7 +91,8 @@ def polfed(H, x0: np.ndarray, n_ev: int, target: float,
            target_kind: str = "absolute", pad: float = 1e-3,
            omega: float = flt.OMEGA_DEFAULT, eta: float = 1.5,
            K: int | None = None, tol_P: float = 1e-10,
-           tol_resid: float = 1e-8, bounds=None):
+           tol_resid: float = 1e-8, bounds=None, kpm_vectors=None,
+           kpm_moments: int = 0):
     """N_ev eigenpairs of H nearest the target.  Returns a dict with E (sorted
     by distance to lambda), U (columns), res, and the plan.  A vector x0
     runs Lanczos; a D x s matrix x0 runs block Lanczos with block size s (the
@@ -96,11 +102,20 @@ def polfed(H, x0: np.ndarray, n_ev: int, target: float,
     else:
         E_min, E_max = bounds
     tr1, _ = flt.trace_moments(H)
-    lam = target_energy(target_kind, target, E_min, E_max, tr1)
+    mu = None
+    if kpm_vectors is not None:
+        # KPM DOS (Sec. 4.1): moments of H~ in the padded rescaling of the plan
+        E_c, dE = flt.rescale(*lz.padded_bounds(E_min, E_max, pad))
+        mu = kpm.moments(H, E_c, dE, kpm_vectors, kpm_moments)
+    if mu is not None and target_kind in ("maxdos", "offset"):
+        em = E_c + kpm.maxdos_point(mu, *kpm.search_interval(E_min, E_max, E_c, dE)) * dE
+        lam = target_energy(target_kind, target, E_min, E_max, em)
+    else:
+        lam = target_energy(target_kind, target, E_min, E_max, tr1)
     n_want = n_ev + buffer_size(n_ev)
     # the window is sized for all n_want pairs, so that the n_ev nearest sit
     # well inside the main lobe of the filter
-    p = plan(H, lam, n_want, E_min, E_max, pad, omega, K)
+    p = plan(H, lam, n_want, E_min, E_max, pad, omega, K, mu)
 
     def apply_P(v):
         return flt.apply_filter(H, p["E_c"], p["dE"], p["a"], v)
