@@ -311,6 +311,21 @@ polfed_status polfed_block_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
                                         double E_c, double dE, const double* a,
                                         int K, double* V, int k, int s, double* A,
                                         double* Bn, int precision);
+/* Kernel polynomial method (Sec. 4.1 eq. dos_kpm, App. B): mu[n] for
+ * n < N, the mean over R vectors r of <r| T_n(H~) |r> with H~ = (H - E_c)/dE,
+ * by the three-term Chebyshev recurrence on the fused step kernel (FP64).
+ * r: device D x R column-major, or NULL: then vector c (0 <= c < R) has
+ * entries sqrt(3) (2 u - 1), u = (z >> 11) / 2^53 for the splitmix64 output
+ * z of seed + c at counter i + 1 (zero mean, unit variance).  mu: host [N].
+ * Synchronizes. */
+polfed_status polfed_kpm_moments(polfed_ctx* ctx, const polfed_op* op, double E_c,
+                                 double dE, int N, int R, const double* r, uint64_t seed,
+                                 double* mu);
+/* The Jackson-damped KPM density rho(x) = [mu_0 g_0 + 2 sum_{n=1}^{N-1}
+ * mu_n g_n T_n(x)] / (pi sqrt(1 - x^2)) at nx host points x in (-1, 1).
+ * Host only. */
+polfed_status polfed_kpm_density(const double* mu, int N, const double* x, int nx,
+                                 double* rho);
 /* Measurement helper: times `iters` back-to-back launches of the fused
  * Clenshaw step kernel on scratch vectors with one pair of HIP events on the
  * context stream (mean = elapsed / iters, the rate of a running recurrence)
@@ -341,6 +356,11 @@ typedef struct {
                           runs out hands the solve to the FP64 filter */
   int block_size;      /* 0 or 1: Lanczos; s in 2..64: block Lanczos with
                           blocks of s vectors (Sec. 2.2), polfed_solve only */
+  int kpm_moments;     /* 0: Gaussian DOS from the traces; N > 0: KPM DOS
+                          (Sec. 4.1 eq. dos_kpm, Jackson kernel) with N
+                          moments, for the window and the maxdos point */
+  int kpm_vectors;     /* KPM: random vectors (0: 100); drawn as in
+                          polfed_kpm_moments with r = NULL and seed 0x4B504D */
 } polfed_params;
 
 typedef struct {

@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
                 ("bound_pad", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("E_min", ctypes.c_double), ("E_max", ctypes.c_double),
                 ("graph", ctypes.c_int), ("refine_max", ctypes.c_int),
-                ("block_size", ctypes.c_int)]
+                ("block_size", ctypes.c_int), ("kpm_moments", ctypes.c_int),
+                ("kpm_vectors", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -115,6 +116,8 @@ SIGNATURES = {
                                    _P, _P, _P, _I, _I],
     "polfed_bounds": [_P, _P, _P, _D, _I, _DP, _DP],
     "polfed_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _P, _P, _I],
+    "polfed_kpm_moments": [_P, _P, _D, _D, _I, _I, _P, ctypes.c_uint64, _DP],
+    "polfed_kpm_density": [_DP, _I, _DP, _I, _DP],
     "polfed_block_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _I, _P, _P, _I],
     "polfed_profile_step": [_P, _P, _I, _I, _DP, _DP],
     "polfed_params_default": [ctypes.POINTER(Params)],
@@ -495,6 +498,26 @@ def block_lanczos_step(op: Operator, E_c, dE, a, V, k, s, A, Bn, precision=FP64)
     _check(_lib.polfed_block_lanczos_step(op.ctx.handle, op.handle, E_c, dE, _dptr(a),
                                           len(a) - 1, _ptr(V), int(k), int(s), _ptr(A),
                                           _ptr(Bn), precision))
+
+
+def kpm_moments(op: Operator, E_c, dE, N, R, vectors=None, seed=0) -> np.ndarray:
+    """KPM moments mu_0..mu_{N-1} of H~ = (H - E_c)/dE averaged over R random
+    vectors: `vectors` is a (R, D) device tensor (rows = vectors), or None for
+    the library's counter-based draws from `seed`."""
+    mu = np.zeros(int(N))
+    _check(_lib.polfed_kpm_moments(op.ctx.handle, op.handle, float(E_c), float(dE), int(N),
+                                   int(R), _ptr(vectors) if vectors is not None else None,
+                                   int(seed), _dptr(mu)))
+    return mu
+
+
+def kpm_density(mu, x) -> np.ndarray:
+    """Jackson-damped KPM density at the points x (host)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    x = np.ascontiguousarray(np.atleast_1d(x), dtype=np.float64)
+    rho = np.zeros_like(x)
+    _check(_lib.polfed_kpm_density(_dptr(mu), len(mu), _dptr(x), len(x), _dptr(rho)))
+    return rho
 
 
 def profile_step(op: Operator, precision=FP64, iters=200):

@@ -673,6 +673,27 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E
   });
 }
 
+polfed_status polfed_kpm_moments(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
+                                 int N, int R, const double* r, uint64_t seed, double* mu) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(mu, "null output");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    kpm_moments(ctx, op, E_c, dE, N, R, r, seed, mu);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_kpm_density(const double* mu, int N, const double* x, int nx, double* rho) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(mu && x && rho && nx >= 0, "null argument");
+    kpm_density(mu, N, x, nx, rho);
+    return POLFED_OK;
+  });
+}
+
 polfed_status polfed_block_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c,
                                         double dE, const double* a, int K, double* V, int k,
                                         int s, double* A, double* Bn, int precision) {

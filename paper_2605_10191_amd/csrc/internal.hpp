@@ -368,13 +368,25 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
 void sym_eig_tail(int n, const std::vector<double>& A, int r, std::vector<double>& w,
                   std::vector<double>& Ztail);
 
+// ----------------------------------------------------------------- kpm ----
+// mu[0..N) = mean over R vectors of <r|T_n(H~)|r>; rvecs: device D x R, or
+// null for vectors drawn from the counter-based generator of dev_random
+// (vector c with seed + c), scaled to unit variance.
+void kpm_moments(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE, int N, int R,
+                 const double* rvecs, uint64_t seed, double* mu);
+void kpm_density(const double* mu, int N, const double* x, int nx, double* rho);
+// argmax of the KPM density over the Chebyshev nodes of 4096 that lie in [lo, hi]
+double kpm_maxdos(const double* mu, int N, double lo, double hi);
+constexpr uint64_t kKpmSeed = 0x4B504DULL;  // random vectors of the KPM DOS of a solve
+
 // ---------------------------------------------------------------- plan ----
 double filter_value_closed(double lambda_t, int K, double x);
 void filter_coefficients(double lambda_t, int K, double* a);
 void filter_quotient(const double* a, int K, double theta, double* q, double* p_theta);
 polfed_plan make_plan(int64_t D, double E_min, double E_max, double pad,
                       double lambda, double tr1, double tr2, int n_window,
-                      double omega, int K_override);
+                      double omega, int K_override, const double* kpm_mu = nullptr,
+                      int kpm_n = 0);
 constexpr double kOmegaDefault = 0.17612720216036546;  // sin(2.655)/2.655
 int expected_krylov_dim(int howmany, int blocksize, double eta);
 

@@ -95,7 +95,7 @@ int expected_krylov_dim(int howmany, int blocksize, double eta) {
 
 polfed_plan make_plan(int64_t D, double E_min, double E_max, double pad,
                       double lambda, double tr1, double tr2, int n_window,
-                      double omega, int K_override) {
+                      double omega, int K_override, const double* kpm_mu, int kpm_n) {
   REQUIRE(D >= 1, "plan: empty operator");
   REQUIRE(std::isfinite(E_min) && std::isfinite(E_max) && E_max > E_min,
           "plan: need finite E_min < E_max");
@@ -116,6 +116,13 @@ polfed_plan make_plan(int64_t D, double E_min, double E_max, double pad,
   if (!(p.Gamma_t > 0)) p.Gamma_t = 1e-300;
   const double z = (p.lambda_t - p.mu_t) / p.Gamma_t;
   p.rho = (double)D / (std::sqrt(2.0 * M_PI) * p.Gamma_t) * std::exp(-0.5 * z * z);
+  if (kpm_n > 0) {
+    // KPM density at the target (Sec. 4.1 eq. dos_kpm); a stochastic
+    // estimate that is not positive there leaves the Gaussian one
+    double r = 0;
+    kpm_density(kpm_mu, kpm_n, &p.lambda_t, 1, &r);
+    if (r > 0 && std::isfinite(r)) p.rho = r;
+  }
   p.delta = n_window / (2.0 * p.rho);
   p.K_approx = 2.655 * std::sqrt(std::max(0.0, 1.0 - p.lambda_t * p.lambda_t)) / p.delta;
   if (K_override > 0) {

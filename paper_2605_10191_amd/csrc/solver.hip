@@ -422,13 +422,27 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   HIPC(hipMemcpyAsync(tr, two.get(), sizeof tr, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   const double tr1 = tr[0] / (double)D, tr2 = tr[1] / (double)D;
-  lam = target_energy(p.target_kind, p.target, E_min, E_max, tr1);
+  // KPM density of states (Sec. 4.1) in the rescaled coordinates of the
+  // padded bounds, when asked for: it sets the window and the maxdos point
+  std::vector<double> kmu;
+  double peak = tr1;  // maxdos point: the Gaussian estimate's mean by default
+  if (p.kpm_moments > 0) {
+    const double w = E_max - E_min, lo = E_min - pad * w, hi = E_max + pad * w;
+    const double Ec = 0.5 * (hi + lo), dEk = 0.5 * (hi - lo);
+    kmu.resize(p.kpm_moments);
+    kpm_moments(ctx, op, Ec, dEk, p.kpm_moments, p.kpm_vectors > 0 ? p.kpm_vectors : 100,
+                nullptr, kKpmSeed, kmu.data());
+    peak = Ec + dEk * kpm_maxdos(kmu.data(), p.kpm_moments, (E_min + 0.05 * w - Ec) / dEk,
+                                 (E_max - 0.05 * w - Ec) / dEk);
+  }
+  lam = target_energy(p.target_kind, p.target, E_min, E_max, peak);
   // FP32 bulk keeps twice the buffer: the window edge moves away from the
   // wanted pairs, whose refinement then converges in about two sweeps (the
   // wider window also lowers K, so the Lanczos work stays about the same)
   n_want = (int)std::min<int64_t>(D, p.n_ev + (fp32 ? 2 : 1) * buffer_size(p.n_ev));
   n_want0 = n_want;
-  pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega, p.K_override);
+  pl = make_plan(D, E_min, E_max, pad, lam, tr1, tr2, n_want, p.omega, p.K_override,
+                 kmu.empty() ? nullptr : kmu.data(), (int)kmu.size());
   a.assign(pl.K + 1, 0.0);
   filter_coefficients(pl.lambda_t, pl.K, a.data());
   // An FP32 recurrence carries a relative error of a few times sqrt(K) unit

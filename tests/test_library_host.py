@@ -153,3 +153,14 @@ def test_filter_quotient_is_the_divided_difference(pk, K, theta):
 def test_filter_quotient_order_zero(pk):
     q, p_th = pk.filter_quotient([0.7], 0.2)
     assert q.shape == (0,) and p_th == 0.7
+
+
+def test_kpm_density_matches_oracle(pk):
+    """The host KPM density (Clenshaw sum) against the oracle's cosine form."""
+    from oracle import kpm
+    mu = np.random.default_rng(2).standard_normal(70) * np.exp(-0.05 * np.arange(70))
+    mu[0] = 50.0
+    x = np.linspace(-0.97, 0.97, 301)
+    got = pk.kpm_density(mu, x)
+    ref = kpm.density(mu, x)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))

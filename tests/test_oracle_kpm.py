@@ -86,3 +86,11 @@ def test_polfed_with_kpm_dos_vs_dense():
     # the KPM maximum lies near the Gaussian one for this near-Gaussian DOS
     tr1, tr2 = flt.trace_moments(H)
     assert abs(out["lam"] - tr1) < 0.1 * math.sqrt(tr2 - tr1 * tr1)
+
+
+def test_splitmix_draws_have_unit_variance_and_differ_per_vector():
+    R = kpm.splitmix_vectors(20000, 3, 7)
+    assert np.all(np.abs(R.mean(axis=0)) < 0.03)
+    assert np.all(np.abs(R.var(axis=0) - 1.0) < 0.03)
+    assert np.all(np.abs(R) < np.sqrt(3.0))
+    assert abs(np.corrcoef(R[:, 0], R[:, 1])[0, 1]) < 0.03
