@@ -59,6 +59,47 @@ def _occupied_below(s: np.ndarray, site: int) -> np.ndarray:
     return np.bitwise_count(s & ((1 << site) - 1)).astype(np.int64)
 
 
+def spin_chain(L: int, N: int, Js, Deltas, h, periodic: bool = True):
+    """Spin-1/2 chain with couplings of range r = 1..R, eqs. (j1j2) and
+    (j1j2j3) of App. A (R = 2, 3; R = 1 is eq. (xxz)):
+        H = sum_r J_r sum_i (S^x_i S^x_{i+r} + S^y_i S^y_{i+r} + Delta_r S^z_i S^z_{i+r})
+            + sum_i h_i S^z_i
+    in the sector with N up spins; periodic bonds wrap around (needs L > 2R).
+    Returns (H_csr, states)."""
+    h = np.asarray(h, dtype=np.float64)
+    Js = [float(x) for x in Js]
+    Deltas = [float(x) for x in Deltas]
+    assert h.shape == (L,) and len(Js) == len(Deltas) >= 1
+    assert not periodic or L > 2 * len(Js)
+    states = basis.sector_states(L, N)
+    D = len(states)
+    rows = np.arange(D, dtype=np.int64)
+    diag = np.zeros(D)
+    for i in range(L):
+        diag += h[i] * (_bit(states, i) - 0.5)
+    r_list, c_list, v_list = [rows], [rows], [None]
+    for r, (J, Dl) in enumerate(zip(Js, Deltas), start=1):
+        for i in range(L):
+            j = i + r
+            if j >= L:
+                if not periodic:
+                    continue
+                j -= L
+            bi, bj = _bit(states, i), _bit(states, j)
+            diag += J * Dl * (bi - 0.5) * (bj - 0.5)
+            flip = bi != bj
+            partner = states[flip] ^ ((1 << i) | (1 << j))
+            r_list.append(rows[flip])
+            c_list.append(basis.rank(states, partner))
+            v_list.append(np.full(int(flip.sum()), 0.5 * J))
+    v_list[0] = diag
+    H = sp.coo_matrix((np.concatenate(v_list),
+                       (np.concatenate(r_list), np.concatenate(c_list))),
+                      shape=(D, D)).tocsr()
+    H.sum_duplicates()
+    return H, states
+
+
 def fermion_hop_sign(s: np.ndarray, a: int, b: int) -> np.ndarray:
     """Sign of c^dag_a c_b |s> for states with site b occupied and site a empty,
     Jordan-Wigner ordering by site index: c_b picks up (-1)^(#occupied below b),

@@ -49,6 +49,25 @@ def xxz_full(L, J, Delta, h, periodic=True):
     return H
 
 
+def spin_chain_full(L, Js, Deltas, h, periodic=True):
+    """Couplings of range r = 1..R, full 2^L space, from Kronecker products."""
+    D = 1 << L
+    H = np.zeros((D, D))
+    for r, (J, Dl) in enumerate(zip(Js, Deltas), start=1):
+        for i in range(L):
+            j = i + r
+            if j >= L:
+                if not periodic:
+                    continue
+                j -= L
+            H += J * 0.5 * (site_op(SP, i, L) @ site_op(SM, j, L)
+                            + site_op(SM, i, L) @ site_op(SP, j, L))
+            H += J * Dl * site_op(SZ, i, L) @ site_op(SZ, j, L)
+    for i in range(L):
+        H += h[i] * site_op(SZ, i, L)
+    return H
+
+
 def fermion_c(i, L):
     """Jordan-Wigner annihilator: string of (-1)^n over sites below i."""
     op = np.eye(1)
