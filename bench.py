@@ -188,6 +188,23 @@ def kernel_legs(pk, wl, ctx, L, W, iters):
         out[f"tv_L26_{name}"] = {"GBps": round(4 * w * D26 / (avg * 1e-3) / 1e9, 1),
                                  "us": round(avg * 1e3, 2), "bytes": 4 * w * D26, "D": D26}
     op26.close()
+    # J1-J2 chain L = 22 (App. A eq. j1j2) in CSR: generic values vs the
+    # optimized mapping (value table and one-byte codes)
+    hj = wl.xxz_fields(22, 1.0, 0)
+    opj = pk.Operator.spin_chain(ctx, 22, 11, [1.0, 0.5], [1.0, 1.0], hj, True)
+    Dj, nnzj = opj.D, opj.nnz
+    gen, _ = pk.profile_step(opj, pk.FP64, max(20, iters // 4))
+    nvals = opj.optimize_mapping()
+    opt, _ = pk.profile_step(opj, pk.FP64, max(20, iters // 4))
+    bg = 4 * 8 * Dj + nnzj * 12 + 8 * (Dj + 1) + 8 * Dj
+    bo = 4 * 8 * Dj + nnzj * 5 + 8 * (Dj + 1) + 8 * Dj
+    out["j1j2_L22_fp64_csr"] = {"D": Dj, "nnz": nnzj, "generic_us": round(gen * 1e3, 2),
+                                "generic_GBps": round(bg / (gen * 1e-3) / 1e9, 1),
+                                "optimized_us": round(opt * 1e3, 2),
+                                "optimized_GBps": round(bo / (opt * 1e-3) / 1e9, 1),
+                                "distinct_values": nvals,
+                                "speedup": round(gen / opt, 2)}
+    opj.close()
     # quantum random energy model, full 2^L space: the hypercube step kernel
     for Lq in (20, 24):
         opq = pk.Operator.qrem(ctx, Lq, wl.qrem_energies(Lq, 0), 1.0)

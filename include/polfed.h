@@ -76,9 +76,10 @@ typedef struct polfed_req polfed_req;
 int polfed_version(void);
 const char* polfed_last_error(void);
 
-/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t
- * that the context borrows (NULL: the library creates its own stream, at the
- * default priority).  Fails with POLFED_ERR_NODEVICE when no GPU is visible. */
+/* Creates a context on HIP device `device`.  `hip_stream` is the hipStream_t
+ * the context borrows for all its work; NULL is the device's null stream, so
+ * that library work is ordered with other work queued there (e.g. torch's
+ * default stream).  Fails with POLFED_ERR_NODEVICE when no GPU is visible. */
 polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out);
 polfed_status polfed_destroy(polfed_ctx* ctx);
 /* Waits for all work queued on the context's stream. */
@@ -146,6 +147,23 @@ polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L,
  * Matrix-free only (no CSR copy). */
 polfed_status polfed_op_qrem(polfed_ctx* ctx, int L, const double* E, double Gamma,
                              polfed_op** out);
+/* Spin-1/2 chain with couplings of range r = 1..R (App. A: eq. xxz for
+ * R = 1, eq. j1j2 for R = 2, eq. j1j2j3 for R = 3):
+ * H = sum_r J[r-1] sum_i (S^x_i S^x_{i+r} + S^y_i S^y_{i+r}
+ *     + Delta[r-1] S^z_i S^z_{i+r}) + sum_i h[i] S^z_i,
+ * in the sector of N up spins (site i is bit i, ascending order), built as
+ * a CSR operator (host arrays J[R], Delta[R], h[L] copied).  Periodic bonds
+ * wrap around and need L > 2R.  2 <= L <= 24, 1 <= R <= 8. */
+polfed_status polfed_op_spin_chain(polfed_ctx* ctx, int L, int N, int R, const double* J,
+                                   const double* Delta, const double* h, int periodic,
+                                   polfed_op** out);
+/* Optimized mapping (Sec. 5.6): replaces the off-diagonal values of the
+ * operator's CSR copy by a table of the distinct values and a one-byte code
+ * per entry (no code at all when every value is the same), so the filter
+ * reads 5 (or 4) instead of 12 bytes per entry.  With more than 256 distinct
+ * values the operator is left as it is.  *n_values (may be NULL) gets the
+ * number of distinct values found (257 meaning "more than 256"). */
+polfed_status polfed_op_optimize_mapping(polfed_ctx* ctx, polfed_op* op, int* n_values);
 /* Generic symmetric sparse matrix in CSR (host arrays, copied): rowptr[D+1]
  * (int64), col[nnz] (int32, any order within a row), val[nnz].  Diagonal
  * entries may appear; they are split off internally.  Symmetry is the

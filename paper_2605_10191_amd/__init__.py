@@ -94,6 +94,8 @@ SIGNATURES = {
                        ctypes.POINTER(_P)],
     "polfed_op_csr": [_P, _I64, _I64P, _I32P, _DP, ctypes.POINTER(_P)],
     "polfed_op_qrem": [_P, _I, _DP, _D, ctypes.POINTER(_P)],
+    "polfed_op_spin_chain": [_P, _I, _I, _I, _DP, _DP, _DP, _I, ctypes.POINTER(_P)],
+    "polfed_op_optimize_mapping": [_P, _P, ctypes.POINTER(_I)],
     "polfed_op_materialize_csr": [_P, _P],
     "polfed_op_set_storage": [_P, _I],
     "polfed_op_set_kernel": [_P, _I, _I, ctypes.POINTER(_I)],
@@ -345,6 +347,19 @@ class Operator:
         return cls(ctx, out)
 
     @classmethod
+    def spin_chain(cls, ctx, L, N, Js, Deltas, h, periodic=True):
+        """J1-J2(-J3...) chain: couplings of range 1..len(Js), CSR storage."""
+        Js = np.ascontiguousarray(Js, dtype=np.float64)
+        Ds = np.ascontiguousarray(Deltas, dtype=np.float64)
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        if Js.shape != Ds.shape or h.shape != (L,):
+            raise ValueError("need len(Js) == len(Deltas) and L fields")
+        out = ctypes.c_void_p()
+        _check(_lib.polfed_op_spin_chain(ctx.handle, int(L), int(N), len(Js), _dptr(Js),
+                                         _dptr(Ds), _dptr(h), int(periodic), ctypes.byref(out)))
+        return cls(ctx, out)
+
+    @classmethod
     def csr(cls, ctx, D, rowptr, col, val):
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         col = np.ascontiguousarray(col, dtype=np.int32)
@@ -359,6 +374,13 @@ class Operator:
     def materialize_csr(self):
         _check(_lib.polfed_op_materialize_csr(self.ctx.handle, self.handle))
         return self
+
+    def optimize_mapping(self) -> int:
+        """Value table + one-byte codes for the CSR copy; returns the number
+        of distinct off-diagonal values (257: more than 256, unchanged)."""
+        n = _I()
+        _check(_lib.polfed_op_optimize_mapping(self.ctx.handle, self.handle, ctypes.byref(n)))
+        return n.value
 
     def set_storage(self, storage: int):
         _check(_lib.polfed_op_set_storage(self.handle, storage))

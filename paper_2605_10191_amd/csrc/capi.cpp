@@ -14,6 +14,9 @@ polfed_op* make_qsun(polfed_ctx*, int, int, const double*, double, double, doubl
                      const double*, const int32_t*, const double*);
 polfed_op* make_csr(polfed_ctx*, int64_t, const int64_t*, const int32_t*, const double*);
 polfed_op* make_qrem(polfed_ctx*, int, const double*, double);
+polfed_op* make_spin_chain(polfed_ctx*, int, int, int, const double*, const double*,
+                           const double*, int);
+int optimize_mapping(polfed_ctx*, polfed_op*);
 polfed_status serve_start(polfed_ctx*, size_t, int);
 polfed_status serve_submit(polfed_ctx*, const polfed_op*, const polfed_params*,
                            const double*, double*, double*, double*, polfed_req**);
@@ -146,12 +149,9 @@ polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out) {
     DeviceGuard g(device);
     auto ctx = std::make_unique<polfed_ctx>();
     ctx->device = device;
-    if (hip_stream) {
-      ctx->stream = static_cast<hipStream_t>(hip_stream);
-    } else {
-      HIPC(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-      ctx->own_stream = true;
-    }
+    // NULL is the device's null stream: library work is then ordered with
+    // everything else the caller queues there (torch's default stream)
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
     HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     hipDeviceProp_t prop;
     HIPC(hipGetDeviceProperties(&prop, device));
@@ -307,6 +307,32 @@ polfed_status polfed_op_qrem(polfed_ctx* ctx, int L, const double* E, double Gam
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     *out = make_qrem(ctx, L, E, Gamma);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_spin_chain(polfed_ctx* ctx, int L, int N, int R, const double* J,
+                                   const double* Delta, const double* h, int periodic,
+                                   polfed_op** out) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(out, "null output handle");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = make_spin_chain(ctx, L, N, R, J, Delta, h, periodic);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_op_optimize_mapping(polfed_ctx* ctx, polfed_op* op, int* n_values) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int n = optimize_mapping(ctx, op);
+    if (n_values) *n_values = n;
     return POLFED_OK;
   });
 }

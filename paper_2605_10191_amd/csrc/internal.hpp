@@ -185,6 +185,13 @@ struct CsrDev {
   const float* diag32;
   const int64_t* blk_row;  // [nblk + 1]
   int64_t nblk;
+  // optimized mapping: off-diagonal values from a table of ncode distinct
+  // values, by one byte per entry (code), or the single value vtab[0]
+  // (ncode = 1, no code array); ncode = 0: the val arrays
+  int ncode;
+  const uint8_t* code;
+  const double* vtab;
+  const float* vtab32;
 };
 
 enum class Model { Chain, Qsun, Csr, Qrem };
@@ -252,6 +259,9 @@ struct polfed_op {
   int64_t nnz = -1;
   polfed::DevBuf d_rowptr, d_col, d_val, d_val32, d_diag, d_diag32, d_blk;
   int64_t nblk = 0;
+  // optimized mapping (polfed_op_optimize_mapping): value table and codes
+  int ncode = 0;
+  polfed::DevBuf d_code, d_vtab, d_vtab32;
   polfed::ChainDev chain() const;
   polfed::QsunDev qsun() const;
   polfed::CsrDev csr() const;

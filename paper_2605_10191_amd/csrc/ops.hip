@@ -18,7 +18,9 @@
 // the fields, so neither the basis nor the diagonal is read from HBM.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -34,6 +36,7 @@ struct Tab<double> {
   __host__ __device__ static const double* qsun(const QsunDev& q) { return q.ftab; }
   __host__ __device__ static const double* val(const CsrDev& m) { return m.val; }
   __host__ __device__ static const double* diag(const CsrDev& m) { return m.diag; }
+  __host__ __device__ static const double* vtab(const CsrDev& m) { return m.vtab; }
 };
 template <>
 struct Tab<float> {
@@ -41,7 +44,21 @@ struct Tab<float> {
   __host__ __device__ static const float* qsun(const QsunDev& q) { return q.ftab32; }
   __host__ __device__ static const float* val(const CsrDev& m) { return m.val32; }
   __host__ __device__ static const float* diag(const CsrDev& m) { return m.diag32; }
+  __host__ __device__ static const float* vtab(const CsrDev& m) { return m.vtab32; }
 };
+
+// Off-diagonal value of entry e: from the value array, or (MAPPED) from the
+// table of an optimized mapping, by a one-byte code per entry or, for a
+// single value, without any per-entry data.
+template <typename T, bool MAPPED>
+__device__ __forceinline__ T csr_value(const CsrDev& m, const T* val, const T* vt, int64_t e) {
+  if constexpr (MAPPED) {
+    if (m.ncode == 1) return vt[0];
+    return vt[m.code[e]];
+  } else {
+    return val[e];
+  }
+}
 
 using u32x4 = __attribute__((ext_vector_type(4))) uint32_t;
 
@@ -265,29 +282,49 @@ __device__ __forceinline__ T block_sum(T x, T* red) {
   return tot;
 }
 
-template <typename T>
+template <typename T, bool MAPPED>
 __global__ __launch_bounds__(256) void k_csr_step(
     CsrDev m, T sigma, T tau, T a, const T* __restrict__ v,
     const T* __restrict__ b1, const T* b2, T* out) {
+  // the mapped variant stages one-byte codes instead of values, which
+  // leaves room for more workgroups per CU
+  using Stage = std::conditional_t<MAPPED, uint8_t, T>;
   __shared__ int32_t scol[kCsrStage];
-  __shared__ T sval[kCsrStage];
+  __shared__ Stage sval[kCsrStage];
   __shared__ T red[8];
+  __shared__ T stab[MAPPED ? 256 : 1];  // value table of an optimized mapping
   const int64_t blk = blockIdx.x;
   const int64_t rb = m.blk_row[blk], re = m.blk_row[blk + 1];
   const int64_t z0 = m.rowptr[rb], z1 = m.rowptr[re];
   const T* val = Tab<T>::val(m);
   const T* dia = Tab<T>::diag(m);
+  if constexpr (MAPPED) {
+    const T* vg = Tab<T>::vtab(m);
+    for (int i = threadIdx.x; i < m.ncode; i += blockDim.x) stab[i] = vg[i];
+    __syncthreads();
+  }
+  const T* vt = stab;
   if (z1 - z0 <= kCsrStage) {
     for (int64_t i = threadIdx.x; i < z1 - z0; i += blockDim.x) {
       scol[i] = m.col[z0 + i];
-      sval[i] = val[z0 + i];
+      if constexpr (MAPPED)
+        sval[i] = m.ncode == 1 ? (uint8_t)0 : m.code[z0 + i];
+      else
+        sval[i] = val[z0 + i];
     }
     __syncthreads();
     for (int64_t r = rb + threadIdx.x; r < re; r += blockDim.x) {
       const int64_t e0 = m.rowptr[r] - z0, e1 = m.rowptr[r + 1] - z0;
       const T bo = b1[r];
       T acc = dia[r] * bo;
-      for (int64_t e = e0; e < e1; ++e) acc += sval[e] * b1[scol[e]];
+      for (int64_t e = e0; e < e1; ++e) {
+        T x;
+        if constexpr (MAPPED)
+          x = vt[sval[e]];
+        else
+          x = sval[e];
+        acc += x * b1[scol[e]];
+      }
       T o = sigma * acc + tau * bo;
       if (v) o += a * v[r];
       if (b2) o -= b2[r];
@@ -297,7 +334,7 @@ __global__ __launch_bounds__(256) void k_csr_step(
     // a single long row
     T part = 0;
     for (int64_t e = z0 + threadIdx.x; e < z1; e += blockDim.x)
-      part += val[e] * b1[m.col[e]];
+      part += csr_value<T, MAPPED>(m, val, vt, e) * b1[m.col[e]];
     const T tot = block_sum(part, red);
     if (threadIdx.x == 0) {
       const T bo = b1[rb];
@@ -325,8 +362,12 @@ void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
   if (op->D == 0) return;
   if (op->storage == POLFED_CSR) {
     CsrDev m = op->csr();
-    hipLaunchKernelGGL((k_csr_step<T>), dim3((unsigned)m.nblk), dim3(256), 0, s,
-                       m, sigma, tau, a, v, b1, b2, out);
+    if (m.ncode > 0)
+      hipLaunchKernelGGL((k_csr_step<T, true>), dim3((unsigned)m.nblk), dim3(256), 0, s, m, sigma,
+                         tau, a, v, b1, b2, out);
+    else
+      hipLaunchKernelGGL((k_csr_step<T, false>), dim3((unsigned)m.nblk), dim3(256), 0, s, m,
+                         sigma, tau, a, v, b1, b2, out);
     HIPC(hipGetLastError());
     return;
   }
@@ -808,6 +849,93 @@ polfed_op* make_qsun(polfed_ctx* ctx, int N, int L, const double* A, double gamm
   return op.release();
 }
 
+// The optimized mapping (Sec. 5.6): the off-diagonal values of a CSR copy
+// are replaced by a table of their distinct values and one byte per entry
+// (none when all are equal), cutting the matrix stream from 12 to 5 (or 4)
+// bytes per entry.  More than 256 distinct values leave the operator as it
+// is.  Returns the number of distinct values.
+int optimize_mapping(polfed_ctx* ctx, polfed_op* op) {
+  REQUIRE(op->has_csr, "optimize_mapping: the operator has no CSR copy");
+  hipStream_t s = ctx->stream;
+  const int64_t nnz = op->nnz;
+  std::vector<double> v((size_t)std::max<int64_t>(nnz, 0));
+  if (nnz) HIPC(hipMemcpyAsync(v.data(), op->d_val.get(), nnz * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  std::vector<double> tab;
+  std::vector<uint8_t> code((size_t)std::max<int64_t>(nnz, 0));
+  for (int64_t e = 0; e < nnz; ++e) {
+    int c = 0;
+    while (c < (int)tab.size() && std::memcmp(&tab[c], &v[e], sizeof(double)) != 0) ++c;
+    if (c == (int)tab.size()) {
+      if (tab.size() == 256) return 257;  // too many: unchanged
+      tab.push_back(v[e]);
+    }
+    code[e] = (uint8_t)c;
+  }
+  if (tab.empty()) return 0;
+  std::vector<float> tab32(tab.begin(), tab.end());
+  upload(op->d_vtab, tab.data(), tab.size(), s);
+  upload(op->d_vtab32, tab32.data(), tab32.size(), s);
+  if (tab.size() > 1) upload(op->d_code, code.data(), code.size(), s);
+  HIPC(hipStreamSynchronize(s));
+  op->ncode = (int)tab.size();
+  return op->ncode;
+}
+
+polfed_op* make_csr(polfed_ctx* ctx, int64_t D, const int64_t* rowptr, const int32_t* col,
+                    const double* val);
+
+// Spin-1/2 chain with couplings of range 1..R (eqs. xxz, j1j2, j1j2j3 of
+// App. A) in the sector of N up spins, built on the host as a CSR matrix:
+// a bond (i, i + r) flips the antiparallel pair with amplitude J_r / 2 and
+// adds J_r Delta_r (b_i - 1/2)(b_j - 1/2) to the diagonal.
+polfed_op* make_spin_chain(polfed_ctx* ctx, int L, int N, int R, const double* J,
+                           const double* Delta, const double* h, int periodic) {
+  REQUIRE(L >= 2 && L <= 24 && N >= 0 && N <= L, "spin chain: need 2 <= L <= 24, 0 <= N <= L");
+  REQUIRE(R >= 1 && R <= 8 && J && Delta && h, "spin chain: need 1 <= R <= 8 and parameters");
+  REQUIRE(!periodic || L > 2 * R, "spin chain: periodic bonds need L > 2 R");
+  const int64_t D = binom64(L, N);
+  std::vector<uint32_t> st;
+  st.reserve((size_t)D);
+  for (uint32_t x = 0; x < (1u << L); ++x)
+    if (__builtin_popcount(x) == N) st.push_back(x);
+  std::vector<int64_t> rp((size_t)D + 1, 0);
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  col.reserve((size_t)D * (R * L + 1));
+  val.reserve((size_t)D * (R * L + 1));
+  for (int64_t k = 0; k < D; ++k) {
+    const uint32_t x = st[(size_t)k];
+    double dg = 0;
+    for (int i = 0; i < L; ++i) dg += h[i] * ((double)((x >> i) & 1u) - 0.5);
+    for (int r = 1; r <= R; ++r)
+      for (int i = 0; i < L; ++i) {
+        int j = i + r;
+        if (j >= L) {
+          if (!periodic) continue;
+          j -= L;
+        }
+        const int bi = (x >> i) & 1u, bj = (x >> j) & 1u;
+        dg += J[r - 1] * Delta[r - 1] * ((double)bi - 0.5) * ((double)bj - 0.5);
+        if (bi != bj) {
+          const uint32_t y = x ^ ((1u << i) | (1u << j));
+          const int64_t c = std::lower_bound(st.begin(), st.end(), y) - st.begin();
+          col.push_back((int32_t)c);
+          val.push_back(0.5 * J[r - 1]);
+        }
+      }
+    col.push_back((int32_t)k);
+    val.push_back(dg);
+    rp[(size_t)k + 1] = (int64_t)col.size();
+  }
+  polfed_op* op = make_csr(ctx, D, rp.data(), col.data(), val.data());
+  op->L = L;
+  op->N = N;
+  op->periodic = periodic;
+  return op;
+}
+
 polfed_op* make_csr(polfed_ctx* ctx, int64_t D, const int64_t* rowptr,
                     const int32_t* col, const double* val) {
   REQUIRE(D >= 0 && D < (int64_t(1) << 31), "CSR: need 0 <= D < 2^31");
@@ -896,5 +1024,9 @@ polfed::CsrDev polfed_op::csr() const {
   m.diag32 = d_diag32.as<float>();
   m.blk_row = d_blk.as<int64_t>();
   m.nblk = nblk;
+  m.ncode = ncode;
+  m.code = d_code.as<uint8_t>();
+  m.vtab = d_vtab.as<double>();
+  m.vtab32 = d_vtab32.as<float>();
   return m;
 }

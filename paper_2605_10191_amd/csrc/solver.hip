@@ -39,8 +39,11 @@ double step_bytes(const polfed_op* op, int precision) {
   const double w = precision == POLFED_FP32 ? 4.0 : 8.0;
   double b = 4.0 * w * (double)op->D;
   if (op->model == Model::Qrem) b += w * (double)op->D;  // the energies E_a
-  if (op->storage == POLFED_CSR)
-    b += (double)op->nnz * (w + 4.0) + 8.0 * (double)(op->D + 1) + w * (double)op->D;
+  if (op->storage == POLFED_CSR) {
+    // column index plus the value, its one-byte code, or nothing (one value)
+    const double per = op->ncode == 1 ? 4.0 : (op->ncode > 1 ? 5.0 : w + 4.0);
+    b += (double)op->nnz * per + 8.0 * (double)(op->D + 1) + w * (double)op->D;
+  }
   return b;
 }
 
