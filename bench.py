@@ -87,7 +87,9 @@ def step_kernel_name(op, prec, tname: str, L: int) -> str:
         return f"k_chain_split<{tname}, {L}, 2>"
     if var in (1, 2):
         return f"k_chain_tile<{tname}, {L}, {kt - (var - 1)}>"
-    return f"k_chain_split<{tname}, {L}>"
+    if var == 5:
+        return f"k_chain_tile<{tname}, {L}, {kt - 2}>"
+    return f"k_chain_split<{tname}, {L}, 1>"
 
 
 def xxz_setup(pk, wl, ctx, L, W, seed, n_ev):

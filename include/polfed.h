@@ -181,7 +181,8 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage);
  * -1 = pick by timing on the next step (the default), 0 = segment kernel,
  * 1 = tile kernel with the largest tile, 2 = tile kernel with half that tile,
  * 3 = segment kernel with two adjacent rows per lane (16-byte accesses),
- * 4 = segment kernel with each segment split between two wavefronts;
+ * 4 = segment kernel with each segment split between two wavefronts,
+ * 5 = tile kernel with a quarter of the largest tile;
  * -2 only reports the variant in use.
  * A variant that does not exist for the chain length (tiles need L >= 22)
  * gives POLFED_ERR_INVALID.  For a quantum random energy model the variant is

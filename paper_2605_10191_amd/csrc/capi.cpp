@@ -391,12 +391,13 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
       if (chosen) *chosen = op->tuned[pi];
       return POLFED_OK;
     }
-    REQUIRE(variant >= -1 && variant <= 4, "variant must be -2 .. 4");
+    REQUIRE(variant >= -1 && variant <= 5, "variant must be -2 .. 5");
     if (variant > 0) {
       REQUIRE(op->model == Model::Chain && op->split_nseg > 0,
               "step-kernel variants exist only for matrix-free chains");
-      if (variant <= 2)
-        REQUIRE(op->tiles[variant - 1].n > 0, "no tile kernel of this size for this chain length");
+      if (variant <= 2 || variant == 5)
+        REQUIRE(op->tiles[variant == 5 ? 2 : variant - 1].n > 0,
+                "no tile kernel of this size for this chain length");
     }
     op->tuned[pi] = variant;
     if (chosen) *chosen = op->tuned[pi];

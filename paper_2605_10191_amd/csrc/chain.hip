@@ -158,7 +158,7 @@ void build_chain_split(polfed_op* op) {
     seg_of_hi[nhi] = sidx;
   }
   const int KT = chain_tile_bits(L);
-  for (int v = 0; v < 2; ++v) {
+  for (int v = 0; v < 3; ++v) {
     auto& T = op->tiles[v];
     T = polfed_op::Tiles{};
     const int kt = KT - v;
@@ -706,7 +706,8 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
   }
   if constexpr (KT >= 2) {
     constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
-    const auto& tl = op->tiles[var - 1];
+    if (var != 1 && var != 2 && var != 5) return false;
+    const auto& tl = op->tiles[var == 5 ? 2 : var - 1];
     if (tl.n <= 0) return false;
     if (chain_blob_bytes(1 << Lb, (int)sizeof(T)) + (size_t)tl.max_rows * sizeof(T) > kLdsPerCU)
       return false;
@@ -717,6 +718,12 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
     if constexpr (KT - 1 >= 2) {
       if (var == 2 && tl.bits == KT - 1) {
         launch_tile<T, L, KT - 1>(s, op, tl, sigma, tau, a, v, b1, b2, out);
+        return true;
+      }
+    }
+    if constexpr (KT - 2 >= 2) {
+      if (var == 5 && tl.bits == KT - 2) {
+        launch_tile<T, L, KT - 2>(s, op, tl, sigma, tau, a, v, b1, b2, out);
         return true;
       }
     }
@@ -732,7 +739,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   if (op->tuned[pi] >= 0) return op->tuned[pi];
   static const int allow_tile = env_int("POLFED_CHAIN_TILE", -1);
   if (allow_tile == 0) return op->tuned[pi] = 0;
-  if (allow_tile >= 1 && allow_tile <= 4) return op->tuned[pi] = allow_tile;
+  if (allow_tile >= 1 && allow_tile <= 5) return op->tuned[pi] = allow_tile;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return 0;
@@ -746,7 +753,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   HIPC(hipEventCreate(&e1));
   int best = 0;
   float best_ms = 1e30f;
-  for (int var = 0; var < 5; ++var) {
+  for (int var = 0; var < 6; ++var) {
     auto go = [&] {
       return launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(),
                                   bb2.as<T>(), bb2.as<T>());

@@ -243,11 +243,11 @@ struct polfed_op {
   int split_Lb = 0;
   int64_t split_nseg = 0;
   polfed::DevBuf d_blob64, d_blob32, d_rec;
-  // tile-kernel tables for two tile sizes (bits KT and KT - 1)
+  // tile-kernel tables for three tile sizes (bits KT, KT - 1, KT - 2)
   struct Tiles {
     int bits = 0, max_rows = 0, n = 0;
     polfed::DevBuf d;  // [n][4]: first row, rows, first segment, segments
-  } tiles[2];
+  } tiles[3];
   // step-kernel variant picked by timing on first use, per precision
   // (-1: not tuned yet, 0: segment kernel, 1 + i: tile kernel tiles[i])
   mutable int tuned[2] = {-1, -1};
