@@ -315,9 +315,10 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
  * for the current block V_j = columns k..k+s-1 of V (one multi-column
  * Clenshaw recurrence for chain operators, s single ones otherwise), full
  * reorthogonalization of W against columns 0..k+s-1 and its QR, which gives
- * the next block (columns k+s..k+2s-1, written) and B_{j+1}.  Column c of W
- * is orthogonalized by classical Gram-Schmidt applied twice against columns
- * 0..k+s+c-1 and normalized (a Gram-Schmidt QR, positive diagonal).
+ * the next block (columns k+s..k+2s-1, written) and B_{j+1}.  W gets two
+ * passes of block Gram-Schmidt against columns 0..k+s-1 (tall-skinny
+ * products); then column c gets two passes against the new block's columns
+ * 0..c-1 and is normalized (a Gram-Schmidt QR, positive diagonal).
  * V: device basis, column-major D x (k+2s), columns 0..k+s-1 orthonormal,
  * k a multiple of s, 1 <= s <= 64 and k + 2s <= D.
  * A: device s x s column-major, A_j = V_j^T P(H~) V_j (as computed; not

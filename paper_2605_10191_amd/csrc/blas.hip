@@ -125,6 +125,106 @@ void dev_gemv_t(hipStream_t s, int64_t D, int k, const double* V, int64_t ld,
   HIPC(hipGetLastError());
 }
 
+// ---- tall-skinny block products: C = V^T W and W -= V C for W of S <= 8
+// columns (block Gram-Schmidt); V is read once per product ----
+template <int S>
+__global__ __launch_bounds__(kTB) void k_gemm_tn_tall(int64_t D, int k, const double* V,
+                                                      const double* W, int64_t seg_len,
+                                                      int64_t nseg, double* part) {
+  __shared__ double red[kCols * S][kTB / 64];
+  const int j0 = blockIdx.x * kCols;
+  const int64_t seg = blockIdx.y;
+  const int64_t r0 = seg * seg_len, r1 = std::min<int64_t>(D, r0 + seg_len);
+  double acc[kCols][S];
+#pragma unroll
+  for (int q = 0; q < kCols; ++q)
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc[q][j] = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    double w[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) w[j] = W[r + (int64_t)j * D];
+#pragma unroll
+    for (int q = 0; q < kCols; ++q)
+      if (j0 + q < k) {
+        const double x = V[r + (int64_t)(j0 + q) * D];
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[q][j] += x * w[j];
+      }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kCols; ++q)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const double t = wave_sum(acc[q][j]);
+      if (lane == 0) red[q * S + j][wid] = t;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCols * S; i += blockDim.x) {
+    const int q = i / S, j = i % S;
+    if (j0 + q < k) {
+      double t = 0;
+      for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) t += red[i][w2];
+      // column-major k x S result: entry (j0 + q, j)
+      part[((int64_t)j * k + j0 + q) * nseg + seg] = t;
+    }
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(kTB) void k_gemm_nn_sub_tall(int64_t D, int k, const double* V,
+                                                          const double* C, double* W) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  double acc[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) acc[j] = 0;
+  for (int i = 0; i < k; ++i) {
+    const double x = V[r + (int64_t)i * D];
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc[j] += x * C[i + (int64_t)j * k];
+  }
+#pragma unroll
+  for (int j = 0; j < S; ++j) W[r + (int64_t)j * D] -= acc[j];
+}
+
+template <int S>
+static void tall_pass(hipStream_t s, int64_t D, int k, const double* V, double* W,
+                      double* partial, int64_t nseg, double* C) {
+  const int64_t len = seg_len_for(D, nseg);
+  const int64_t ns = std::max<int64_t>(1, (D + len - 1) / len);
+  dim3 grid((unsigned)((k + kCols - 1) / kCols), (unsigned)ns);
+  hipLaunchKernelGGL(k_gemm_tn_tall<S>, grid, dim3(kTB), 0, s, D, k, V, W, len, ns, partial);
+  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((k * S + 63) / 64)), dim3(64), 0, s, partial,
+                     ns, k * S, C, nullptr, 0);
+  hipLaunchKernelGGL(k_gemm_nn_sub_tall<S>, dim3((unsigned)((D + kTB - 1) / kTB)), dim3(kTB), 0,
+                     s, D, k, V, C, W);
+  HIPC(hipGetLastError());
+}
+
+// One Gram-Schmidt pass of the D x n block W against the first k columns of
+// V: C = V^T W (k x n col-major, ld k), W -= V C, in chunks of 8 columns.
+// partial: nseg * k * 8 doubles.
+void dev_block_gs_pass(hipStream_t s, int64_t D, int k, const double* V, double* W, int n,
+                       double* partial, int64_t nseg, double* C) {
+  if (k <= 0 || D == 0) return;
+  for (int j0 = 0; j0 < n; j0 += 8) {
+    const int m = std::min(8, n - j0);
+    double* Wc = W + (int64_t)j0 * D;
+    double* Cc = C + (int64_t)j0 * k;
+    switch (m) {
+#define POLFED_CASE(S) \
+  case S:              \
+    tall_pass<S>(s, D, k, V, Wc, partial, nseg, Cc); \
+    break;
+      POLFED_CASE(1) POLFED_CASE(2) POLFED_CASE(3) POLFED_CASE(4)
+      POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
+#undef POLFED_CASE
+    }
+  }
+}
+
 // ---- w -= V c ----
 __global__ __launch_bounds__(kTB) void k_gemv_n_sub(int64_t D, int k, const double* V,
                                                     int64_t ld, const double* c,

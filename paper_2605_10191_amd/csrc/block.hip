@@ -10,6 +10,9 @@
 // two passes of classical Gram-Schmidt against all earlier basis vectors,
 // the new block's earlier columns included, then normalization, which is the
 // Gram-Schmidt QR of the orthogonalized block (positive diagonal of B_{j+1}).
+// The passes against the existing basis are tall-skinny block products
+// (C = V^T W, W -= V C, twice), so each block step reads the basis four times
+// (per 8 columns) instead of four times per column.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -75,27 +78,27 @@ template void block_filter_on<float>(hipStream_t, const polfed_op*, BlockWs&,
 
 // ------------------------------------------------- block orthogonalization ----
 
-// Adds pass `pass` of the Gram-Schmidt coefficients c[0..k+s+col) of column
-// col into column col of A (the coefficients on basis columns k..k+s-1, the
-// current block) and of Bn (those on the new block's earlier columns); the
-// first pass also zeroes Bn's entries below the diagonal in that column.
-__global__ void k_block_coef(const double* __restrict__ c, int k, int s, int col, int pass,
-                             double* __restrict__ A, double* __restrict__ Bn) {
-  for (int i = threadIdx.x; i < 2 * s; i += blockDim.x) {
-    if (i < s) {
-      const double v = c[k + i];
-      double* d = A + i + (size_t)col * s;
-      *d = pass ? *d + v : v;
-    } else {
-      const int r = i - s;
-      double* d = Bn + r + (size_t)col * s;
-      if (r < col) {
-        const double v = c[k + s + r];
-        *d = pass ? *d + v : v;
-      } else if (r > col && pass == 0) {
-        *d = 0.0;
-      }
-    }
+// A (s x s) = (pass 0) or += (pass 1) rows row0..row0+s-1 of the ldc x s
+// coefficient block C.
+__global__ void k_take_rows(const double* __restrict__ C, int ldc, int row0, int s, int pass,
+                            double* __restrict__ A) {
+  for (int i = threadIdx.x; i < s * s; i += blockDim.x) {
+    const int r = i % s, col = i / s;
+    const double v = C[row0 + r + (size_t)col * ldc];
+    A[i] = pass ? A[i] + v : v;
+  }
+}
+
+// Column col of Bn: rows 0..col-1 = (pass 0) or += (pass 1) c[0..col); the
+// first pass also zeroes the rows below the diagonal.
+__global__ void k_r_col(const double* __restrict__ c, int s, int col, int pass,
+                        double* __restrict__ Bn) {
+  for (int r = threadIdx.x; r < s; r += blockDim.x) {
+    double* d = Bn + r + (size_t)col * s;
+    if (r < col)
+      *d = pass ? *d + c[r] : c[r];
+    else if (r > col && pass == 0)
+      *d = 0.0;
   }
 }
 
@@ -115,23 +118,33 @@ void cgs2_plain(hipStream_t st, int64_t D, int k1, const double* V, double* w, d
 
 int block_orth(hipStream_t st, int64_t D, int k, int s, double* V, double* W, double* save,
                double* c, double* partial, int64_t nseg, int* flag, double* scal, double* A,
-               double* Bn, uint64_t& seed) {
+               double* Bn, double* Cb, uint64_t& seed) {
+  const int kb = k + s;  // basis columns before the new block
+  // block Gram-Schmidt against all kb columns, two passes, as tall-skinny
+  // products: C = V^T W, W -= V C; the rows of the current block sum to A
+  for (int pass = 0; pass < 2; ++pass) {
+    dev_block_gs_pass(st, D, kb, V, W, s, partial, nseg, Cb);
+    hipLaunchKernelGGL(k_take_rows, dim3(1), dim3(256), 0, st, Cb, kb, k, s, pass, A);
+    HIPC(hipGetLastError());
+  }
   HIPC(hipMemcpyAsync(save, W, (size_t)D * s * sizeof(double), hipMemcpyDeviceToDevice, st));
+  const double* Vn = V + (size_t)kb * D;  // the new block
   int c0 = 0, replaced = 0;
   std::vector<double> Bh((size_t)s * s);
   for (;;) {
+    // inside the block: column col against the new columns 0..col-1 (two
+    // passes), then normalized into column kb + col
     for (int col = c0; col < s; ++col) {
       double* w = W + (size_t)col * D;
-      const int k1 = k + s + col;
       for (int pass = 0; pass < 2; ++pass) {
-        dev_gemv_t(st, D, k1, V, D, w, partial, nseg, c, nullptr, 0);
-        hipLaunchKernelGGL(k_block_coef, dim3(1), dim3(128), 0, st, c, k, s, col, pass, A, Bn);
+        if (col > 0) dev_gemv_t(st, D, col, Vn, D, w, partial, nseg, c, nullptr, 0);
+        hipLaunchKernelGGL(k_r_col, dim3(1), dim3(64), 0, st, c, s, col, pass, Bn);
         HIPC(hipGetLastError());
-        dev_gemv_n_sub(st, D, k1, V, D, c, w);
+        if (col > 0) dev_gemv_n_sub(st, D, col, Vn, D, c, w);
       }
       double* rcc = Bn + col + (size_t)col * s;
       dev_dot(st, D, w, w, partial, 1024, rcc, 1);
-      dev_scale_into(st, D, w, rcc, V + (size_t)k1 * D, flag);
+      dev_scale_into(st, D, w, rcc, V + (size_t)(kb + col) * D, flag);
     }
     HIPC(hipMemcpyAsync(Bh.data(), Bn, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
@@ -150,7 +163,7 @@ int block_orth(hipStream_t st, int64_t D, int k, int s, double* V, double* W, do
     // The block lost rank at column `bad`: its direction is a random unit
     // vector orthogonal to the basis, with a zero entry on the diagonal of
     // Bn (W's column lies in the span of the earlier ones).
-    const int k1 = k + s + bad;
+    const int k1 = kb + bad;
     double* w = W + (size_t)bad * D;
     dev_random(st, D, seed++, w);
     cgs2_plain(st, D, k1, V, w, c, partial, nseg);
@@ -160,7 +173,7 @@ int block_orth(hipStream_t st, int64_t D, int k, int s, double* V, double* W, do
     HIPC(hipMemcpyAsync(Bn + bad + (size_t)bad * s, &zero, sizeof(double), hipMemcpyHostToDevice,
                         st));
     HIPC(hipMemsetAsync(flag, 0, sizeof(int), st));
-    // the later columns start again from their filtered values
+    // the later columns start again from their state after the block passes
     c0 = bad + 1;
     if (c0 < s)
       HIPC(hipMemcpyAsync(W + (size_t)c0 * D, save + (size_t)c0 * D,
@@ -275,10 +288,16 @@ void SolveRun::advance_block() {
   HIPC(hipEventCreate(&r0));
   HIPC(hipEventCreate(&r1));
   HIPC(hipEventRecord(r0, st));
+  const size_t cb_need = (size_t)(k + s) * s * sizeof(double);
+  if (bw.cb.bytes() < cb_need) bw.cb.alloc(std::max(cb_need, (size_t)(cap + 2 * s) * s * sizeof(double)));
+  // partials: 8 columns of coefficients per row segment and basis vector
+  const size_t part_need = ((size_t)ws.nseg * (k + 2 * s + 1) * 8 + 8192) * sizeof(double);
+  if (bw.part.bytes() < part_need)
+    bw.part.alloc(std::max(part_need, ((size_t)ws.nseg * (cap + 2 * s + 1) * 8 + 8192) * sizeof(double)));
   R.restarts += block_orth(st, D, k, s, B.V.as<double>(), bw.w.as<double>(),
-                           bw.save.as<double>(), ws.c.as<double>(), ws.partial.as<double>(),
+                           bw.save.as<double>(), ws.c.as<double>(), bw.part.as<double>(),
                            ws.nseg, ws.flag.as<int>(), ws.scal.as<double>(), Aj, Aj + ss,
-                           restart_seed);
+                           bw.cb.as<double>(), restart_seed);
   HIPC(hipEventRecord(r1, st));
   rev.emplace_back(r0, r1);
   k += s;
@@ -416,12 +435,14 @@ void block_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double
   }
   const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(256, (D + 8191) / 8192));
   DevBuf c((size_t)(k + 2 * s + 1) * sizeof(double)),
-      part(((size_t)nseg * (k + 2 * s + 1) + 8192) * sizeof(double)), flag(64),
+      part(((size_t)nseg * (k + 2 * s + 1) * 8 + 8192) * sizeof(double)), flag(64),
       scal(8 * sizeof(double));
   HIPC(hipMemsetAsync(flag.get(), 0, 64, st));
   uint64_t seed = 0xB10CULL + (uint64_t)k;
+  DevBuf cb((size_t)(k + s) * s * sizeof(double));
   block_orth(st, D, k, s, V, bw.w.as<double>(), bw.save.as<double>(), c.as<double>(),
-             part.as<double>(), nseg, flag.as<int>(), scal.as<double>(), A, Bn, seed);
+             part.as<double>(), nseg, flag.as<int>(), scal.as<double>(), A, Bn, cb.as<double>(),
+             seed);
   HIPC(hipStreamSynchronize(st));
 }
 

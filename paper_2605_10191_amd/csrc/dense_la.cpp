@@ -66,6 +66,20 @@ void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A, const double*
       "rocblas_dgemm");
 }
 
+void dev_dgemm(hipStream_t s, bool ta, bool tb, int m, int n, int64_t k, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+               double* C, int64_t ldc) {
+  if (m <= 0 || n <= 0) return;
+  REQUIRE(k < (int64_t(1) << 31) && lda < (int64_t(1) << 31) && ldb < (int64_t(1) << 31) &&
+              ldc < (int64_t(1) << 31),
+          "gemm: dimension too large");
+  rbc(rocblas_dgemm(handle_for(s), ta ? rocblas_operation_transpose : rocblas_operation_none,
+                    tb ? rocblas_operation_transpose : rocblas_operation_none, m, n,
+                    (rocblas_int)k, &alpha, A, (rocblas_int)lda, B, (rocblas_int)ldb, &beta, C,
+                    (rocblas_int)ldc),
+      "rocblas_dgemm");
+}
+
 void dev_syevd(hipStream_t s, int n, double* A, double* w) {
   if (n <= 0) return;
   DevBuf e((size_t)n * sizeof(double)), info(sizeof(rocblas_int));

@@ -340,6 +340,11 @@ void dev_copy_f2d(hipStream_t s, int64_t n, const float* x, double* y);
 void dev_fill(hipStream_t s, int64_t n, double v, double* y);
 void dev_fillf(hipStream_t s, int64_t n, float v, float* y);
 void dev_random(hipStream_t s, int64_t n, uint64_t seed, double* y);
+// One block Gram-Schmidt pass: C = V^T W (k x n, ld k), W -= V C, for the
+// D x n block W against the first k columns of V (ld D); hand-written
+// tall-skinny kernels (V read once per product).  partial: nseg * k * 8.
+void dev_block_gs_pass(hipStream_t s, int64_t D, int k, const double* V, double* W, int n,
+                       double* partial, int64_t nseg, double* C);
 // Dense products through rocBLAS (dense_la.cpp):
 // C (D x n) = A (D x m, ld lda) * B (m x n, device, col-major, ld m)
 void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A,
@@ -347,6 +352,11 @@ void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A,
 // G (n x n) = A^T B for A, B of D x n (ld D); G on device, col-major.
 void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A,
                  const double* B, double* partial, int64_t nseg, double* G);
+// C (m x n) = alpha op(A) op(B) + beta C, op = transpose when ta / tb;
+// k is the inner dimension; column-major, device pointers.
+void dev_dgemm(hipStream_t s, bool ta, bool tb, int m, int n, int64_t k, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+               double* C, int64_t ldc);
 // Device eigensolvers through rocSOLVER: symmetric A (n x n col-major, lower
 // triangle read) -> eigenvalues w ascending, eigenvectors over A; symmetric
 // tridiagonal (d[n], e[n-1], both overwritten) -> eigenvalues ascending in d,

@@ -97,6 +97,8 @@ struct BlockWs {
   int64_t D = 0;
   bool fp32 = false, batched = false;
   DevBuf w, save, vin;     // D x s FP64
+  DevBuf cb;               // (k + s) x s block Gram-Schmidt coefficients
+  DevBuf part;             // reduction partials of the block products
   DevBuf v32, w32;         // D x s FP32 (FP32 filter)
   DevBuf bA, bB;           // D x s of the filter precision
   ChainBatch bt;
@@ -112,15 +114,17 @@ void block_filter_on(hipStream_t st, const polfed_op* op, BlockWs& bw, const pol
 
 // Orthogonalizes the filtered block W (D x s, overwritten) against basis
 // columns [0, k + s) of V and writes the next block into columns
-// [k + s, k + 2s): column c gets two passes of classical Gram-Schmidt
-// against [0, k + s + c) and is normalized.  The summed projections onto the
-// current block give A (s x s, col-major); those onto the new columns and
-// the norms give the upper triangular Bn.  save: D x s scratch; c, partial:
-// coefficient scratch for k + 2s columns; scal: 8 device doubles.  Returns
-// the number of rank-deficient columns replaced by random directions.
+// [k + s, k + 2s): two passes of block Gram-Schmidt against [0, k + s)
+// (tall-skinny products through Cb, (k + s) x s), then, column by column,
+// two passes against the new block's earlier columns and normalization.
+// The summed projections onto the current block give A (s x s, col-major);
+// those onto the new columns and the norms give the upper triangular Bn.
+// save: D x s scratch; c, partial: coefficient scratch for k + 2s columns;
+// scal: 8 device doubles.  Returns the number of rank-deficient columns
+// replaced by random directions.
 int block_orth(hipStream_t st, int64_t D, int k, int s, double* V, double* W, double* save,
                double* c, double* partial, int64_t nseg, int* flag, double* scal, double* A,
-               double* Bn, uint64_t& seed);
+               double* Bn, double* Cb, uint64_t& seed);
 
 // Orthonormal start block: Gram-Schmidt QR (two passes per column) of the
 // D x s block X0 into columns [0, s) of V; fails on a rank-deficient X0.
