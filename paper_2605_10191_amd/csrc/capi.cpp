@@ -95,6 +95,10 @@ template <class F>
 polfed_status guarded(F&& f) {
   try {
     g_err.clear();
+    // hipGetLastError is per-thread state that any earlier HIP call of the
+    // caller (another library, the framework) may have left set; the launch
+    // checks inside this call must only see errors of this call
+    (void)hipGetLastError();
     return f();
   } catch (const Error& e) {
     g_err = e.what();

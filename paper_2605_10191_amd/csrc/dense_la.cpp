@@ -18,6 +18,9 @@ namespace polfed {
 namespace {
 
 void rbc(rocblas_status st, const char* what) {
+  // the libraries report through their status; HIP's per-thread last-error
+  // state they may leave behind is not an error of this library's launches
+  (void)hipGetLastError();
   if (st != rocblas_status_success)
     fail(POLFED_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(st));
 }
