@@ -56,12 +56,51 @@ void BlockWs::init(polfed_ctx* ctx, const polfed_op* op, int s_, bool fp32_,
 }
 
 template <typename T>
+__global__ void k_scale_block(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+// The Clenshaw recurrence of eq. clenshaw_chebyshev_prod for the n columns
+// of a QREM block at once, on the multi-column step (same sequence of
+// operations as the single-column filter, column by column).
+template <typename T>
+static void qrem_filter_block(hipStream_t st, const polfed_op* op, const polfed_plan& pl,
+                              const double* a, int n, const T* X, T* Wout, T* bA, T* bB) {
+  const int64_t D = op->D, tot = D * n;
+  const int K = pl.K;
+  const T sigma = (T)(2.0 / pl.dE), tau = (T)(-2.0 * pl.E_c / pl.dE);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (tot + 255) / 256));
+  if (K == 0) {
+    hipLaunchKernelGGL((k_scale_block<T>), dim3(g), dim3(256), 0, st, tot, (T)a[0], X, Wout);
+    HIPC(hipGetLastError());
+    return;
+  }
+  hipLaunchKernelGGL((k_scale_block<T>), dim3(g), dim3(256), 0, st, tot, (T)a[K], X, bA);
+  HIPC(hipGetLastError());
+  const T* cur = bA;
+  T* prev = nullptr;
+  for (int i = K - 1; i >= 1; --i) {
+    T* o = prev ? prev : bB;
+    qrem_step_multi<T>(st, op, n, sigma, tau, (T)a[i], X, cur, prev, o);
+    prev = const_cast<T*>(cur);
+    cur = o;
+  }
+  qrem_step_multi<T>(st, op, n, (T)(0.5 * sigma), (T)(0.5 * tau), (T)a[0], X, cur, prev, Wout);
+}
+
+template <typename T>
 void block_filter_on(hipStream_t st, const polfed_op* op, BlockWs& bw, const polfed_plan& pl,
                      const double* a, const T* X, T* W) {
   T* bA = (T*)bw.bA.get();
   T* bB = (T*)bw.bB.get();
   if (bw.batched) {
     filter_apply_batch_on<T>(st, bw.bt, bw.co, X, W, bA, bB);
+    return;
+  }
+  if (op->model == Model::Qrem && op->L >= 10) {
+    qrem_filter_block<T>(st, op, pl, a, bw.s, X, W, bA, bB);
     return;
   }
   const int64_t D = bw.D;

@@ -320,6 +320,11 @@ template <typename T>
 void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v, const T* b1,
                const T* b2, T* out);
 int qrem_tile_bits(int L);
+// The step for n columns of one QREM operator (blocks of column stride D);
+// every column equals the single-column step's result.  L >= 10.
+template <typename T>
+void qrem_step_multi(hipStream_t s, const polfed_op* op, int n, T sigma, T tau, T a, const T* v,
+                     const T* b1, const T* b2, T* out);
 void materialize_csr(polfed_ctx* ctx, polfed_op* op);
 
 // ---------------------------------------------------------------- blas ----

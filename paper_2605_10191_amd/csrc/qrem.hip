@@ -89,6 +89,81 @@ __global__ __launch_bounds__(kQremThreads) void k_qrem_step(
   }
 }
 
+// The same step for NC columns of one operator (block Lanczos): column c of
+// the D x NC blocks (column stride D) gets out_c = a v_c + sigma H b1_c +
+// tau b1_c - b2_c.  The tile, index arithmetic and the energies are shared;
+// each column keeps its own gathers.  Per column the sums run in the same
+// order as in k_qrem_step, so each column equals the single-column result.
+template <typename T, int TB, int NC>
+__global__ __launch_bounds__(kQremThreads) void k_qrem_step_multi(
+    int L, int64_t ntiles, int nxcd, T gamma, T sigma, T tau, T a, const T* __restrict__ E,
+    const T* __restrict__ v, const T* __restrict__ b1, const T* b2, T* out, int64_t D) {
+  constexpr int NP = 1 << (TB - 1);
+  constexpr int PPT = NP > kQremThreads ? NP / kQremThreads : 1;
+  constexpr uint32_t W = sizeof(T);
+  __shared__ __attribute__((aligned(16))) T tile[NC][2 * NP];
+  const uint32_t vbytes = (uint32_t)(D * W);
+  const rsrc_t rE = make_rsrc(E, vbytes);
+  const int xcd = blockIdx.x % nxcd;
+  const int64_t per_xcd = gridDim.x / nxcd;
+  const int64_t t_end = ntiles * (xcd + 1) / nxcd;
+  for (int64_t t = ntiles * xcd / nxcd + blockIdx.x / nxcd; t < t_end; t += per_xcd) {
+    const uint32_t toff = (uint32_t)uniform((int)(t << TB)) * W;
+    T x[NC][PPT][2];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const rsrc_t rb1 = make_rsrc(b1 + (size_t)c * D, vbytes);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int q = threadIdx.x + j * kQremThreads;
+        if (q < NP) {
+          bload2<T>(rb1, (uint32_t)(2 * q) * W, toff, x[c][j][0], x[c][j][1]);
+          tile[c][2 * q] = x[c][j][0];
+          tile[c][2 * q + 1] = x[c][j][1];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int q = threadIdx.x + j * kQremThreads;
+      if (q < NP) {
+        const uint32_t vo = (uint32_t)(2 * q) * W;
+        T e0, e1;
+        bload2<T, kAuxNT>(rE, vo, toff, e0, e1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const rsrc_t rb1 = make_rsrc(b1 + (size_t)c * D, vbytes);
+          T s0 = x[c][j][1], s1 = x[c][j][0];
+#pragma unroll
+          for (int i = 1; i < TB; ++i) {
+            const int p = q ^ (1 << (i - 1));
+            s0 += tile[c][2 * p];
+            s1 += tile[c][2 * p + 1];
+          }
+#pragma unroll 4
+          for (int i = TB; i < L; ++i) {
+            const uint32_t po =
+                (uint32_t)uniform((int)((t ^ ((int64_t)1 << (i - TB))) << TB)) * W;
+            T g0, g1;
+            bload2<T>(rb1, vo, po, g0, g1);
+            s0 += g0;
+            s1 += g1;
+          }
+          T v0 = T(0), v1 = T(0), c0 = T(0), c1 = T(0);
+          if (v) bload2<T, kAuxNT>(make_rsrc(v + (size_t)c * D, vbytes), vo, toff, v0, v1);
+          if (b2) bload2<T, kAuxNT>(make_rsrc(b2 + (size_t)c * D, vbytes), vo, toff, c0, c1);
+          const T h0 = e0 * x[c][j][0] - gamma * s0, h1 = e1 * x[c][j][1] - gamma * s1;
+          const T o0 = a * v0 + sigma * h0 + tau * x[c][j][0] - c0;
+          const T o1 = a * v1 + sigma * h1 + tau * x[c][j][1] - c1;
+          bstore2<kAuxNT>(o0, o1, make_rsrc(out + (size_t)c * D, vbytes), vo, toff);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int TB>
 static void launch_qrem(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v,
                         const T* b1, const T* b2, T* out) {
@@ -180,6 +255,51 @@ void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T*
                const T* b2, T* out) {
   launch_tb<T>(s, op, tuned_tile_bits<T>(s, op), sigma, tau, a, v, b1, b2, out);
 }
+
+template <typename T, int NC>
+static void launch_multi(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v,
+                         const T* b1, const T* b2, T* out) {
+  constexpr int TB = 10;  // 8 KB of FP64 rows per column and tile
+  const int64_t ntiles = op->D >> TB;
+  const int per_cu = std::max(1, (int)(2048 / kQremThreads));
+  int64_t grid = std::min<int64_t>(ntiles, (int64_t)op->ctx->n_cu * per_cu);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  const bool f64 = sizeof(T) == 8;
+  const T* E = (const T*)(f64 ? op->d_diag.get() : op->d_diag32.get());
+  hipLaunchKernelGGL((k_qrem_step_multi<T, TB, NC>), dim3((unsigned)std::max<int64_t>(grid, 1)),
+                     dim3(kQremThreads), 0, s, op->L, ntiles, nxcd, (T)op->qrem_gamma, sigma, tau,
+                     a, E, v, b1, b2, out, op->D);
+  HIPC(hipGetLastError());
+}
+
+template <typename T>
+void qrem_step_multi(hipStream_t s, const polfed_op* op, int n, T sigma, T tau, T a, const T* v,
+                     const T* b1, const T* b2, T* out) {
+  REQUIRE(op->L >= 10, "qrem: the multi-column step needs L >= 10");
+  const int64_t D = op->D;
+  for (int c0 = 0; c0 < n;) {
+    const int m = n - c0 >= 4 ? 4 : (n - c0 >= 2 ? 2 : 1);
+    const size_t o = (size_t)c0 * D;
+    const T* vc = v ? v + o : nullptr;
+    const T* b2c = b2 ? b2 + o : nullptr;
+    if (m == 4)
+      launch_multi<T, 4>(s, op, sigma, tau, a, vc, b1 + o, b2c, out + o);
+    else if (m == 2)
+      launch_multi<T, 2>(s, op, sigma, tau, a, vc, b1 + o, b2c, out + o);
+    else
+      launch_multi<T, 1>(s, op, sigma, tau, a, vc, b1 + o, b2c, out + o);
+    c0 += m;
+  }
+}
+
+template void qrem_step_multi<double>(hipStream_t, const polfed_op*, int, double, double, double,
+                                      const double*, const double*, const double*, double*);
+template void qrem_step_multi<float>(hipStream_t, const polfed_op*, int, float, float, float,
+                                     const float*, const float*, const float*, float*);
 
 template void qrem_step<double>(hipStream_t, const polfed_op*, double, double, double,
                                 const double*, const double*, const double*, double*);

@@ -171,3 +171,38 @@ def test_qrem_many_pairs_device_eigensolvers(pk, ctx, s):
     assert rel.max() <= 1e-10 and R.max() <= 1e-8
     assert np.linalg.norm(H @ U - U * Ev, axis=0).max() <= 1e-8
     assert np.min(np.abs(np.sum(U * Ur, axis=0))) >= 1 - 1e-8
+
+
+@pytest.mark.parametrize("L,s,k,prec", [(12, 4, 0, "fp64"), (13, 3, 6, "fp64"), (14, 2, 4, "fp32"),
+                                        (11, 5, 5, "fp64")])
+def test_qrem_block_step_matches_oracle(pk, ctx, L, s, k, prec):
+    """Block Lanczos step on QREM: the filter of the whole block runs on the
+    multi-column hypercube step (chunks of 4, 2, 1 columns)."""
+    say(f"qrem block step L={L} s={s} k={k} {prec}")
+    op, E = qrem_case(pk, ctx, L, 11)
+    H = models.qrem(L, E, 1.0)
+    D = op.D
+    lo, hi = lanczos.spectral_extremes(H)
+    E_c, dE = flt.rescale(*lanczos.padded_bounds(lo, hi, 1e-3))
+    K = 120 if prec == "fp64" else 60
+    a = flt.coefficients(0.03, K)
+
+    def P(X):
+        return flt.apply_filter(H, E_c, dE, a, X)
+    X0 = np.stack([wl.start_vector(D, 70 + c) for c in range(s)], 1)
+    V = np.zeros((D, k + 2 * s))
+    V[:, :s] = lanczos.orthonormal_start_block(X0)
+    for j in range(k // s):
+        _, _, Vn = lanczos.block_lanczos_step(P, V, j * s, s)
+        V[:, (j + 1) * s:(j + 2) * s] = Vn
+    A_ref, B_ref, Vn_ref = lanczos.block_lanczos_step(P, V, k, s)
+    tV = dev(V.T)
+    tA = torch.zeros((s, s), dtype=torch.float64, device="cuda:0")
+    tB = torch.zeros((s, s), dtype=torch.float64, device="cuda:0")
+    pk.block_lanczos_step(op, E_c, dE, a, tV, k, s, tA, tB, pk.FP64 if prec == "fp64" else pk.FP32)
+    eps = 2.2e-16 if prec == "fp64" else 1.2e-7
+    tol = 8 * (K + 1) * eps
+    assert np.max(np.abs(host(tA).T - A_ref)) <= tol
+    assert np.max(np.abs(host(tB).T - B_ref)) <= tol
+    Vn = host(tV)[k + s:k + 2 * s].T
+    assert np.max(np.abs(Vn - Vn_ref)) <= 4 * s * tol / np.min(np.diag(B_ref))
