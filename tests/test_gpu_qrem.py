@@ -206,3 +206,17 @@ def test_qrem_block_step_matches_oracle(pk, ctx, L, s, k, prec):
     assert np.max(np.abs(host(tB).T - B_ref)) <= tol
     Vn = host(tV)[k + s:k + 2 * s].T
     assert np.max(np.abs(Vn - Vn_ref)) <= 4 * s * tol / np.min(np.diag(B_ref))
+
+
+def test_qrem_block_solve_graph_replay(pk, ctx):
+    """The multi-column QREM filter recorded once as a HIP graph and replayed
+    every block step gives the dense pairs."""
+    say("qrem block solve graph replay")
+    op, E = qrem_case(pk, ctx, 12, 2)
+    H = models.qrem(12, E, 1.0)
+    X0 = np.stack([wl.start_vector(op.D, c) for c in range(4)])
+    evals, evecs, res, rep, status = pk.solve(op, dev(X0), 30, 0.0, "maxdos", graph=1)
+    assert status == "OK"
+    Er, _ = dense.nearest_eigenpairs(H, rep["lambda"], 30)
+    assert np.max(np.abs(host(evals) - Er) / np.maximum(np.abs(Er), 1.0)) <= 1e-10
+    assert host(res).max() <= 1e-8

@@ -164,3 +164,10 @@ def test_kpm_density_matches_oracle(pk):
     got = pk.kpm_density(mu, x)
     ref = kpm.density(mu, x)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_kpm_density_rejects_points_outside_the_interval(pk):
+    with pytest.raises(pk.PolfedError):
+        pk.kpm_density(np.ones(10), [0.5, 1.0])
+    with pytest.raises(pk.PolfedError):
+        pk.kpm_density(np.ones(10), [-1.5])
