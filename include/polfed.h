@@ -73,7 +73,10 @@ typedef struct polfed_req polfed_req;
 
 /* ---------------------------------------------------------------- context */
 
+/* Library version (major * 10000 + minor * 100 + patch). */
 int polfed_version(void);
+/* Text of the last error on the calling thread ("" after a success); owned
+ * by the library, valid until the thread's next call. */
 const char* polfed_last_error(void);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is the hipStream_t
@@ -81,6 +84,8 @@ const char* polfed_last_error(void);
  * that library work is ordered with other work queued there (e.g. torch's
  * default stream).  Fails with POLFED_ERR_NODEVICE when no GPU is visible. */
 polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out);
+/* Stops a running server, waits for the context's work and frees the
+ * context; its operators must not be used afterwards (NULL is a no-op). */
 polfed_status polfed_destroy(polfed_ctx* ctx);
 /* Waits for all work queued on the context's stream. */
 polfed_status polfed_sync(polfed_ctx* ctx);
@@ -191,6 +196,7 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage);
  * be NULL) receives the variant in use after the call (-1 while not tuned
  * yet). */
 polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, int* chosen);
+/* Dimension D of the operator's space (sector or full space). */
 polfed_status polfed_op_dim(const polfed_op* op, int64_t* D);
 /* Off-diagonal nnz of the CSR copy (-1 if there is none). */
 polfed_status polfed_op_nnz(const polfed_op* op, int64_t* nnz_offdiag);
@@ -199,6 +205,7 @@ polfed_status polfed_op_nnz(const polfed_op* op, int64_t* nnz_offdiag);
 polfed_status polfed_op_export_csr(polfed_ctx* ctx, const polfed_op* op,
                                    int64_t* rowptr, int32_t* col, double* val,
                                    double* diag);
+/* Frees the operator and its device tables (NULL is a no-op). */
 polfed_status polfed_op_destroy(polfed_op* op);
 /* y = H x (device vectors of length D, FP64). */
 polfed_status polfed_op_apply(polfed_ctx* ctx, const polfed_op* op,
@@ -397,6 +404,8 @@ typedef struct {
                             was completed by the FP64 filter */
 } polfed_report;
 
+/* Defaults: normalized target 0.5, 20 pairs, FP64, eta 1.5, residual
+ * tolerance 1e-8, bound pad 1e-3; every other field 0 (automatic). */
 polfed_status polfed_params_default(polfed_params* p);
 
 /* Synchronous solve.  x0: device start vector [D], or with block_size s > 1
@@ -438,10 +447,14 @@ polfed_status polfed_submit(polfed_ctx* ctx, const polfed_op* op,
                             const polfed_params* params, const double* x0,
                             double* evals, double* evecs, double* resid,
                             polfed_req** out);
+/* *done = 1 once the request has finished (does not block). */
 polfed_status polfed_poll(polfed_req* req, int* done);
 /* Blocks until the request finished; returns its solve status. */
 polfed_status polfed_wait(polfed_req* req, int* n_found, polfed_report* rep);
+/* Frees a finished request (POLFED_ERR_BUSY while it still runs; NULL is a
+ * no-op). */
 polfed_status polfed_req_destroy(polfed_req* req);
+/* Finishes every submitted request, then stops the scheduler. */
 polfed_status polfed_serve_stop(polfed_ctx* ctx);
 
 #ifdef __cplusplus
