@@ -731,7 +731,7 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
   return false;
 }
 
-// Picks the fastest variant for (op, precision) by timing 20 launches of
+// Picks the fastest variant for (op, precision) by replaying 20 launches of
 // each on scratch vectors; not while the stream is being captured.
 template <typename T, int L>
 static int tuned_variant(hipStream_t s, const polfed_op* op) {
@@ -748,34 +748,29 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   HIPC(hipMemsetAsync(bv.get(), 0, n * sizeof(T), s));
   HIPC(hipMemsetAsync(bb1.get(), 0, n * sizeof(T), s));
   HIPC(hipMemsetAsync(bb2.get(), 0, n * sizeof(T), s));
-  hipEvent_t e0, e1;
-  HIPC(hipEventCreate(&e0));
-  HIPC(hipEventCreate(&e1));
+  HIPC(hipStreamSynchronize(s));  // the operator's tables and the scratch vectors
   int best = 0;
-  float best_ms = 1e30f;
+  float best_us = 1e30f;
   for (int var = 0; var < 6; ++var) {
-    auto go = [&] {
-      return launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(),
-                                  bb2.as<T>(), bb2.as<T>());
-    };
-    if (!go()) continue;
-    go();
-    HIPC(hipEventRecord(e0, s));
-    for (int i = 0; i < 20; ++i) go();
-    HIPC(hipEventRecord(e1, s));
-    HIPC(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    const bool ok = launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(),
+                                         bb1.as<T>(), bb2.as<T>(), bb2.as<T>());
+    if (!ok) continue;
+    HIPC(hipStreamSynchronize(s));
+    const float us = replay_time_us(
+        [&](hipStream_t ts) {
+          launch_variant<T, L>(ts, op, var, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(),
+                               bb2.as<T>(), bb2.as<T>());
+        },
+        20);
     if (verbose())
       std::fprintf(stderr, "[polfed] chain step L=%d %s variant %d: %.2f us\n", L,
-                   sizeof(T) == 8 ? "fp64" : "fp32", var, 1e3f * ms / 20);
-    if (ms < best_ms) {
-      best_ms = ms;
+                   sizeof(T) == 8 ? "fp64" : "fp32", var, us);
+    if (us < best_us) {
+      best_us = us;
       best = var;
     }
   }
-  HIPC(hipEventDestroy(e0));
-  HIPC(hipEventDestroy(e1));
+  HIPC(hipStreamSynchronize(s));
   return op->tuned[pi] = best;
 }
 

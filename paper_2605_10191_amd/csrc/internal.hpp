@@ -88,6 +88,43 @@ class GraphExec {
   hipGraphExec_t exec_ = nullptr;
 };
 
+// Average run time in microseconds of one call of launch(stream), taken from
+// a replay of a graph of `reps` calls on a private stream.  Between eager
+// launches the host leaves gaps longer than a small kernel's own run time, so
+// an eager timing would not tell kernel variants apart at small sizes; a
+// replay runs the kernels back to back, as the filter's graphs do.  The caller
+// synchronizes whatever stream produced the data the launches read.
+template <class F>
+float replay_time_us(F&& launch, int reps) {
+  struct Timing {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Timing() {
+      if (s) (void)hipStreamSynchronize(s);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (s) (void)hipStreamDestroy(s);
+    }
+  };
+  GraphExec g;  // destroyed after the stream has drained
+  Timing t;
+  HIPC(hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking));
+  HIPC(hipEventCreate(&t.e0));
+  HIPC(hipEventCreate(&t.e1));
+  launch(t.s);  // any first-call work outside the capture
+  g.capture(t.s, [&](hipStream_t c) {
+    for (int i = 0; i < reps; ++i) launch(c);
+  });
+  g.launch(t.s);
+  HIPC(hipEventRecord(t.e0, t.s));
+  g.launch(t.s);
+  HIPC(hipEventRecord(t.e1, t.s));
+  HIPC(hipEventSynchronize(t.e1));
+  float ms = 0;
+  HIPC(hipEventElapsedTime(&ms, t.e0, t.e1));
+  return 1e3f * ms / (float)reps;
+}
+
 template <class T>
 void upload(DevBuf& b, const T* host, size_t n, hipStream_t s) {
   b.alloc(n * sizeof(T) > 0 ? n * sizeof(T) : 16);

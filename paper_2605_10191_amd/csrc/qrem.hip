@@ -203,8 +203,8 @@ static void launch_tb(hipStream_t s, const polfed_op* op, int tb, T sigma, T tau
   }
 }
 
-// Tile size picked by timing: the default and its two neighbours, 20
-// launches each on scratch vectors, at the first step of an operator in each
+// Tile size picked by timing: the default and its two neighbours, a replay
+// of 20 launches each on scratch vectors, at the first step of an operator in each
 // precision (not while the stream is being captured).
 template <typename T>
 static int tuned_tile_bits(hipStream_t s, const polfed_op* op) {
@@ -219,34 +219,26 @@ static int tuned_tile_bits(hipStream_t s, const polfed_op* op) {
   HIPC(hipMemsetAsync(bv.get(), 0, n * sizeof(T), s));
   HIPC(hipMemsetAsync(bb1.get(), 0, n * sizeof(T), s));
   HIPC(hipMemsetAsync(bb2.get(), 0, n * sizeof(T), s));
-  hipEvent_t e0, e1;
-  HIPC(hipEventCreate(&e0));
-  HIPC(hipEventCreate(&e1));
+  HIPC(hipStreamSynchronize(s));  // the operator's tables and the scratch vectors
   int best = t0;
-  float best_ms = 1e30f;
+  float best_us = 1e30f;
   for (int tb = t0 - 1; tb <= t0 + 1; ++tb) {
     if (tb < 1 || tb > std::min(op->L, kQremMaxTileBits)) continue;
-    auto go = [&] {
-      launch_tb<T>(s, op, tb, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(), bb2.as<T>(),
-                   bb2.as<T>());
-    };
-    go();
-    HIPC(hipEventRecord(e0, s));
-    for (int i = 0; i < 20; ++i) go();
-    HIPC(hipEventRecord(e1, s));
-    HIPC(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    const float us = replay_time_us(
+        [&](hipStream_t ts) {
+          launch_tb<T>(ts, op, tb, T(0.1), T(0), T(0), bv.as<T>(), bb1.as<T>(), bb2.as<T>(),
+                       bb2.as<T>());
+        },
+        20);
     if (verbose())
       std::fprintf(stderr, "[polfed] qrem step L=%d %s tile bits %d: %.2f us\n", op->L,
-                   sizeof(T) == 8 ? "fp64" : "fp32", tb, 1e3f * ms / 20);
-    if (ms < best_ms) {
-      best_ms = ms;
+                   sizeof(T) == 8 ? "fp64" : "fp32", tb, us);
+    if (us < best_us) {
+      best_us = us;
       best = tb;
     }
   }
-  HIPC(hipEventDestroy(e0));
-  HIPC(hipEventDestroy(e1));
+  HIPC(hipStreamSynchronize(s));
   return op->tuned[pi] = best;
 }
 
