@@ -457,3 +457,34 @@ def test_fp32_stalled_refinement_case(pk, ctx):
     U = host(U32)
     assert np.linalg.norm(H @ U - U * E32, axis=0).max() <= 1e-8
     say(f"   fallback={rep32['fp32_fallback']} sweeps={rep32['refine_sweeps']} iters={rep32['iters']}")
+
+
+# ------------------------------------------------------------ edge cases ----
+
+@pytest.mark.parametrize("L,N", [(6, 0), (6, 6), (5, 1), (4, 2)])
+def test_tiny_sectors_apply_and_step(pk, ctx, L, N):
+    """Sectors of dimension 1 (no hop possible) and a few states."""
+    say(f"tiny sector L={L} N={N}")
+    h = wl.xxz_fields(L, 1.0, 3)
+    op = pk.Operator.xxz(ctx, L, N, 1.0, 1.0, h, True)
+    H, _ = models.xxz(L, N, 1.0, 1.0, h, True)
+    assert op.D == H.shape[0]
+    rng = np.random.default_rng(0)
+    v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
+    assert np.max(np.abs(host(op.apply(dev(b1))) - H @ b1)) <= 1e-13 * max(1.0, np.max(np.abs(H @ b1)))
+    tb2 = dev(b2)
+    pk.clenshaw_step(op, 0.1, 3.0, 0.2, dev(v), dev(b1), tb2, pk.FP64)
+    ref = 0.2 * v + 2.0 * (H @ b1 - 0.1 * b1) / 3.0 - b2
+    assert np.max(np.abs(host(tb2) - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_solve_nearly_the_whole_spectrum(pk, ctx):
+    """XXZ L=8 (D = 70): 50 of the 70 eigenpairs, so the Krylov space
+    reaches the whole space."""
+    say("solve 50 of 70 pairs")
+    h = wl.xxz_fields(8, 2.0, 1)
+    op = pk.Operator.xxz(ctx, 8, 4, 1.0, 1.0, h, True)
+    H, _ = models.xxz(8, 4, 1.0, 1.0, h, True)
+    E_min, E_max = lanczos.spectral_extremes(H)
+    lam = polfed.target_energy("normalized", 0.5, E_min, E_max)
+    _check_solve(pk, op, H, 50, lam)
