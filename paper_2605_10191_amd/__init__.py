@@ -387,7 +387,9 @@ class Operator:
         return self
 
     def set_kernel(self, precision: int, variant: int) -> int:
-        """Step-kernel variant for a chain (-1 auto, 0 segment, 1/2 tile);
+        """Step-kernel variant for a chain (-1 autotuned, 0 segment, 3 paired
+        rows, 4 half segments, 1/2/5 tile kernels with the largest, middle
+        and smallest tile), or the tile size in bits for QREM (-1 autotuned);
         returns the variant in use."""
         out = _I()
         _check(_lib.polfed_op_set_kernel(self.handle, precision, variant, ctypes.byref(out)))

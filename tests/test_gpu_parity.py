@@ -205,19 +205,20 @@ def test_large_chain_sampled_rows(pk, ctx):
     assert np.max(np.abs(y[rows] - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("L", [22, 23, 24])
+@pytest.mark.parametrize("L,periodic", [(22, True), (23, True), (24, True), (23, False),
+                                        (24, False)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
-def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, prec, variant):
-    """Full-size Clenshaw steps of long chains with each step kernel (the
-    segment kernel; the tile kernels with 8/4 (L = 22), 16/8/4 (L = 23) and
-    32/16/8 (L = 24) high parts per tile; the paired-row and half-segment
-    kernels): sampled rows of a v + 2 H~ b1 - b2 against the oracle's
-    row-by-row eq. (xxz)."""
-    say(f"L={L} sampled clenshaw step {prec} variant {variant}")
+def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, periodic, prec, variant):
+    """Full-size Clenshaw steps of long chains, periodic and open, with each
+    step kernel (the segment kernel; the tile kernels with 8/4 (L = 22),
+    16/8/4 (L = 23) and 32/16/8 (L = 24) high parts per tile; the paired-row
+    and half-segment kernels): sampled rows of a v + 2 H~ b1 - b2 against the
+    oracle's row-by-row eq. (xxz)."""
+    say(f"L={L} periodic={periodic} sampled clenshaw step {prec} variant {variant}")
     N = L // 2
     h = wl.xxz_fields(L, 3.0, 1)
-    op = pk.Operator.xxz(ctx, L, N, 1.0, 1.0, h, True)
+    op = pk.Operator.xxz(ctx, L, N, 1.0, 1.0, h, periodic)
     if variant == 5 and L == 22:
         # no tile of a quarter size at L = 22 (the largest tile has 2 bits)
         with pytest.raises(pk.PolfedError):
@@ -237,7 +238,7 @@ def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, prec, variant):
     got = host(tb2).astype(np.float64)
     rows = np.unique(np.concatenate([rng.integers(0, op.D, 6000), np.arange(300),
                                      np.arange(op.D - 300, op.D)]))
-    Hb = models.xxz_rows_apply(L, N, 1.0, 1.0, h, True, st, rows, b1)
+    Hb = models.xxz_rows_apply(L, N, 1.0, 1.0, h, periodic, st, rows, b1)
     ref = a_i * v[rows] + 2.0 * (Hb - E_c * b1[rows]) / dE - b2[rows]
     tol = 1e-13 if prec == "fp64" else 3e-6
     assert np.max(np.abs(got[rows] - ref)) <= tol * np.max(np.abs(ref))
