@@ -20,7 +20,8 @@ Beside it the JSON line carries
                 8 TB/s HBM peak; traffic = HBM bytes per launch from the
                 rocprofv3 counters recorded in profiles/, when they were taken
                 on the current kernel source;
-  kernels       the same step kernel in FP32, as CSR SpMV, and as the
+  kernels       a plain 2 GiB device copy (the attainable HBM rate); the
+                same step kernel in FP32, as CSR SpMV, and as the
                 multi-column kernel over 8 realizations (a working set of
                 692 MB per step, larger than the 256 MB last-level cache);
                 XXZ L=20 matrix-free vs CSR; t-V L=26 (D = 10,400,600);
@@ -105,6 +106,17 @@ def xxz_setup(pk, wl, ctx, L, W, seed, n_ev):
     return op, x0, (E_min, E_max, lam, n_want, plan)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(L: int, W: float, seed: int, steps: int):
     """The oracle (plain FP64 SciPy CSR Clenshaw) on the same workload: a
     sample of `steps` Clenshaw steps, converted to the same algorithmic
@@ -125,7 +137,7 @@ def cpu_baseline(L: int, W: float, seed: int, steps: int):
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} Clenshaw steps (K={steps} filter application) of the "
                       f"oracle's SciPy CSR recurrence, XXZ L={L} D={D}, "
-                      f"{dt:.1f} s; host has {os.cpu_count()} CPUs, "
+                      f"{dt:.1f} s; host: {cpu_model()}, {os.cpu_count()} CPUs; "
                       "SciPy sparse mat-vec runs on one thread",
             "ms_per_clenshaw_step": round(1e3 * dt / steps, 3)}
 
@@ -135,6 +147,24 @@ def kernel_legs(pk, wl, ctx, L, W, iters):
     multi-column kernel on 8 realizations sharing the pattern."""
     import torch
     out = {}
+    # the attainable HBM rate on this chip: a plain device copy of 2 GiB
+    # (4 GiB touched, far beyond the 256 MB last-level cache)
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float64, device=ctx.torch_device)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["hbm_copy_2GiB"] = {"GBps": round(2 * 8 * n / (ms * 1e-3) / 1e9, 1),
+                            "us": round(ms * 1e3, 1), "bytes": 2 * 8 * n,
+                            "note": "torch device-to-device copy, read + write"}
+    del src, dst
     h = wl.xxz_fields(L, W, 0)
     op = pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, h, True)
     D = op.D
