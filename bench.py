@@ -30,9 +30,11 @@ Beside it the JSON line carries
                 plain FP64 and FP32 bulk + FP64 refinement, with the FP32
                 result's error per eigenpair against the FP64 one;
   serving       a Poisson stream of XXZ requests (L in 14, 16, 18; W in 1,
-                3, 5; 50 pairs each) through the continuous-batching server,
-                FP32 bulk (the workload's precision) and the same stream in
-                FP64: p50 / p99 latency and throughput;
+                3, 5; 50 pairs each) through the continuous-batching server
+                with the automatic precision (FP32 bulk where its step is
+                clearly faster, else FP64; the choice per L is recorded), and
+                the same stream with FP32 bulk forced: p50 / p99 latency and
+                throughput;
   cpu_baseline  the CPU oracle's Clenshaw steps at L=24 on a bounded sample.
 """
 from __future__ import annotations
@@ -417,8 +419,13 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
         t_end = time.perf_counter()
     lat = np.array([res[3]["t_latency"] for res in results])
     ok = sum(res[4] == "OK" for res in results)
+    label = {pk.FP32: "fp32_bulk+fp64_refine", pk.FP64: "fp64", pk.AUTO: "auto"}
+    used = {}
+    for (r, _, _), res in zip(reqs, results):
+        used.setdefault(f"L={r['L']}", set()).add(label[res[3]["precision"]])
     return {"requests": n_req, "ok": int(ok), "n_ev": n_ev,
-            "precision": "fp32_bulk+fp64_refine" if precision == pk.FP32 else "fp64",
+            "precision": label[precision],
+            "precision_used": {k: sorted(v) for k, v in sorted(used.items())},
             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 1),
             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 1),
             "mean_ms": round(1e3 * float(lat.mean()), 1),
@@ -457,7 +464,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     ap.add_argument("--serve-cols", type=int, default=16)
-    ap.add_argument("--serve-fp32-only", action="store_true")
+    ap.add_argument("--serve-one-leg", action="store_true",
+                    help="serve the stream with the automatic precision only")
     ap.add_argument("--serve-rate", type=float, default=1.0,
                     help="arrival rate as a multiple of the single-stream capacity")
     ap.add_argument("--profile-only", action="store_true",
@@ -581,15 +589,15 @@ def main():
                                            args.qrem_block)
     if not args.no_serve:
         sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
-                         args.serve_cols, pk.FP32, rate=args.serve_rate)
+                         args.serve_cols, pk.AUTO, rate=args.serve_rate)
         out["p50_p99_batched_solve_ms"] = [sv["p50_ms"], sv["p99_ms"]]
         out["serving"] = sv
         log(f"serving: {sv}")
-        if not args.serve_fp32_only:
-            sv64 = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
-                               args.serve_cols, pk.FP64, rate=args.serve_rate)
-            out["serving_fp64"] = sv64
-            log(f"serving fp64: {sv64}")
+        if not args.serve_one_leg:
+            sv32 = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
+                               args.serve_cols, pk.FP32, rate=args.serve_rate)
+            out["serving_fp32_bulk"] = sv32
+            log(f"serving fp32 bulk: {sv32}")
     else:
         out["p50_p99_batched_solve_ms"] = None
 

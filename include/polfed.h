@@ -54,6 +54,16 @@ typedef enum {
 } polfed_status;
 
 enum { POLFED_FP64 = 0, POLFED_FP32 = 1 };        /* Clenshaw precision */
+/* polfed_params.precision only (solves, batches, served requests): FP32 bulk
+ * filtering with FP64 refinement when the operator's FP32 Clenshaw step runs
+ * in less than 0.7 of the FP64 step's time, else FP64.  The two steps are
+ * timed (graph replays of 20 launches on scratch vectors, about 3 D-vectors
+ * of device memory for the duration) at the first such solve of an operator,
+ * or of any chain operator with the same off-diagonal pattern and storage on
+ * the device, and the choice is kept; polfed_report.precision says which
+ * ran.  The refinement costs about 40% of the FP32 filter time, so FP32 bulk
+ * only pays where the step is bound by bytes rather than by latency. */
+enum { POLFED_PRECISION_AUTO = 2 };
 enum { POLFED_MATRIX_FREE = 0, POLFED_CSR = 1 };  /* operator storage */
 enum {
   POLFED_TARGET_ABSOLUTE = 0,   /* target is lambda itself */
@@ -366,7 +376,8 @@ typedef struct {
   int target_kind;     /* POLFED_TARGET_* */
   double target;
   int n_ev;            /* N_ev >= 1 */
-  int precision;       /* POLFED_FP64, or POLFED_FP32 for the bulk filter */
+  int precision;       /* POLFED_FP64, POLFED_FP32 for the bulk filter, or
+                          POLFED_PRECISION_AUTO */
   int K_override;      /* 0: plan K */
   double omega;        /* 0: default cutoff */
   double eta;          /* 0: 1.5, over-allocation of the Krylov basis */
@@ -402,6 +413,9 @@ typedef struct {
   double t_latency;      /* served requests: submission to result (s) */
   int fp32_fallback;     /* 1: the FP32-bulk refinement stalled and the solve
                             was completed by the FP64 filter */
+  int precision;         /* POLFED_FP64 or POLFED_FP32: the filter precision
+                            the solve started in (the resolved choice for
+                            POLFED_PRECISION_AUTO) */
 } polfed_report;
 
 /* Defaults: normalized target 0.5, 20 pairs, FP64, eta 1.5, residual

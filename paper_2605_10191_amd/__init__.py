@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpolfed.so")
 
 FP64, FP32 = 0, 1
+# solves only: FP32 bulk filtering where its step is clearly faster, else FP64
+AUTO = 2
 MATRIX_FREE, CSR = 0, 1
 TARGET_ABSOLUTE, TARGET_RESCALED, TARGET_NORMALIZED = 0, 1, 2
 _TARGETS = {"absolute": 0, "rescaled": 1, "normalized": 2, "maxdos": 3, "offset": 4}
@@ -63,7 +65,7 @@ class Report(ctypes.Structure):
                  ("t_bounds", "t_plan", "t_filter", "t_reorth", "t_check",
                   "t_extract", "t_refine", "t_total", "filter_steps",
                   "filter_bytes", "filter_GBps", "t_queue", "t_latency")] +
-                [("fp32_fallback", ctypes.c_int)])
+                [("fp32_fallback", ctypes.c_int), ("precision", ctypes.c_int)])
 
     def as_dict(self) -> dict:
         d = {n: getattr(self, n) for n, _ in self._fields_}

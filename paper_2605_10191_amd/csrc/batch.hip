@@ -237,10 +237,14 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
                 ops[i]->pattern_key == ops[0]->pattern_key,
             "solve_batch: operators must be chains sharing the off-diagonal pattern");
   }
+  // one precision for the whole batch: the operators share the pattern, so
+  // the first one's timing stands for all
+  polfed_params q = p;
+  q.precision = resolve_precision(ctx->stream, ops[0], p.precision);
   std::vector<std::unique_ptr<SolveRun>> runs;
   for (int i = 0; i < B; ++i) {
     runs.emplace_back(new SolveRun());
-    runs.back()->setup(ctx, ops[i], p, x0[i], evals[i], evecs[i], resid[i], &n_found[i]);
+    runs.back()->setup(ctx, ops[i], q, x0[i], evals[i], evecs[i], resid[i], &n_found[i]);
   }
   // one batched filter per precision: an FP32-bulk run whose refinement
   // stalls continues with the FP64 filter

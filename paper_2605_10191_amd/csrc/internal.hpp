@@ -288,6 +288,8 @@ struct polfed_op {
   // step-kernel variant picked by timing on first use, per precision
   // (-1: not tuned yet, 0: segment kernel, 1 + i: tile kernel tiles[i])
   mutable int tuned[2] = {-1, -1};
+  // POLFED_PRECISION_AUTO resolved for this operator (-1: not timed yet)
+  mutable int auto_precision = -1;
   std::vector<double> split_dseg;  // uniform diagonal part of each segment
   std::vector<double> split_fab;   // field sums of low bits 0-4 | 5-9
   polfed::ChainSplitDev chain_split() const;
@@ -479,6 +481,11 @@ void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
 void block_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
                         const double* a, int K, double* V, int k, int s, double* A,
                         double* Bn, int precision);
+// POLFED_PRECISION_AUTO: FP32 when the operator's FP32 Clenshaw step runs in
+// under 0.7 of the FP64 step's time, else FP64; timed once per operator, or
+// per off-diagonal pattern and storage for chains, and kept.  Any other
+// precision is returned unchanged.  Synchronizes s when it times.
+int resolve_precision(hipStream_t s, const polfed_op* op, int precision);
 void profile_step(polfed_ctx* ctx, const polfed_op* op, int precision, int iters,
                   double* avg_ms, double* min_ms);
 

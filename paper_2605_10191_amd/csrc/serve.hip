@@ -253,11 +253,21 @@ polfed_status serve_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_pa
   REQUIRE(op && op->ctx == ctx, "serve: operator missing or from another context");
   REQUIRE(p && x0 && evals && evecs && resid && out, "serve: null argument");
   REQUIRE(p->n_ev >= 1 && p->n_ev <= op->D, "serve: need 1 <= n_ev <= D");
-  REQUIRE(p->precision == POLFED_FP64 || p->precision == POLFED_FP32, "serve: bad precision");
+  REQUIRE(p->precision == POLFED_FP64 || p->precision == POLFED_FP32 ||
+              p->precision == POLFED_PRECISION_AUTO,
+          "serve: bad precision");
   REQUIRE(p->block_size <= 1, "serve: block Lanczos (block_size > 1) runs through polfed_solve only");
   Server* s = ctx->server;
-  const size_t tb = p->precision == POLFED_FP32 ? 4 : 8;
-  const size_t fp = SolveRun::footprint(op, *p) + 4 * (size_t)op->D * tb;
+  // device bytes of the request; an automatic precision is resolved at
+  // admission, so it reserves the larger of the two
+  size_t fp = 0;
+  for (const int prec : {POLFED_FP64, POLFED_FP32}) {
+    if (p->precision != prec && p->precision != POLFED_PRECISION_AUTO) continue;
+    polfed_params q = *p;
+    q.precision = prec;
+    const size_t tb = prec == POLFED_FP32 ? 4 : 8;
+    fp = std::max(fp, SolveRun::footprint(op, q) + 4 * (size_t)op->D * tb);
+  }
   if (fp > s->budget)
     fail(POLFED_ERR_REJECTED, "serve: request needs " + std::to_string(fp) +
                                   " device bytes, more than the whole budget of " +

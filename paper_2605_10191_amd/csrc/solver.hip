@@ -13,7 +13,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
 
 #include "internal.hpp"
 #include "solve_run.hpp"
@@ -390,6 +393,7 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   const int64_t D = op->D;
   REQUIRE(D >= 1, "solve: empty operator");
   REQUIRE(p.n_ev >= 1 && p.n_ev <= D, "solve: need 1 <= n_ev <= D");
+  p.precision = resolve_precision(s, op, p.precision);
   REQUIRE(p.precision == POLFED_FP64 || p.precision == POLFED_FP32, "solve: bad precision");
   REQUIRE(x0 && evals && evecs && resid && n_found, "solve: null buffer");
   this->s = std::max(1, p.block_size);
@@ -404,6 +408,7 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   const double pad = p.bound_pad > 0 ? p.bound_pad : 1e-3;
   const double eta = p.eta > 0 ? p.eta : 1.5;
   R = polfed_report{};
+  R.precision = p.precision;
   *n_found = 0;
 
   // 1. spectral bounds
@@ -879,6 +884,54 @@ void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
 
 // Times `iters` back-to-back launches of the fused step kernel with a pair
 // of HIP events around each launch on the context stream.
+int resolve_precision(hipStream_t s, const polfed_op* op, int precision) {
+  if (precision != POLFED_PRECISION_AUTO) return precision;
+  if (op->auto_precision >= 0) return op->auto_precision;
+  // operators sharing the off-diagonal pattern and the storage run the same
+  // kernels at the same speed: one timing per pattern and device
+  static std::mutex mu;
+  static std::map<std::string, int> by_pattern;
+  const std::string key =
+      op->pattern_key.empty()
+          ? std::string()
+          : std::to_string(op->ctx->device) + "|" + std::to_string(op->storage) + "|" +
+                op->pattern_key;
+  if (!key.empty()) {
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = by_pattern.find(key);
+    if (it != by_pattern.end()) return op->auto_precision = it->second;
+  }
+  const int64_t D = op->D;
+  const size_t nd = (size_t)std::max<int64_t>(D, 1);
+  DevBuf v(nd * 8), b1(nd * 8), b2(nd * 8);
+  HIPC(hipMemsetAsync(v.get(), 0, nd * 8, s));
+  HIPC(hipMemsetAsync(b1.get(), 0, nd * 8, s));
+  HIPC(hipMemsetAsync(b2.get(), 0, nd * 8, s));
+  auto step = [&](hipStream_t st, bool f32) {
+    if (f32)
+      op_step<float>(st, op, 0.1f, 0.0f, 0.0f, v.as<float>(), b1.as<float>(), b2.as<float>(),
+                     b2.as<float>());
+    else
+      op_step<double>(st, op, 0.1, 0.0, 0.0, v.as<double>(), b1.as<double>(), b2.as<double>(),
+                      b2.as<double>());
+  };
+  // the first steps pick the kernel variants (timed on s, outside any capture)
+  step(s, false);
+  step(s, true);
+  HIPC(hipStreamSynchronize(s));
+  const float t64 = replay_time_us([&](hipStream_t st) { step(st, false); }, 20);
+  const float t32 = replay_time_us([&](hipStream_t st) { step(st, true); }, 20);
+  op->auto_precision = t32 < 0.7f * t64 ? POLFED_FP32 : POLFED_FP64;
+  if (!key.empty()) {
+    std::lock_guard<std::mutex> lk(mu);
+    by_pattern.emplace(key, op->auto_precision);
+  }
+  if (verbose())
+    std::fprintf(stderr, "[polfed] precision auto: step %.2f us FP64, %.2f us FP32 -> %s\n",
+                 t64, t32, op->auto_precision == POLFED_FP32 ? "FP32 bulk" : "FP64");
+  return op->auto_precision;
+}
+
 void profile_step(polfed_ctx* ctx, const polfed_op* op, int precision, int iters,
                   double* avg_ms, double* min_ms) {
   hipStream_t s = ctx->stream;

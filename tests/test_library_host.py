@@ -40,6 +40,32 @@ def test_library_exports_every_declared_symbol(pk):
     assert set(pk.SIGNATURES) | {"polfed_version", "polfed_last_error"} == set(names)
 
 
+def struct_fields(name):
+    """(field, C type) of a typedef'd struct of the header, in order."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", txt).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            typ, names = decl.split(None, 1)
+            out += [(n.strip(), typ) for n in names.split(",")]
+    return out
+
+
+def test_binding_structs_and_constants_match_the_header(pk):
+    ctypes_of = {"double": ctypes.c_double, "int": ctypes.c_int}
+    for cname, cls in (("polfed_report", pk.Report), ("polfed_params", pk.Params),
+                       ("polfed_plan", pk.Plan)):
+        want = [(n, ctypes_of[t]) for n, t in struct_fields(cname)]
+        got = [(n.rstrip("_"), t) for n, t in cls._fields_]
+        assert got == want, cname
+    txt = open(HEADER).read()
+    for cname, val in (("POLFED_FP64", pk.FP64), ("POLFED_FP32", pk.FP32),
+                       ("POLFED_PRECISION_AUTO", pk.AUTO)):
+        assert int(re.search(cname + r"\s*=\s*(\d+)", txt).group(1)) == val
+
+
 def test_version_and_basis_dim(pk):
     assert pk.load_library().polfed_version() >= 10000
     for L, N in [(12, 6), (20, 10), (24, 12), (26, 13), (32, 16), (5, 0)]:
