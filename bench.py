@@ -373,7 +373,8 @@ def solve_legs(pk, wl, ctx, L, n_ev, block_sizes=(4, 8)):
 
 def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate=1.0):
     """A Poisson stream through the server; arrival rate = `rate` times the
-    measured single-stream capacity (mean service time of one request per L)."""
+    measured single-stream capacity (mean service time of one request per L).
+    Latency runs from each request's planned arrival to its result."""
     import torch
     n_ev = 50
 
@@ -403,7 +404,8 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
             if r["t_arrive"] > now:
                 time.sleep(r["t_arrive"] - now)
             op, x0 = make(r["L"], r["W"], r["seed"])
-            reqs.append((r, op, srv.submit(op, x0, n_ev, 0.5, "normalized", precision=precision)))
+            req = srv.submit(op, x0, n_ev, 0.5, "normalized", precision=precision)
+            reqs.append((r, op, req, time.perf_counter() - t_start))
             log(f"serving: submitted request {len(reqs) - 1} L={r['L']} W={r['W']} "
                 f"at {time.perf_counter() - t_start:.2f}s")
         left = set(range(len(reqs)))
@@ -415,13 +417,16 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
                     log(f"serving: request {i} L={reqs[i][0]['L']} done, latency "
                         f"{rp['t_latency']:.2f}s queue {rp['t_queue']:.2f}s ({len(left)} left)")
             time.sleep(0.05)
-        results = [q.wait(allow_partial=True) for _, _, q in reqs]
+        results = [q.wait(allow_partial=True) for _, _, q, _ in reqs]
         t_end = time.perf_counter()
-    lat = np.array([res[3]["t_latency"] for res in results])
+    # latency from the request's arrival: the client's own delay before the
+    # submission (building the operator) plus the server's submit-to-result
+    delay = np.array([t_sub - r["t_arrive"] for r, _, _, t_sub in reqs])
+    lat = delay + np.array([res[3]["t_latency"] for res in results])
     ok = sum(res[4] == "OK" for res in results)
     label = {pk.FP32: "fp32_bulk+fp64_refine", pk.FP64: "fp64", pk.AUTO: "auto"}
     used = {}
-    for (r, _, _), res in zip(reqs, results):
+    for (r, _, _, _), res in zip(reqs, results):
         used.setdefault(f"L={r['L']}", set()).add(label[res[3]["precision"]])
     return {"requests": n_req, "ok": int(ok), "n_ev": n_ev,
             "precision": label[precision],
@@ -433,6 +438,7 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
             "single_stream_service_s": [round(x, 3) for x in svc],
             "arrival_rate_per_s": round(rate / mean_svc, 3),
             "max_queue_s": round(max(res[3]["t_queue"] for res in results), 3),
+            "max_submit_delay_s": round(float(delay.max()), 3),
             "fp32_fallbacks": int(sum(res[3]["fp32_fallback"] for res in results)),
             "hbm_budget_GiB": budget_gb, "max_cols": max_cols,
             "stream": "L in {14,16,18}, W in {1,3,5} uniform, Poisson arrivals at "

@@ -221,7 +221,7 @@ polfed_status polfed_basis_enumerate(polfed_ctx* ctx, int L, int N, uint32_t* st
     REQUIRE(D < (int64_t(1) << 31), "sector too large");
     REQUIRE(states != nullptr || D == 0, "null states");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     basis_enumerate(ctx->stream, L, N, D, states, ctx_binom(ctx));
     return POLFED_OK;
   });
@@ -236,7 +236,7 @@ polfed_status polfed_basis_rank(polfed_ctx* ctx, int L, int N, const uint32_t* s
     REQUIRE(n == 0 || (states && ranks), "null array");
     REQUIRE(binom64(L, N) < (int64_t(1) << 31), "sector too large");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     basis_rank(ctx->stream, L, N, states, n, ranks, ctx_binom(ctx));
     return POLFED_OK;
   });
@@ -252,7 +252,7 @@ polfed_status polfed_basis_unrank(polfed_ctx* ctx, int L, int N, const int64_t* 
     const int64_t D = binom64(L, N);
     REQUIRE(D < (int64_t(1) << 31), "sector too large");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     basis_unrank(ctx->stream, L, N, D, ranks, n, states, ctx_binom(ctx));
     return POLFED_OK;
   });
@@ -267,7 +267,7 @@ polfed_status polfed_op_xxz(polfed_ctx* ctx, int L, int n_up, double J, double D
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     *out = make_xxz(ctx, L, n_up, J, Delta, h, periodic);
     return POLFED_OK;
   });
@@ -280,7 +280,7 @@ polfed_status polfed_op_tv(polfed_ctx* ctx, int L, int n_part, double t, double 
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     *out = make_tv(ctx, L, n_part, t, V, eps, periodic);
     return POLFED_OK;
   });
@@ -296,7 +296,7 @@ polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L, const double* A,
     REQUIRE(std::isfinite(gamma) && std::isfinite(g0) && std::isfinite(alpha) && alpha > 0,
             "qsun: need finite gamma, g0 and alpha > 0");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     *out = make_qsun(ctx, N_dot, L, A, gamma, g0, alpha, u, n_of_j, h);
     return POLFED_OK;
   });
@@ -309,7 +309,7 @@ polfed_status polfed_op_qrem(polfed_ctx* ctx, int L, const double* E, double Gam
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     *out = make_qrem(ctx, L, E, Gamma);
     return POLFED_OK;
   });
@@ -323,7 +323,7 @@ polfed_status polfed_op_spin_chain(polfed_ctx* ctx, int L, int N, int R, const d
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     *out = make_spin_chain(ctx, L, N, R, J, Delta, h, periodic);
     return POLFED_OK;
   });
@@ -334,7 +334,7 @@ polfed_status polfed_op_optimize_mapping(polfed_ctx* ctx, polfed_op* op, int* n_
     CTX_OK(ctx);
     REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     const int n = optimize_mapping(ctx, op);
     if (n_values) *n_values = n;
     return POLFED_OK;
@@ -348,7 +348,7 @@ polfed_status polfed_op_csr(polfed_ctx* ctx, int64_t D, const int64_t* rowptr,
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     *out = make_csr(ctx, D, rowptr, col, val);
     return POLFED_OK;
   });
@@ -359,7 +359,7 @@ polfed_status polfed_op_materialize_csr(polfed_ctx* ctx, polfed_op* op) {
     CTX_OK(ctx);
     REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     materialize_csr(ctx, op);
     return POLFED_OK;
   });
@@ -551,7 +551,7 @@ polfed_status polfed_filter_apply(polfed_ctx* ctx, const polfed_op* op, double E
     REQUIRE(op->D == 0 || (v && w), "null vector");
     REQUIRE(v != w, "v and w must not overlap");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     const int64_t D = op->D;
     if (precision == POLFED_FP64) {
       DevBuf A(std::max<int64_t>(D, 1) * sizeof(double)), Bb(std::max<int64_t>(D, 1) * sizeof(double));
@@ -615,7 +615,7 @@ polfed_status polfed_filter_apply_batch(polfed_ctx* ctx, int B, const polfed_op*
     for (int i = 0; i < B; ++i) REQUIRE(a[i] && K[i] >= 0, "batch: need K >= 0 and a[K+1]");
     REQUIRE(v && w && v != w, "batch: null or overlapping vector blocks");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     ChainBatch bt;
     bt.init(ctx, ops, B);
     bt.set_scale(E_c, dE);
@@ -648,7 +648,7 @@ polfed_status polfed_clenshaw_step_batch(polfed_ctx* ctx, int B, const polfed_op
     REQUIRE(v && b1 && b2, "batch: null vector block");
     REQUIRE(b1 != b2 && b1 != v, "batch: b1 must not overlap v or b2");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     ChainBatch bt;
     bt.init(ctx, ops, B);
     bt.set_scale(E_c, dE);
@@ -682,7 +682,7 @@ polfed_status polfed_bounds(polfed_ctx* ctx, const polfed_op* op, const double* 
     REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
     REQUIRE(x0 && E_min && E_max, "null argument");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     bounds(ctx, op, x0, tol, max_iter, E_min, E_max, nullptr);
     return POLFED_OK;
   });
@@ -698,7 +698,7 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E
     REQUIRE(k >= 0 && k + 1 < op->D + 1, "need 0 <= k and k + 1 <= D");
     REQUIRE(V && alpha && beta, "null buffer");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     lanczos_step(ctx, op, E_c, dE, a, K, V, k, alpha, beta, precision);
     return POLFED_OK;
   });
@@ -711,7 +711,7 @@ polfed_status polfed_kpm_moments(polfed_ctx* ctx, const polfed_op* op, double E_
     REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
     REQUIRE(mu, "null output");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     kpm_moments(ctx, op, E_c, dE, N, R, r, seed, mu);
     return POLFED_OK;
   });
@@ -737,7 +737,7 @@ polfed_status polfed_block_lanczos_step(polfed_ctx* ctx, const polfed_op* op, do
             "need k >= 0 a multiple of s and k + 2 s <= D");
     REQUIRE(V && A && Bn, "null buffer");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     block_lanczos_step(ctx, op, E_c, dE, a, K, V, k, s, A, Bn, precision);
     return POLFED_OK;
   });
@@ -750,7 +750,7 @@ polfed_status polfed_profile_step(polfed_ctx* ctx, const polfed_op* op, int prec
     REQUIRE(iters >= 1 && iters <= 100000, "need 1 <= iters <= 100000");
     REQUIRE(avg_ms && min_ms, "null output");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     profile_step(ctx, op, precision, iters, avg_ms, min_ms);
     return POLFED_OK;
   });
@@ -780,7 +780,7 @@ polfed_status polfed_solve(polfed_ctx* ctx, const polfed_op* op, const polfed_pa
     REQUIRE(params, "null params");
     if (n_found) *n_found = 0;
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     return solve(ctx, op, *params, x0, evals, evecs, resid, n_found, rep);
   });
 }
@@ -795,7 +795,7 @@ polfed_status polfed_solve_batch(polfed_ctx* ctx, int B, const polfed_op* const*
             "null argument");
     for (int i = 0; i < B; ++i) REQUIRE(ops[i] && ops[i]->ctx == ctx, "bad operator");
     DeviceGuard g(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    CtxLock lk(ctx);
     return solve_batch(ctx, B, ops, *params, x0, evals, evecs, resid, n_found, rep);
   });
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <memory>
@@ -247,6 +248,8 @@ struct polfed_ctx {
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
   int n_cu = 256;
   std::mutex mu;  // serializes calls that use the shared workspaces
+  // API calls waiting for mu (the server thread lets them in between rounds)
+  std::atomic<int> api_waiting{0};
   // reusable workspaces
   polfed::DevBuf scratch_red;  // reduction partials
   polfed::DevBuf scratch_scalar;
@@ -254,6 +257,27 @@ struct polfed_ctx {
   polfed::DevBuf ws[8];  // scratch of the single-step entry points
   polfed::Server* server = nullptr;
 };
+
+namespace polfed {
+// Lock of a context for an API call.  The call announces itself before it
+// blocks: the server thread holds the lock for a whole round of filter work
+// and, as std::mutex is not fair, would otherwise take it again at once and
+// keep a caller (say, one building the next request's operator) waiting for
+// many rounds.
+class CtxLock {
+ public:
+  explicit CtxLock(polfed_ctx* c) : c_(c) {
+    c_->api_waiting.fetch_add(1);
+    c_->mu.lock();
+    c_->api_waiting.fetch_sub(1);
+  }
+  ~CtxLock() { c_->mu.unlock(); }
+  CtxLock(const CtxLock&) = delete;
+  CtxLock& operator=(const CtxLock&) = delete;
+ private:
+  polfed_ctx* c_;
+};
+}  // namespace polfed
 
 struct polfed_op {
   polfed_ctx* ctx = nullptr;

@@ -16,6 +16,7 @@
 // beyond the rounding of the batched filter.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -109,17 +110,29 @@ static std::string group_key(const polfed_req* r) {
   return k + (r->run->fp32 ? "|f32" : "|f64");
 }
 
+// Hands an admitted request back to its caller.  Everything the server keeps
+// of it (its place among the active solves, its share of the budget, the
+// solve and its device memory) is released first: once done is set, the
+// caller may destroy the request at any moment, so marking it done, under
+// its lock and with the waiters notified before the lock is released, is the
+// server's last access to it.
 void Server::complete(polfed_req* r, polfed_status st, const std::string& err) {
+  std::unique_ptr<SolveRun> run = std::move(r->run);
+  const polfed_report rep = run ? run->R : polfed_report{};
+  run.reset();
   {
-    std::lock_guard<std::mutex> lk(r->m);
-    r->status = st;
-    r->err = err;
-    if (r->run) r->rep = r->run->R;
-    r->t_done = now_seconds();
-    r->rep.t_queue = r->t_admit > 0 ? r->t_admit - r->t_submit : 0;
-    r->rep.t_latency = r->t_done - r->t_submit;
-    r->done = true;
+    std::lock_guard<std::mutex> lk(m);
+    active.erase(std::remove(active.begin(), active.end(), r), active.end());
+    used -= r->footprint;
   }
+  std::lock_guard<std::mutex> lk(r->m);
+  r->status = st;
+  r->err = err;
+  r->rep = rep;
+  r->t_done = now_seconds();
+  r->rep.t_queue = r->t_admit > 0 ? r->t_admit - r->t_submit : 0;
+  r->rep.t_latency = r->t_done - r->t_submit;
+  r->done = true;
   r->cv.notify_all();
 }
 
@@ -147,18 +160,11 @@ void Server::admit() {
       HIPC(hipEventDestroy(ready));
       r->run.reset(new SolveRun());
       r->run->setup(cc, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
+      std::lock_guard<std::mutex> lk(m);
       active.push_back(r);
     } catch (const Error& e) {
-      {
-        std::lock_guard<std::mutex> lk(m);
-        used -= r->footprint;
-      }
       complete(r, e.code, e.what());
     } catch (const std::exception& e) {
-      {
-        std::lock_guard<std::mutex> lk(m);
-        used -= r->footprint;
-      }
       complete(r, POLFED_ERR_INVALID, e.what());
     }
   }
@@ -172,6 +178,8 @@ void Server::loop() {
       cv.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
       if (stop && pending.empty() && active.empty()) return;
     }
+    // API calls waiting for the context go first
+    while (ctx->api_waiting.load() > 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
     std::lock_guard<std::mutex> ctx_lk(ctx->mu);
     admit();
     // current groups
@@ -179,7 +187,6 @@ void Server::loop() {
     for (auto* r : active) by_key[group_key(r)].push_back(r);
     for (auto it = groups.begin(); it != groups.end();)
       it = by_key.count(it->first) ? std::next(it) : groups.erase(it);
-    std::vector<polfed_req*> retired;
     for (auto& kv : by_key) {
       std::vector<SolveRun*> runs;
       for (auto* r : kv.second) runs.push_back(r->run.get());
@@ -195,10 +202,7 @@ void Server::loop() {
         }
       } catch (const Error& e) {
         g.bf.forget();
-        for (auto* r : kv.second) {
-          complete(r, e.code, e.what());
-          retired.push_back(r);
-        }
+        for (auto* r : kv.second) complete(r, e.code, e.what());
         continue;
       }
       std::vector<std::pair<polfed_req*, std::pair<polfed_status, std::string>>> fin;
@@ -218,16 +222,7 @@ void Server::loop() {
           polfed_report& R = f.first->run->R;
           R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
           complete(f.first, f.second.first, f.second.second);
-          retired.push_back(f.first);
         }
-      }
-    }
-    if (!retired.empty()) {
-      std::lock_guard<std::mutex> lk(m);
-      for (auto* r : retired) {
-        active.erase(std::remove(active.begin(), active.end(), r), active.end());
-        used -= r->footprint;
-        r->run.reset();
       }
     }
   }

@@ -105,3 +105,52 @@ def test_serve_invalid_request_and_stop_with_pending(pk, ctx):
     for r in reqs:
         assert r.poll()
         check(H, 10, r.wait())
+
+
+def test_api_calls_are_not_starved_by_the_server(pk, ctx):
+    """While the server works through a stream of solves, calls on the same
+    context (here: building operators, as a client does for each request)
+    wait for at most a round of the server's work, not for many rounds."""
+    say("serve: concurrent API calls")
+    n_ev = 50
+    cases = [make(pk, ctx, "xxz", 16, W, s) for s, W in enumerate((1.0, 3.0, 5.0, 3.0))]
+    x0s = [dev(wl.start_vector(op.D, s)) for s, (op, _) in enumerate(cases)]
+    h14 = [wl.xxz_fields(14, 3.0, 100 + i) for i in range(6)]
+    waits = []
+    with pk.Server(ctx, 8 << 30, max_cols=8) as srv:
+        reqs = [srv.submit(op, x0s[i], n_ev, 0.5, "normalized") for i, (op, _) in enumerate(cases)]
+        time.sleep(0.2)  # the server is busy with the solves
+        for h in h14:
+            t0 = time.perf_counter()
+            op = pk.Operator.xxz(ctx, 14, 7, 1.0, 1.0, h, True)
+            waits.append(time.perf_counter() - t0)
+            op.close()
+        busy = [not r.poll() for r in reqs]
+        results = [r.wait() for r in reqs]
+    say(f"   operator builds took {', '.join(f'{w * 1e3:.0f}' for w in waits)} ms "
+        f"(solves still running at the end: {sum(busy)})")
+    assert max(waits) < 1.0
+    for i, (op, H) in enumerate(cases):
+        check(H, n_ev, results[i])
+
+
+def test_requests_destroyed_as_soon_as_done(pk, ctx):
+    """A client that polls and destroys each request the moment it is done,
+    while the server still runs other groups in the same round: the server
+    releases a request's solve before it marks it done, so nothing of the
+    request is touched after that."""
+    say("serve: destroy on completion")
+    n_ev = 20
+    mix = [("xxz", 10, 1.0, 0), ("xxz", 12, 3.0, 1), ("xxz", 14, 5.0, 2), ("tv", 12, 0, 3),
+           ("xxz", 10, 3.0, 4), ("xxz", 12, 5.0, 5), ("xxz", 14, 1.0, 6), ("xxz", 12, 1.0, 7)]
+    cases = [make(pk, ctx, *m) for m in mix]
+    x0s = [dev(wl.start_vector(op.D, 60 + i)) for i, (op, _) in enumerate(cases)]
+    with pk.Server(ctx, 8 << 30, max_cols=8) as srv:
+        reqs = [srv.submit(op, x0s[i], n_ev, 0.5, "normalized") for i, (op, _) in enumerate(cases)]
+        results = [None] * len(reqs)
+        while any(r is None for r in results):
+            for i, q in enumerate(reqs):
+                if results[i] is None and q.poll():
+                    results[i] = q.wait()  # destroys the request at once
+    for i, (op, H) in enumerate(cases):
+        check(H, n_ev, results[i])
