@@ -187,6 +187,11 @@ void Server::loop() {
     for (auto* r : active) by_key[group_key(r)].push_back(r);
     for (auto it = groups.begin(); it != groups.end();)
       it = by_key.count(it->first) ? std::next(it) : groups.erase(it);
+    // every group's filter application is launched before any member is
+    // advanced: advancing reads a member's Lanczos coefficients back and so
+    // waits for its group's filter, which would otherwise keep the groups'
+    // recurrences from running side by side on their streams
+    std::vector<std::pair<Group*, const std::vector<polfed_req*>*>> launched;
     for (auto& kv : by_key) {
       std::vector<SolveRun*> runs;
       for (auto* r : kv.second) runs.push_back(r->run.get());
@@ -205,8 +210,12 @@ void Server::loop() {
         for (auto* r : kv.second) complete(r, e.code, e.what());
         continue;
       }
+      launched.push_back({&g, &kv.second});
+    }
+    for (auto& gm : launched) {
+      Group& g = *gm.first;
       std::vector<std::pair<polfed_req*, std::pair<polfed_status, std::string>>> fin;
-      for (auto* r : kv.second) {
+      for (auto* r : *gm.second) {
         try {
           r->run->advance();
           if (r->run->done) fin.push_back({r, {r->run->status, ""}});
