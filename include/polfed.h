@@ -83,7 +83,9 @@ typedef struct polfed_req polfed_req;
 
 /* ---------------------------------------------------------------- context */
 
-/* Library version (major * 10000 + minor * 100 + patch). */
+/* Library version (major * 10000 + minor * 100 + patch).  10100 added
+ * POLFED_PRECISION_AUTO and polfed_report.precision (the report grew by one
+ * int: callers built against an older header pass a smaller struct). */
 int polfed_version(void);
 /* Text of the last error on the calling thread ("" after a success); owned
  * by the library, valid until the thread's next call. */

@@ -135,7 +135,7 @@ using namespace polfed;
 
 extern "C" {
 
-int polfed_version(void) { return 10000; }
+int polfed_version(void) { return 10100; }
 
 const char* polfed_last_error(void) { return g_err.c_str(); }
 
