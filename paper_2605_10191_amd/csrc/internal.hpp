@@ -268,7 +268,12 @@ class CtxLock {
  public:
   explicit CtxLock(polfed_ctx* c) : c_(c) {
     c_->api_waiting.fetch_add(1);
-    c_->mu.lock();
+    try {
+      c_->mu.lock();
+    } catch (...) {
+      c_->api_waiting.fetch_sub(1);  // else the server would wait for ever
+      throw;
+    }
     c_->api_waiting.fetch_sub(1);
   }
   ~CtxLock() { c_->mu.unlock(); }
