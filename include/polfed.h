@@ -458,7 +458,11 @@ polfed_status polfed_serve_start(polfed_ctx* ctx, size_t hbm_budget_bytes,
                                  int max_cols);
 /* Queues a solve; op, x0 and the output buffers must stay alive until
  * polfed_wait returns.  Requests whose footprint exceeds the budget are
- * rejected (POLFED_ERR_REJECTED); block_size must be 0 or 1. */
+ * rejected (POLFED_ERR_REJECTED); block_size must be 0 or 1.  With
+ * POLFED_PRECISION_AUTO the precision is chosen at admission and the request
+ * reserves the larger of the two footprints.  Calls on ctx from other
+ * threads while the server runs wait for at most the server's current round
+ * of work. */
 polfed_status polfed_submit(polfed_ctx* ctx, const polfed_op* op,
                             const polfed_params* params, const double* x0,
                             double* evals, double* evecs, double* resid,
