@@ -197,3 +197,15 @@ def test_kpm_density_rejects_points_outside_the_interval(pk):
         pk.kpm_density(np.ones(10), [0.5, 1.0])
     with pytest.raises(pk.PolfedError):
         pk.kpm_density(np.ones(10), [-1.5])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asked for more it says so and exits
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
