@@ -209,3 +209,28 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_product_path_is_independent_of_the_oracle():
+    """The library package neither imports nor links the oracle, and the HIP
+    sources include nothing from it; bench.py reaches it only in its CPU
+    baseline leg."""
+    import ast
+    pkg = os.path.join(ROOT, "paper_2605_10191_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            path = os.path.join(dirpath, f)
+            if f.endswith(".py"):
+                tree = ast.parse(open(path).read())
+                for node in ast.walk(tree):
+                    if isinstance(node, ast.Import):
+                        assert not any(a.name.split(".")[0] == "oracle" for a in node.names), path
+                    if isinstance(node, ast.ImportFrom):
+                        assert (node.module or "").split(".")[0] != "oracle", path
+            elif f.endswith((".hip", ".cpp", ".hpp", ".h")):
+                assert "oracle" not in open(path).read(), path
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = {fn.name for fn in ast.walk(tree) if isinstance(fn, ast.FunctionDef)
+             for node in ast.walk(fn)
+             if isinstance(node, ast.ImportFrom) and (node.module or "").startswith("oracle")}
+    assert users == {"cpu_baseline"}
