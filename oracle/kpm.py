@@ -69,24 +69,3 @@ def search_interval(E_min: float, E_max: float, E_c: float, dE: float):
     [E_min, E_max] without 5% of its width at each end."""
     w = E_max - E_min
     return (E_min + 0.05 * w - E_c) / dE, (E_max - 0.05 * w - E_c) / dE
-
-
-def splitmix_vectors(D: int, R: int, seed: int) -> np.ndarray:
-    """D x R random vectors of the library's KPM draws, from the published
-    splitmix64 generator (Steele, Lea and Flood, 2014): for vector c the
-    counter i + 1 is mixed from the state seed + c + golden * (i + 1);
-    u = (z >> 11) / 2^53 on [0, 1), entries sqrt(3) (2u - 1) (zero mean,
-    unit variance)."""
-    M = (1 << 64) - 1
-    golden = 0x9E3779B97F4A7C15
-    out = np.empty((D, R))
-    i = np.arange(1, D + 1, dtype=np.uint64)
-    for c in range(R):
-        with np.errstate(over="ignore"):
-            z = (np.uint64((seed + c) & M) + np.uint64(golden) * i)
-            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-            z = z ^ (z >> np.uint64(31))
-        u = (z >> np.uint64(11)).astype(np.float64) * (2.0 / 9007199254740992.0) - 1.0
-        out[:, c] = np.sqrt(3.0) * u
-    return out

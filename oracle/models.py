@@ -247,6 +247,29 @@ def xxz_rows_apply(L: int, N: int, J: float, Delta: float, h, periodic: bool,
     return out + diag * x[rows]
 
 
+def tv_rows_apply(L: int, N: int, t: float, V: float, eps, periodic: bool,
+                  states: np.ndarray, rows: np.ndarray, x: np.ndarray):
+    """(H x)[r] of the t-V Hamiltonian (see `tv`) for the listed rows only,
+    for checks at sizes where the whole matrix is not built.  Row state s
+    receives c^dag_a c_b from the state s' = s with a and b exchanged when s
+    has a occupied and b empty; the amplitude is -t times the Jordan-Wigner
+    sign of that hop acting on s'.  `states` is the full ascending sector
+    list (basis.sector_states)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    s = states[rows]
+    diag = np.zeros(len(rows))
+    for i in range(L):
+        diag += eps[i] * _bit(s, i)
+    out = np.zeros(len(rows))
+    for (i, j) in _bonds(L, periodic):
+        diag += V * _bit(s, i) * _bit(s, j)
+        for (a, b) in ((i, j), (j, i)):
+            sel = (_bit(s, a) == 1) & (_bit(s, b) == 0)
+            src = s[sel] ^ ((1 << a) | (1 << b))
+            out[sel] += -t * fermion_hop_sign(src, a, b) * x[basis.rank(states, src)]
+    return out + diag * x[rows]
+
+
 def is_symmetric(H, tol: float = 0.0) -> bool:
     diff = (H - H.T).tocsr()
     if diff.nnz == 0:

@@ -97,7 +97,9 @@ def test_filter_apply_batch_matches_oracle(pk, ctx, case, Ks, prec):
     got = host(w).astype(np.float64)
     for c in range(B):
         err = np.linalg.norm(got[c] - refs[c]) / np.linalg.norm(refs[c])
+        err_el = np.max(np.abs(got[c] - refs[c])) / np.max(np.abs(refs[c]))
         assert err <= filter_tol(max(Ks), prec), (c, Ks[c], err)
+        assert err_el <= filter_tol(max(Ks), prec), (c, Ks[c], err_el)
 
 
 def test_batch_rejects_mixed_patterns(pk, ctx):

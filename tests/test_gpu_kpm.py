@@ -44,7 +44,7 @@ def test_kpm_moments_library_draws(pk, ctx):
     op, H = make_op(pk, ctx, *OPS[0])
     E_c, dE = _scale(H)
     got = pk.kpm_moments(op, E_c, dE, 50, 4, None, seed=12345)
-    ref = kpm.moments(H, E_c, dE, kpm.splitmix_vectors(op.D, 4, 12345), 50)
+    ref = kpm.moments(H, E_c, dE, wl.splitmix_vectors(op.D, 4, 12345), 50)
     assert np.max(np.abs(got - ref)) <= 1e-11 * op.D
 
 
@@ -64,7 +64,7 @@ def test_solve_with_kpm_dos_matches_oracle(pk, ctx, case):
     lo, hi = lanczos.spectral_extremes(H)
     x0 = wl.start_vector(op.D, 0)
     ref = polfed.polfed(H, x0, n_ev, 0.0, "maxdos", bounds=(lo, hi),
-                        kpm_vectors=kpm.splitmix_vectors(op.D, 20, 0x4B504D), kpm_moments=64)
+                        kpm_vectors=wl.splitmix_vectors(op.D, 20, 0x4B504D), kpm_moments=64)
     evals, evecs, res, rep, status = pk.solve(op, dev(x0), n_ev, 0.0, "maxdos",
                                               kpm_moments=64, kpm_vectors=20,
                                               E_min=lo, E_max=hi)

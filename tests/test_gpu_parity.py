@@ -209,15 +209,15 @@ def test_large_chain_sampled_rows(pk, ctx):
                                         (24, False)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
-def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, periodic, prec, variant):
+def test_long_chain_clenshaw_step_all_rows(pk, ctx, L, periodic, prec, variant):
     """Full-size Clenshaw steps of long chains, periodic and open, with each
     step kernel (the segment kernel; the tile kernels with 8/4 (L = 22),
     16/8/4 (L = 23) and 32/16/8 (L = 24) high parts per tile; the paired-row
-    and half-segment kernels): sampled rows of a v + 2 H~ b1 - b2 against the
-    oracle's row-by-row eq. (xxz)."""
-    say(f"L={L} periodic={periodic} sampled clenshaw step {prec} variant {variant}")
+    and half-segment kernels): every row of a v + 2 H~ b1 - b2 against the
+    oracle's CSR of eq. (xxz)."""
+    say(f"L={L} periodic={periodic} clenshaw step {prec} variant {variant}")
     N = L // 2
-    h = wl.xxz_fields(L, 3.0, 1)
+    h, H, _ = xxz_case(L, N, 3.0, 1, periodic)
     op = pk.Operator.xxz(ctx, L, N, 1.0, 1.0, h, periodic)
     if variant == 5 and L == 22:
         # no tile of a quarter size at L = 22 (the largest tile has 2 bits)
@@ -225,7 +225,6 @@ def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, periodic, prec, varia
             op.set_kernel(pk.FP64 if prec == "fp64" else pk.FP32, variant)
         return
     assert op.set_kernel(pk.FP64 if prec == "fp64" else pk.FP32, variant) == variant
-    st = basis.sector_states(L, N)
     rng = np.random.default_rng(5)
     v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
     dt = torch.float64 if prec == "fp64" else torch.float32
@@ -236,12 +235,52 @@ def test_long_chain_clenshaw_step_sampled_rows(pk, ctx, L, periodic, prec, varia
     pk.clenshaw_step(op, E_c, dE, a_i, dev(v, dt), dev(b1, dt), tb2,
                      pk.FP64 if prec == "fp64" else pk.FP32)
     got = host(tb2).astype(np.float64)
+    ref = _ref_step(H, E_c, dE, a_i, v, b1, b2, False)
+    tol = 1e-13 if prec == "fp64" else 3e-6
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("L,N,periodic", [(24, 12, True), (26, 13, True), (25, 12, False)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_tv_long_chain_clenshaw_step(pk, ctx, L, N, periodic, prec, variant):
+    """Full-size t-V steps with every step kernel.  N = 12 makes the periodic
+    hop's Jordan-Wigner sign -1, N = 13 (the L = 26 configuration) +1.  Every
+    row at L = 24 against the oracle's CSR; at L = 26 (D = 10,400,600) and
+    the open L = 25 chain, 6,000 random rows and the first and last 300
+    against the oracle's row-by-row evaluation (models.tv_rows_apply, pinned
+    on every row of smaller chains)."""
+    say(f"t-V L={L} N={N} periodic={periodic} step {prec} variant {variant}")
+    eps = wl.tv_onsite(L, 2)
+    op = pk.Operator.tv(ctx, L, N, 1.0, 1.0, eps, periodic)
+    p = pk.FP64 if prec == "fp64" else pk.FP32
+    assert op.set_kernel(p, variant) == variant
+    rng = np.random.default_rng(6)
+    v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        v, b1, b2 = (x.astype(np.float32).astype(np.float64) for x in (v, b1, b2))
+    E_c, dE, a_i = -0.3, 31.0, 0.021
+    tb2 = dev(b2, dt)
+    pk.clenshaw_step(op, E_c, dE, a_i, dev(v, dt), dev(b1, dt), tb2, p)
+    got = host(tb2).astype(np.float64)
+    tol = 1e-13 if prec == "fp64" else 3e-6
+    if L == 24:
+        _, H, _ = tv_case(L, N, 2, periodic)
+        ref = _ref_step(H, E_c, dE, a_i, v, b1, b2, False)
+        assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+        return
+    st = _sector(L, N)
     rows = np.unique(np.concatenate([rng.integers(0, op.D, 6000), np.arange(300),
                                      np.arange(op.D - 300, op.D)]))
-    Hb = models.xxz_rows_apply(L, N, 1.0, 1.0, h, periodic, st, rows, b1)
+    Hb = models.tv_rows_apply(L, N, 1.0, 1.0, eps, periodic, st, rows, b1)
     ref = a_i * v[rows] + 2.0 * (Hb - E_c * b1[rows]) / dE - b2[rows]
-    tol = 1e-13 if prec == "fp64" else 3e-6
     assert np.max(np.abs(got[rows] - ref)) <= tol * np.max(np.abs(ref))
+
+
+@functools.lru_cache(maxsize=2)
+def _sector(L, N):
+    return basis.sector_states(L, N)
 
 
 # ----------------------------------------------------------------- filter ----
@@ -324,8 +363,10 @@ def test_filter_apply_matches_oracle(pk, ctx, case, K, prec):
                         pk.FP64 if prec == "fp64" else pk.FP32)
     got = host(w).astype(np.float64)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    say(f"   rel err {err:.2e} (tol {_filter_tol(K, prec):.1e})")
+    err_el = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say(f"   rel err {err:.2e}, element-wise {err_el:.2e} (tol {_filter_tol(K, prec):.1e})")
     assert err <= _filter_tol(K, prec)
+    assert err_el <= _filter_tol(K, prec)
 
 
 def test_filter_on_diagonal_operator_closed_form(pk, ctx):

@@ -89,7 +89,7 @@ def test_polfed_with_kpm_dos_vs_dense():
 
 
 def test_splitmix_draws_have_unit_variance_and_differ_per_vector():
-    R = kpm.splitmix_vectors(20000, 3, 7)
+    R = wl.splitmix_vectors(20000, 3, 7)
     assert np.all(np.abs(R.mean(axis=0)) < 0.03)
     assert np.all(np.abs(R.var(axis=0) - 1.0) < 0.03)
     assert np.all(np.abs(R) < np.sqrt(3.0))

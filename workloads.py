@@ -12,7 +12,11 @@ Distributions follow the models of the paper's Appendix A:
 * spinless t-V fermions (not in the paper): on-site energies eps_i ~ U[-2, 2];
 * quantum random energy model, eq. (qrem): one Gaussian energy per basis state,
   mean 0 and standard deviation sqrt(L/2);
-* start vector: U[0, 1) entries, as in the paper's usage example (Sec. 5.2).
+* start vector: U[0, 1) entries, as in the paper's usage example (Sec. 5.2);
+* KPM probe vectors (Sec. 4.1, App. B) with zero-mean, unit-variance entries,
+  drawn by the published splitmix64 generator from a counter, so that the
+  library, which draws its own probe vectors on the device, and the oracle see
+  the same vectors.
 """
 from __future__ import annotations
 
@@ -66,3 +70,23 @@ def serving_stream(n_req: int, seed: int, mean_gap_s: float,
     Wc = rng.choice(np.asarray(Ws), n_req)
     return [{"t_arrive": float(t[i]), "L": int(Lc[i]), "W": float(Wc[i]),
              "seed": int(seed * 100003 + i)} for i in range(n_req)]
+
+
+def splitmix_vectors(D: int, R: int, seed: int) -> np.ndarray:
+    """D x R KPM probe vectors from the published splitmix64 generator
+    (Steele, Lea and Flood, 2014): for vector c the counter i + 1 is mixed
+    from the state seed + c + golden * (i + 1); u = (z >> 11) / 2^53 on
+    [0, 1), entries sqrt(3) (2u - 1) (zero mean, unit variance)."""
+    M = (1 << 64) - 1
+    golden = 0x9E3779B97F4A7C15
+    out = np.empty((D, R))
+    i = np.arange(1, D + 1, dtype=np.uint64)
+    for c in range(R):
+        with np.errstate(over="ignore"):
+            z = (np.uint64((seed + c) & M) + np.uint64(golden) * i)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+        u = (z >> np.uint64(11)).astype(np.float64) * (2.0 / 9007199254740992.0) - 1.0
+        out[:, c] = np.sqrt(3.0) * u
+    return out
