@@ -418,6 +418,13 @@ typedef struct {
   int precision;         /* POLFED_FP64 or POLFED_FP32: the filter precision
                             the solve started in (the resolved choice for
                             POLFED_PRECISION_AUTO) */
+  double mem_peak;       /* largest device bytes the solve's own buffers held
+                            at once (operator tables and the server's shared
+                            batch buffers not included) */
+  double mem_reserved;   /* served requests: the most device bytes reserved
+                            for the request against the server's budget
+                            (admission estimate plus later grants); 0 for
+                            polfed_solve */
 } polfed_report;
 
 /* Defaults: normalized target 0.5, 20 pairs, FP64, eta 1.5, residual

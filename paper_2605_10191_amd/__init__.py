@@ -65,7 +65,8 @@ class Report(ctypes.Structure):
                  ("t_bounds", "t_plan", "t_filter", "t_reorth", "t_check",
                   "t_extract", "t_refine", "t_total", "filter_steps",
                   "filter_bytes", "filter_GBps", "t_queue", "t_latency")] +
-                [("fp32_fallback", ctypes.c_int), ("precision", ctypes.c_int)])
+                [("fp32_fallback", ctypes.c_int), ("precision", ctypes.c_int),
+                 ("mem_peak", ctypes.c_double), ("mem_reserved", ctypes.c_double)])
 
     def as_dict(self) -> dict:
         d = {n: getattr(self, n) for n, _ in self._fields_}

@@ -41,6 +41,8 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
   throw Error(POLFED_ERR_HIP, m);
 }
 
+thread_local MemTally* g_mem_tally = nullptr;
+
 void DevBuf::alloc(size_t bytes) {
   release();
   if (bytes == 0) bytes = 16;
@@ -53,12 +55,19 @@ void DevBuf::alloc(size_t bytes) {
   }
   p_ = p;
   n_ = bytes;
+  t_ = g_mem_tally;
+  if (t_) {
+    t_->cur += bytes;
+    t_->peak = std::max(t_->peak, t_->cur);
+  }
 }
 
 void DevBuf::release() {
   if (p_) (void)hipFree(p_);
+  if (p_ && t_) t_->cur -= n_;
   p_ = nullptr;
   n_ = 0;
+  t_ = nullptr;
 }
 
 void GraphExec::reset() {

@@ -1,6 +1,7 @@
 // Small host eigensolvers for the Lanczos matrix and the Rayleigh-Ritz
-// projection.  Symmetric tridiagonal: implicit QL with Wilkinson-type shifts
-// (Bowdler, Martin, Reinsch and Wilkinson, 1968).  Dense symmetric:
+// projection.  Symmetric tridiagonal: the implicit QL algorithm with
+// Wilkinson-type shifts (Dubrulle, Martin and Wilkinson, Numer. Math. 12,
+// 1968, the procedure known as imtql2).  Dense symmetric:
 // Householder reduction to tridiagonal form (Golub and Van Loan, Sec. 8.3)
 // followed by the tridiagonal solver.  Sizes here are a few hundred at most.
 #include <algorithm>

@@ -33,6 +33,22 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 
 // --------------------------------------------------- device buffers ----
 
+// Device bytes held by a set of buffers: the current total and its peak.
+// A buffer counts toward the tally that was active on its thread when it
+// was allocated, until it is released (wherever that happens).
+struct MemTally {
+  size_t cur = 0, peak = 0;
+};
+extern thread_local MemTally* g_mem_tally;
+// Makes t the active tally of this thread for the scope's lifetime.
+struct TallyScope {
+  MemTally* prev;
+  explicit TallyScope(MemTally* t) : prev(g_mem_tally) { g_mem_tally = t; }
+  ~TallyScope() { g_mem_tally = prev; }
+  TallyScope(const TallyScope&) = delete;
+  TallyScope& operator=(const TallyScope&) = delete;
+};
+
 // Owning device allocation (library-internal workspaces and tables).
 class DevBuf {
  public:
@@ -41,9 +57,21 @@ class DevBuf {
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), t_(o.t_) {
+    o.p_ = nullptr;
+    o.n_ = 0;
+    o.t_ = nullptr;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    if (this != &o) {
+      release();
+      p_ = o.p_;
+      n_ = o.n_;
+      t_ = o.t_;
+      o.p_ = nullptr;
+      o.n_ = 0;
+      o.t_ = nullptr;
+    }
     return *this;
   }
   void alloc(size_t bytes);
@@ -54,6 +82,7 @@ class DevBuf {
  private:
   void* p_ = nullptr;
   size_t n_ = 0;
+  MemTally* t_ = nullptr;
 };
 
 // A sequence of launches recorded once on a capture stream and replayed as
@@ -376,6 +405,11 @@ void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool fina
 template <typename T>
 void op_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
              const T* v, const T* b1, const T* b2, T* out);
+// Runs the step-kernel tuner of a matrix-free chain or QREM operator for one
+// precision (one eager step on scratch vectors, on s) if it has not run yet.
+// The tuners time launches and cannot run inside a stream capture, so every
+// caller that records the recurrence into a graph calls this first.
+void op_tune(hipStream_t s, const polfed_op* op, bool fp32);
 void op_moments(hipStream_t s, const polfed_op* op, double* d_two, double* partial,
                 int64_t npart);
 // Split-layout chain step; false when no instantiation covers op->L.

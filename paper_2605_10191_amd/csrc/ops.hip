@@ -403,6 +403,24 @@ template void op_step<double>(hipStream_t, const polfed_op*, double, double,
 template void op_step<float>(hipStream_t, const polfed_op*, float, float, float,
                              const float*, const float*, const float*, float*);
 
+void op_tune(hipStream_t s, const polfed_op* op, bool fp32) {
+  if (op->D == 0 || op->storage == POLFED_CSR) return;
+  const int pi = fp32 ? 1 : 0;
+  // (the QREM tuner skips chains shorter than 12 sites)
+  const bool untuned = op->model == Model::Qrem    ? (op->tuned[pi] < 1 && op->L >= 12)
+                       : op->model == Model::Chain ? (op->tuned[pi] < 0 && op->split_nseg > 0)
+                                                   : false;
+  if (!untuned) return;
+  const size_t bytes = (size_t)op->D * (fp32 ? sizeof(float) : sizeof(double));
+  DevBuf b1(bytes), out(bytes);
+  HIPC(hipMemsetAsync(b1.get(), 0, bytes, s));
+  if (fp32)
+    op_step<float>(s, op, 0.0f, 0.0f, 0.0f, nullptr, b1.as<float>(), nullptr, out.as<float>());
+  else
+    op_step<double>(s, op, 0.0, 0.0, 0.0, nullptr, b1.as<double>(), nullptr, out.as<double>());
+  HIPC(hipStreamSynchronize(s));
+}
+
 // ------------------------------------------------------------ moments ----
 // Per row: diag and (diag^2 + sum of squared off-diagonal entries).
 

@@ -33,7 +33,10 @@ struct polfed_req {
   polfed_params p{};
   const double* x0 = nullptr;
   double *evals = nullptr, *evecs = nullptr, *resid = nullptr;
-  size_t footprint = 0;
+  size_t footprint = 0;     // device bytes reserved at admission
+  size_t held = 0;          // bytes reserved now (admission plus grants)
+  size_t held_max = 0;      // the most ever reserved
+  size_t prepaid = 0;       // part of footprint learned from an eviction
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::mutex m;
   std::condition_variable cv;
@@ -69,6 +72,9 @@ struct Server {
   void loop();
   void admit();
   void complete(polfed_req* r, polfed_status st, const std::string& err);
+  void evict(polfed_req* r);
+  bool take(polfed_req* r, size_t bytes);
+  void give(polfed_req* r, size_t bytes);
 };
 
 static std::string pattern_of(const polfed_op* op) {
@@ -118,12 +124,15 @@ static std::string group_key(const polfed_req* r) {
 // server's last access to it.
 void Server::complete(polfed_req* r, polfed_status st, const std::string& err) {
   std::unique_ptr<SolveRun> run = std::move(r->run);
-  const polfed_report rep = run ? run->R : polfed_report{};
+  polfed_report rep = run ? run->R : polfed_report{};
+  if (run) rep.mem_peak = (double)run->tally.peak;
+  rep.mem_reserved = (double)r->held_max;
   run.reset();
   {
     std::lock_guard<std::mutex> lk(m);
     active.erase(std::remove(active.begin(), active.end(), r), active.end());
-    used -= r->footprint;
+    used -= r->held;
+    r->held = 0;
   }
   std::lock_guard<std::mutex> lk(r->m);
   r->status = st;
@@ -134,6 +143,49 @@ void Server::complete(polfed_req* r, polfed_status st, const std::string& err) {
   r->rep.t_latency = r->t_done - r->t_submit;
   r->done = true;
   r->cv.notify_all();
+}
+
+// Grants a running solve more of the budget (false: not available now).
+bool Server::take(polfed_req* r, size_t bytes) {
+  std::lock_guard<std::mutex> lk(m);
+  if (used + bytes > budget) return false;
+  used += bytes;
+  r->held += bytes;
+  r->held_max = std::max(r->held_max, r->held);
+  return true;
+}
+
+void Server::give(polfed_req* r, size_t bytes) {
+  std::lock_guard<std::mutex> lk(m);
+  bytes = std::min(bytes, r->held);
+  used -= bytes;
+  r->held -= bytes;
+}
+
+// Every running solve waits for bytes that only a finishing solve could
+// free: the latest admitted one is stopped, its memory returned, and it goes
+// back to the head of the queue reserving what it has learned it needs (or
+// fails if that exceeds the whole budget).  Its solve restarts from x0 when
+// it is admitted again.
+void Server::evict(polfed_req* r) {
+  const size_t need = r->held + r->run->want;
+  r->run.reset();
+  {
+    std::lock_guard<std::mutex> lk(m);
+    active.erase(std::remove(active.begin(), active.end(), r), active.end());
+    used -= r->held;
+    r->held = 0;
+    if (need <= budget) {
+      r->prepaid += need - std::min(need, r->footprint);
+      r->footprint = std::max(r->footprint, need);
+      pending.push_front(r);
+      return;
+    }
+  }
+  complete(r, POLFED_ERR_OOM,
+           "serve: the solve needs " + std::to_string(need) +
+               " device bytes as its Krylov space grew, more than the whole budget of " +
+               std::to_string(budget));
 }
 
 // Admission in arrival order: stop at the first request that does not fit,
@@ -148,6 +200,8 @@ void Server::admit() {
       r = pending.front();
       pending.pop_front();
       used += r->footprint;
+      r->held = r->footprint;
+      r->held_max = std::max(r->held_max, r->held);
     }
     r->t_admit = now_seconds();
     try {
@@ -159,6 +213,10 @@ void Server::admit() {
       HIPC(hipStreamWaitEvent(cc->stream, ready, 0));
       HIPC(hipEventDestroy(ready));
       r->run.reset(new SolveRun());
+      r->run->granted = r->prepaid;
+      r->run->take = [this, r](size_t b) { return take(r, b); };
+      r->run->give = [this, r](size_t b) { give(r, b); };
+      TallyScope ts(&r->run->tally);
       r->run->setup(cc, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
       std::lock_guard<std::mutex> lk(m);
       active.push_back(r);
@@ -183,8 +241,15 @@ void Server::loop() {
     std::lock_guard<std::mutex> ctx_lk(ctx->mu);
     admit();
     // current groups
+    // a solve waiting for budget takes no filter step this round
     std::map<std::string, std::vector<polfed_req*>> by_key;
-    for (auto* r : active) by_key[group_key(r)].push_back(r);
+    std::vector<polfed_req*> waiting;
+    for (auto* r : active) {
+      if (r->run->blocked())
+        waiting.push_back(r);
+      else
+        by_key[group_key(r)].push_back(r);
+    }
     for (auto it = groups.begin(); it != groups.end();)
       it = by_key.count(it->first) ? std::next(it) : groups.erase(it);
     // every group's filter application is launched before any member is
@@ -198,6 +263,7 @@ void Server::loop() {
       Group& g = groups[kv.first];
       try {
         if (runs.size() == 1 && kv.first.rfind("op:", 0) == 0) {
+          TallyScope ts(&runs[0]->tally);
           runs[0]->filter_self();
         } else {
           // rebuilt whenever a member joined or left (a new solve may reuse
@@ -217,6 +283,7 @@ void Server::loop() {
       std::vector<std::pair<polfed_req*, std::pair<polfed_status, std::string>>> fin;
       for (auto* r : *gm.second) {
         try {
+          TallyScope ts(&r->run->tally);
           r->run->advance();
           if (r->run->done) fin.push_back({r, {r->run->status, ""}});
         } catch (const Error& e) {
@@ -233,6 +300,28 @@ void Server::loop() {
           complete(f.first, f.second.first, f.second.second);
         }
       }
+    }
+    // solves waiting for budget: granted now if others have released bytes
+    bool progress = !launched.empty();
+    for (auto* r : waiting) {
+      try {
+        TallyScope ts(&r->run->tally);
+        r->run->resume();
+        if (!r->run->blocked()) progress = true;
+        if (r->run->done) complete(r, r->run->status, "");
+      } catch (const Error& e) {
+        complete(r, e.code, e.what());
+        progress = true;
+      } catch (const std::exception& e) {
+        complete(r, POLFED_ERR_INVALID, e.what());
+        progress = true;
+      }
+    }
+    if (!progress && !waiting.empty()) {
+      polfed_req* last = nullptr;
+      for (auto* r : waiting)
+        if (r->run && r->run->blocked() && (!last || r->t_admit > last->t_admit)) last = r;
+      if (last) evict(last);
     }
   }
 }

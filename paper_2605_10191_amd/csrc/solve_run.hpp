@@ -2,6 +2,7 @@
 // iteration, driven either one column at a time or by a multi-column filter
 // shared with other realizations.
 #pragma once
+#include <functional>
 #include <utility>
 #include <vector>
 
@@ -132,6 +133,9 @@ void block_start(hipStream_t st, int64_t D, int s, const double* X0, double* V, 
                  double* c, double* partial, int64_t nseg, int* flag, double* scal);
 
 struct SolveRun {
+  // device bytes held by this solve's own buffers (declared first, so it
+  // outlives every buffer member that counts toward it)
+  MemTally tally;
   // inputs
   polfed_ctx* ctx = nullptr;
   const polfed_op* op = nullptr;
@@ -176,8 +180,28 @@ struct SolveRun {
   // bounds, plan, basis allocation, v_0 = x0 / ||x0||
   void setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm, const double* x0,
              double* ev, double* vecs, double* res, int* nf);
-  // device bytes a solve of this operator holds at its expected Krylov size
+  // Largest device bytes a solve of this operator holds when its Krylov
+  // space stays within the expected size and n_want does not grow: basis,
+  // work and filter vectors, and the larger of the extraction (FP64) and
+  // the FP32 refinement with its FP64 fallback.
   static size_t footprint(const polfed_op* op, const polfed_params& p);
+  // the same for m basis columns and n wanted pairs
+  static size_t bytes_at(int64_t D, int m, int n, bool fp32);
+  // Served solves: bytes beyond the admission's footprint (a basis grown
+  // past the expected size, a larger n_want) are asked for through take()
+  // before they are allocated; bytes no longer held go back through give().
+  // Both are empty outside the server.  A refused request blocks the solve
+  // (no filter runs for it) until resume() obtains the bytes.
+  std::function<bool(size_t)> take;
+  std::function<void(size_t)> give;
+  size_t want = 0;     // bytes a blocked solve waits for
+  size_t granted = 0;  // bytes obtained ahead of the allocation that needs them
+  enum { kPendNone, kPendGrow, kPendWant } pend = kPendNone;
+  int pend_n_want = 0;
+  bool blocked() const { return want > 0; }
+  bool reserve(size_t bytes);  // false: blocked, want = bytes
+  void resume();               // retries a blocked request, then continues
+  void step_tail();            // basis growth and the periodic check
   const double* vec() const { return B.col(k); }  // v_k, the vector to filter
   double* wbuf() const { return ws.w.as<double>(); }  // where P(H~) v_k goes
   void filter_self();  // single-column filter of v_k into wbuf()

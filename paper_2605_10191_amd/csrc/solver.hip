@@ -496,14 +496,60 @@ void SolveRun::setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm
   sbytes = step_bytes(op, p.precision);
 }
 
+size_t SolveRun::bytes_at(int64_t D_, int m, int n, bool f32) {
+  const size_t D = (size_t)std::max<int64_t>(D_, 1), vec = D * 8, M = (size_t)m, N = (size_t)n;
+  const size_t nseg = (size_t)std::max<int64_t>(1, std::min<int64_t>(256, (D_ + 8191) / 8192));
+  // basis (M + 2 columns) and the coefficient and partial-sum arrays
+  size_t b = (M + 2) * vec + (nseg * (M + 1) + 8192 + 3 * (M + 2)) * 8;
+  // w, the filter's two recurrence buffers, the FP32 copies of v and w,
+  // and the fixed graph input (FP64)
+  b += vec + (f32 ? 4 * D * 4 : 3 * vec);
+  // check and extraction: the tridiagonal eigenvectors (M x M), the chosen
+  // ones (M x n), the projected matrix and its eigenvectors, partial sums
+  b += (M * M + M * N + 2 * N * N + nseg * N + 8192) * 8;
+  // FP64: U, HU, U2, HU2.  FP32 refinement: the extracted U2, HU2, four
+  // FP32 blocks, five FP64 blocks and the next Rayleigh-Ritz generation;
+  // then the two FP64 recurrence buffers of the FP64 fallback.
+  b += f32 ? 11 * N * vec + 2 * vec : 4 * N * vec;
+  return b;
+}
+
 size_t SolveRun::footprint(const polfed_op* op, const polfed_params& p) {
   const int n_ev = std::max(1, p.n_ev);
-  const int g = (p.precision == POLFED_FP32 ? 2 : 1) * buffer_size(n_ev);
+  const bool f32 = p.precision == POLFED_FP32;
+  const int g = (f32 ? 2 : 1) * buffer_size(n_ev);
   const int n_want = (int)std::min<int64_t>(op->D, n_ev + g);
-  const int M = expected_krylov_dim(n_want, 1, p.eta > 0 ? p.eta : 1.5);
-  const size_t D = (size_t)op->D;
-  // basis, the work vectors and the extraction blocks (U, HU, U2, HU2)
-  return D * 8 * ((size_t)M + 2) + D * 8 * 4 * (size_t)n_want + D * 8 * 3;
+  const int M = (int)std::min<int64_t>(op->D, expected_krylov_dim(n_want, 1, p.eta > 0 ? p.eta : 1.5));
+  return bytes_at(op->D, M, n_want, f32);
+}
+
+bool SolveRun::reserve(size_t bytes) {
+  if (!take) return true;
+  if (granted >= bytes) {
+    granted -= bytes;
+    return true;
+  }
+  if (!take(bytes - granted)) {
+    want = bytes;
+    return false;
+  }
+  granted = 0;
+  return true;
+}
+
+void SolveRun::resume() {
+  if (!want) return;
+  if (!take(want - std::min(want, granted))) return;
+  granted = want;
+  want = 0;
+  const auto what = pend;
+  pend = kPendNone;
+  if (what == kPendGrow) {
+    step_tail();
+  } else if (what == kPendWant) {
+    granted = 0;
+    n_want = pend_n_want;
+  }
 }
 
 void SolveRun::filter_self() {
@@ -518,6 +564,7 @@ void SolveRun::filter_self() {
   const bool use_graph = mode == kTimeGraph || mode == kGraph;
   if (use_graph && !graph.ready()) {
     if (!fp32) vst.alloc((size_t)std::max<int64_t>(D, 1) * sizeof(double));
+    op_tune(s, op, fp32);
     graph.capture(ctx->cap_stream, [&](hipStream_t cs) {
       if (fp32)
         filter_apply_on<float>(cs, op, pl.E_c, pl.dE, a.data(), pl.K, ws.v32.as<float>(),
@@ -610,11 +657,25 @@ void SolveRun::advance() {
   HIPC(hipEventRecord(r1, s));
   rev.emplace_back(r0, r1);
   ++k;
+  step_tail();
+}
+
+void SolveRun::step_tail() {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
   if (k >= cap && cap < M_max) {
     const int ncap = std::min(M_max, (int)std::ceil(1.25 * cap) + 1);
+    // the larger basis is allocated before the old one is freed
+    const size_t old_basis = (size_t)D * (B.cap + 1) * 8;
+    const size_t more = bytes_at(D, ncap, n_want, fp32) - bytes_at(D, cap, n_want, fp32);
+    if (!reserve(more + old_basis)) {
+      pend = kPendGrow;
+      return;
+    }
     B.ensure(s, D, ncap, k + 1);
     ws.grow(s, ncap + 1);
     cap = ncap;
+    if (give) give(old_basis);
   }
   if (k < next_check && k < M_max) return;
 
@@ -767,8 +828,15 @@ bool SolveRun::conclude(const std::vector<double>& thf, const DevBuf& dC, int nw
     fallback_fp64();
     return true;
   }
-  if ((int)ex.sel.size() == p.n_ev && !ex.complete)
-    n_want = std::min(M_max, n_want + std::max(10, n_want / 5));
+  if ((int)ex.sel.size() == p.n_ev && !ex.complete) {
+    const int nw2 = std::min(M_max, n_want + std::max(10, n_want / 5));
+    if (reserve(bytes_at(op->D, cap, nw2, fp32) - bytes_at(op->D, cap, n_want, fp32))) {
+      n_want = nw2;
+    } else {
+      pend = kPendWant;
+      pend_n_want = nw2;
+    }
+  }
   return false;
 }
 
@@ -836,11 +904,13 @@ polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p
                     const double* x0, double* evals, double* evecs, double* resid,
                     int* n_found, polfed_report* rep) {
   SolveRun run;
+  TallyScope ts(&run.tally);
   run.setup(ctx, op, p, x0, evals, evecs, resid, n_found);
   while (!run.done) {
     run.filter_self();
     run.advance();
   }
+  run.R.mem_peak = (double)run.tally.peak;
   if (rep) *rep = run.R;
   return run.status;
 }

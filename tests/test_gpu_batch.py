@@ -164,3 +164,21 @@ def test_solve_batch_graph_replay(pk, ctx):
     assert status == "OK"
     for c, (ev, U, R, rep) in enumerate(out):
         _check_pairs(Hs[c], rep["lambda"], 20, ev, U, R)
+
+
+@pytest.mark.parametrize("kind,L,B,n_ev", [("xxz", 12, 3, 20), ("xxz", 14, 4, 50),
+                                           ("tv", 12, 3, 20)])
+def test_solve_batch_fp32_bulk_matches_dense(pk, ctx, kind, L, B, n_ev):
+    """FP32 recurrence for the whole batch, FP64 reorthogonalization,
+    Rayleigh-Ritz and refinement: every column meets the FP64 bar against
+    the dense FP64 oracle, and its per-eigenpair error is reported."""
+    say(f"solve_batch FP32 bulk {kind} L={L} B={B} n_ev={n_ev}")
+    ops, Hs = batch_ops(pk, ctx, kind, L, B)
+    x0s = [dev(wl.start_vector(o.D, c)) for c, o in enumerate(ops)]
+    out, status = pk.solve_batch(ops, x0s, n_ev, 0.5, "normalized", precision=pk.FP32)
+    assert status == "OK"
+    for c, (ev, U, R, rep) in enumerate(out):
+        assert rep["precision"] == pk.FP32
+        rel, res = _check_pairs(Hs[c], rep["lambda"], n_ev, ev, U, R)
+        say(f"   col {c}: K={rep['K']} iters={rep['iters']} sweeps={rep['refine_sweeps']} "
+            f"fallback={rep['fp32_fallback']} max rel dE={rel:.1e} max res={res:.1e}")

@@ -471,6 +471,20 @@ def test_solve_graph_replay_matches_direct_launches(pk, ctx, prec):
     assert rep_g["iters"] == rep_d["iters"] or prec == "fp32"
 
 
+def test_graph_solve_tunes_step_kernel_before_capture(pk, ctx):
+    """A solve whose first FP32 filter is recorded into a graph (graph=1)
+    still picks the FP32 step kernel by timing: the tuner runs on the
+    library stream before the capture (it cannot time launches inside one),
+    so the captured recurrence uses the tuned variant, not the default."""
+    say("graph solve tunes before capture")
+    op, H = make_op(pk, ctx, *OPS[0])
+    assert op.set_kernel(pk.FP32, -2) == -1  # a fresh operator is not tuned
+    E_min, E_max = lanczos.spectral_extremes(H)
+    lam = polfed.target_energy("normalized", 0.5, E_min, E_max)
+    _check_solve(pk, op, H, 20, lam, precision=pk.FP32, graph=1, refine_max=-1)
+    assert op.set_kernel(pk.FP32, -2) >= 0
+
+
 def test_fp32_refinement_fallback_to_fp64(pk, ctx):
     """With no refinement sweeps allowed, an FP32-bulk solve hands over to the
     FP64 filter and still returns the dense oracle's pairs."""

@@ -154,3 +154,67 @@ def test_requests_destroyed_as_soon_as_done(pk, ctx):
                     results[i] = q.wait()  # destroys the request at once
     for i, (op, H) in enumerate(cases):
         check(H, n_ev, results[i])
+
+
+def test_serve_fp32_bulk_stream_matches_dense_and_alone(pk, ctx):
+    """A mixed stream of FP32-bulk requests (FP32 recurrence, FP64
+    reorthogonalization, Rayleigh-Ritz and refinement): each result meets
+    the FP64 bar against the dense oracle and equals the same request
+    solved alone; the per-eigenpair error against the oracle is printed."""
+    say("serve FP32 bulk stream")
+    n_ev = 20
+    mix = [("xxz", 12, 1.0, 0), ("xxz", 14, 3.0, 1), ("tv", 12, 0, 2), ("xxz", 12, 5.0, 3),
+           ("xxz", 14, 5.0, 4), ("xxz", 12, 3.0, 5)]
+    cases = [make(pk, ctx, *m) for m in mix]
+    x0s = [dev(wl.start_vector(op.D, 80 + i)) for i, (op, _) in enumerate(cases)]
+    with pk.Server(ctx, 8 << 30, max_cols=4) as srv:
+        reqs = []
+        for i, (op, _) in enumerate(cases):
+            reqs.append(srv.submit(op, x0s[i], n_ev, 0.5, "normalized", precision=pk.FP32))
+            time.sleep(0.01 * (i % 3))
+        results = [r.wait() for r in reqs]
+    for i, (op, H) in enumerate(cases):
+        rep = results[i][3]
+        assert rep["precision"] == pk.FP32
+        E = check(H, n_ev, results[i])
+        Er, _ = dense.nearest_eigenpairs(H, rep["lambda"], n_ev)
+        say(f"   req {i} {mix[i]}: max rel dE vs oracle "
+            f"{np.max(np.abs(E - Er) / np.maximum(np.abs(Er), 1.0)):.1e} "
+            f"sweeps {rep['refine_sweeps']} fallback {rep['fp32_fallback']}")
+        ev1, _, _, rep1, st = pk.solve(op, x0s[i], n_ev, 0.5, "normalized", precision=pk.FP32)
+        assert st == "OK"
+        assert np.max(np.abs(host(ev1) - E) / np.maximum(np.abs(E), 1.0)) <= 1e-10
+
+
+def test_serve_memory_stays_within_reservation(pk, ctx):
+    """FP32-bulk requests (their refinement holds several blocks of pairs)
+    and FP64 requests whose Krylov space outgrows the expected size (eta
+    0.6 forces basis growth) under a budget of about two requests: each
+    request's own device buffers never exceed what the server reserved for
+    it, growth beyond the admission estimate is granted from the budget, and
+    every result meets the FP64 bar."""
+    say("serve memory within reservation")
+    n_ev = 20
+    cases = [make(pk, ctx, "xxz", 14, W, s) for s, W in enumerate((1.0, 3.0, 5.0, 3.0, 1.0, 5.0))]
+    prec = [pk.FP32, pk.FP64, pk.FP32, pk.FP64, pk.FP32, pk.FP64]
+    kw = [{}, {"eta": 0.6}, {}, {"eta": 0.6}, {"eta": 0.6}, {}]
+    x0s = [dev(wl.start_vector(op.D, s)) for s, (op, _) in enumerate(cases)]
+    # the admission estimate of one FP32 request, from a server of its own
+    with pk.Server(ctx, 8 << 30, max_cols=2) as srv:
+        one = srv.submit(cases[0][0], x0s[0], n_ev, 0.5, "normalized", precision=pk.FP32).wait()
+    check(cases[0][1], n_ev, one)
+    assert 0 < one[3]["mem_peak"] <= one[3]["mem_reserved"]
+    budget = int(2.2 * one[3]["mem_reserved"])
+    with pk.Server(ctx, budget, max_cols=8) as srv:
+        reqs = [srv.submit(op, x0s[i], n_ev, 0.5, "normalized", precision=prec[i], **kw[i])
+                for i, (op, _) in enumerate(cases)]
+        results = [r.wait() for r in reqs]
+    for i, (op, H) in enumerate(cases):
+        rep = results[i][3]
+        say(f"   req {i}: prec {rep['precision']} M_alloc {rep['M_alloc']} iters {rep['iters']} "
+            f"peak {rep['mem_peak'] / 1e6:.2f} MB reserved {rep['mem_reserved'] / 1e6:.2f} MB "
+            f"queue {rep['t_queue']:.2f}s")
+        check(H, n_ev, results[i])
+        assert 0 < rep["mem_peak"] <= rep["mem_reserved"] <= budget
+    # the eta = 0.6 requests outgrew their expected Krylov size
+    assert any(results[i][3]["iters"] > results[i][3]["M_alloc"] for i in (1, 3, 4))
