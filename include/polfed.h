@@ -200,9 +200,16 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage);
  * 3 = segment kernel with two adjacent rows per lane (16-byte accesses),
  * 4 = segment kernel with each segment split between two wavefronts,
  * 5 = tile kernel with a quarter of the largest tile;
+ * 6 .. 9 = staged-tile kernel (the tile's rows and segment records copied
+ * to LDS by direct-to-LDS loads; the tile also spans the top state bit, so
+ * the periodic bond is an LDS read): 6 the largest tile with one buffer and
+ * 1024 threads, 7 half that tile with two buffers (the next tile is staged
+ * while the current one is processed) and 512 threads, 8 half that tile
+ * with one buffer, 9 the largest tile with two buffers (where the LDS holds
+ * them, FP32);
  * -2 only reports the variant in use.
- * A variant that does not exist for the chain length (tiles need L >= 22)
- * gives POLFED_ERR_INVALID.  For a quantum random energy model the variant is
+ * A variant that does not exist for the chain length and precision (tiles
+ * need L >= 22) gives POLFED_ERR_INVALID.  For a quantum random energy model the variant is
  * the tile size in bits (rows per LDS tile = 2^variant), 1 .. min(L, 12), or
  * -1 to pick among the default and its neighbours by timing.  *chosen (may
  * be NULL) receives the variant in use after the call (-1 while not tuned

@@ -392,8 +392,8 @@ class Operator:
     def set_kernel(self, precision: int, variant: int) -> int:
         """Step-kernel variant for a chain (-1 autotuned, 0 segment, 3 paired
         rows, 4 half segments, 1/2/5 tile kernels with the largest, middle
-        and smallest tile), or the tile size in bits for QREM (-1 autotuned);
-        returns the variant in use."""
+        and smallest tile, 6-9 staged-tile kernels), or the tile size in bits
+        for QREM (-1 autotuned); returns the variant in use."""
         out = _I()
         _check(_lib.polfed_op_set_kernel(self.handle, precision, variant, ctypes.byref(out)))
         return out.value

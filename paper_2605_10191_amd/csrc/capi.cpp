@@ -404,13 +404,17 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
       if (chosen) *chosen = op->tuned[pi];
       return POLFED_OK;
     }
-    REQUIRE(variant >= -1 && variant <= 5, "variant must be -2 .. 5");
+    REQUIRE(variant >= -1 && variant < kChainVariants,
+            "variant must be -2 .. " + std::to_string(kChainVariants - 1));
     if (variant > 0) {
       REQUIRE(op->model == Model::Chain && op->split_nseg > 0,
               "step-kernel variants exist only for matrix-free chains");
       if (variant <= 2 || variant == 5)
         REQUIRE(op->tiles[variant == 5 ? 2 : variant - 1].n > 0,
                 "no tile kernel of this size for this chain length");
+      if (variant >= 6)
+        REQUIRE(chain_wt_exists(op, variant, pi == 1),
+                "no staged-tile kernel of this shape for this chain length and precision");
     }
     op->tuned[pi] = variant;
     if (chosen) *chosen = op->tuned[pi];

@@ -35,6 +35,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 
 #include "chain_dev.hpp"
 #include "internal.hpp"
@@ -126,7 +127,26 @@ void build_chain_split(polfed_op* op) {
   op->split_Lb = Lb;
   op->split_nseg = (int64_t)(rec.size() / kChainRecWords);
   // packed LDS images: [neighbour positions | diagonal of the low part (T) |
-  // low-part list]
+  // low-part list], indexed by the low part; then the same three tables
+  // indexed by position p in the low-part list (entry p describes lolist[p]),
+  // so that a row's tables are one lookup away from its list position
+  for (int w = 0; w < 2; ++w) {
+    const int tb = w == 0 ? 8 : 4;
+    std::vector<unsigned char> blob(chain_blob_bytes(nlo, tb), 0);
+    unsigned char* p = blob.data();
+    for (int q = 0; q < nlo; ++q) std::memcpy(p + 16 * q, &npos[(size_t)lolist[q] * 16], 16);
+    p += 16 * (size_t)nlo;
+    for (int q = 0; q < nlo; ++q) {
+      if (tb == 8) {
+        std::memcpy(p + 8 * q, &dlo[lolist[q]], 8);
+      } else {
+        const float f = (float)dlo[lolist[q]];
+        std::memcpy(p + 4 * q, &f, 4);
+      }
+    }
+    std::memcpy(p + (size_t)tb * nlo, lolist.data(), 2 * (size_t)nlo);
+    upload(w == 0 ? op->d_blobl64 : op->d_blobl32, blob.data(), blob.size(), s);
+  }
   for (int w = 0; w < 2; ++w) {
     const int tb = w == 0 ? 8 : 4;
     std::vector<unsigned char> blob(chain_blob_bytes(nlo, tb), 0);
@@ -157,6 +177,9 @@ void build_chain_split(polfed_op* op) {
     }
     seg_of_hi[nhi] = sidx;
   }
+  op->split_hi_off = hi_off;
+  op->split_seg_of_hi = seg_of_hi;
+  op->wtiles.clear();
   const int KT = chain_tile_bits(L);
   for (int v = 0; v < 3; ++v) {
     auto& T = op->tiles[v];
@@ -641,6 +664,346 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
   }
 }
 
+// Staged-tile kernel.  A tile is the set of rows whose state bits outside
+// [0, Lb + KT) (and, for a wrapped tile, outside the top bit L - 1) are
+// fixed: 2^WR runs of 2^KT consecutive high parts, each run a contiguous
+// range of rows.  The workgroup copies the tile's rows of b_{i+1}, and the
+// records of its segments, into LDS with direct-to-LDS buffer loads (one
+// 16-byte load per lane fills 1 KB of LDS, no registers involved), so that
+//   - the low-part hops, the joining bond and the KT - 1 bonds among the
+//     tile's high bits read LDS;
+//   - in a wrapped tile the periodic bond (L - 1, 0) reads LDS too: its
+//     target differs in the top bit, so it lies in the tile's other run;
+//   - only the bonds between the tile's high bits and the fixed middle
+//     bits gather from global memory, at wave-uniform row offsets;
+//   - a segment's record and its rows' low-part tables (in list order) are
+//     LDS reads, so the global gathers of a segment start after two short
+//     LDS round trips instead of a scalar load from global memory.
+// With DB the next tile is staged into a second LDS buffer while the current
+// one is processed.
+template <typename T, int L, int KT, int WR, int DB, int NT>
+__global__ __launch_bounds__(NT) void k_chain_wt(
+    ChainSplitDev c, T sigma, T tau, T a, const T* __restrict__ v,
+    const T* __restrict__ b1, const T* b2, T* out, int nxcd, int ntiles, int buf_rows,
+    int rec_slots, const int32_t* __restrict__ recs, const int32_t* __restrict__ tiles) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = L - Lb - 1;  // bonds inside the high part
+  constexpr int NHL = KT - 1;     // of which inside the tile: b < NHL
+  constexpr int NL = Lb - 1;
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr int CH = 1024 / (int)sizeof(T);  // rows per staging load of a wave
+  constexpr int RB = kChainRecWords * 4;      // bytes per segment record
+  constexpr int NW = NT / 64;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  using lds_ptr = __attribute__((address_space(3))) void*;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  {
+    const u4* src = reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blobl64 : c.blobl32);
+    u4* dst = reinterpret_cast<u4*>(smem);
+    for (int i = threadIdx.x; i < CHUNKS; i += NT) dst[i] = src[i];
+  }
+  // list-ordered tables: entry p describes the p-th low part of the list
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const T* s_dlo = reinterpret_cast<const T*>(smem + 16 * NLO);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(s_dlo + NLO);
+  // per buffer: buf_rows rows of b_{i+1}, then rec_slots segment records
+  const size_t buf_bytes = (size_t)buf_rows * TB + (size_t)rec_slots * RB;
+  unsigned char* const s_b0 = smem + BLOB;
+  unsigned char* const s_b1 = s_b0 + (DB ? buf_bytes : 0);
+
+  const int xcd = blockIdx.x % nxcd;
+  const int wg = blockIdx.x / nxcd, nwg = gridDim.x / nxcd;
+  const int t_begin = (int)((int64_t)ntiles * xcd / nxcd);
+  const int t_end = (int)((int64_t)ntiles * (xcd + 1) / nxcd);
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t vbytes = (uint32_t)(c.D * TB);
+  const rsrc_t rb1 = make_rsrc(b1, vbytes), rv = make_rsrc(v, v ? vbytes : 0),
+               rb2 = make_rsrc(b2, b2 ? vbytes : 0), rout = make_rsrc(out, vbytes),
+               rrec = make_rsrc(recs, (uint32_t)(c.nseg * RB));
+  // the tile's runs of rows and of segment records into a buffer, in chunks
+  // of 1 KB dealt round robin to the waves; a run's last chunk spills into
+  // the run's padding
+  auto stage = [&](int t, unsigned char* buf) {
+    const int32_t* tt = tiles + 8 * t;
+    int rbase = 0, sbase = 0;
+#pragma unroll
+    for (int r = 0; r < (1 << WR); ++r) {
+      const int row0 = tt[4 * r], rows = tt[4 * r + 1];
+      const int seg0 = tt[4 * r + 2], nseg = tt[4 * r + 3];
+      const int nch = (rows + CH - 1) / CH;
+      for (int ch = wave; ch < nch; ch += NW)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rb1, (lds_ptr)(buf + (size_t)(rbase + ch * CH) * TB), 16,
+            (uint32_t)(ch * CH) * TB + 16u * lane, (uint32_t)row0 * TB, 0, 0);
+      const int nrc = (nseg + 7) / 8;
+      for (int ch = wave; ch < nrc; ch += NW)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rrec, (lds_ptr)(buf + (size_t)buf_rows * TB + (size_t)(sbase + 8 * ch) * RB), 16,
+            (uint32_t)(8 * ch * RB) + 16u * lane, (uint32_t)seg0 * RB, 0, 0);
+      rbase += nch * CH;
+      sbase += nrc * 8;
+    }
+  };
+  int t = t_begin + wg;
+  if (DB && t < t_end) stage(t, s_b0);
+  for (int it = 0; t < t_end; t += nwg, ++it) {
+    unsigned char* const cb = (DB && (it & 1)) ? s_b1 : s_b0;
+    if (DB) {
+      // this tile was requested one iteration ago; once every wave has it
+      // (and is done with the other buffer), stage the next tile
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (t + nwg < t_end) stage(t + nwg, (it & 1) ? s_b0 : s_b1);
+    } else {
+      __syncthreads();  // the previous tile's LDS reads are done
+      stage(t, s_b0);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    const T* const cur_buf = reinterpret_cast<const T*>(cb);
+    const int32_t* const s_rec = reinterpret_cast<const int32_t*>(cb + (size_t)buf_rows * TB);
+    const int32_t* tt = tiles + 8 * t;
+    const int r0row = tt[0], r0nseg = tt[3];
+    const int r1row = WR ? tt[4] : 0, r1nseg = WR ? tt[7] : 0;
+    const int base1 = WR ? ((tt[1] + CH - 1) / CH) * CH : 0;
+    const int sbase1 = ((r0nseg + 7) / 8) * 8;
+    const int nsegs = r0nseg + r1nseg;
+    for (int j = wave; j < nsegs; j += NW) {
+      const bool in1 = WR && j >= r0nseg;
+      // LDS index = global row + shift (own run), + pshift (the other run)
+      const int shift = in1 ? base1 - r1row : -r0row;
+      const int pshift = in1 ? -r0row : base1 - r1row;
+      const SegRec<NH> cur = load_rec<NH>(s_rec + (in1 ? sbase1 + j - r0nseg : j) * kChainRecWords);
+      const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+      const int st = (cur.flags >> 12) & 1023;
+      const int blk0 = cur.row0 - st;
+      const int lrow0 = cur.row0 + shift, lblk0 = blk0 + shift;
+      const uint32_t so_row = (uint32_t)cur.row0 * TB;
+      const uint32_t pair_off = (uint32_t)(2 * lane) * TB;
+      // global gathers first: high-part hops at uniform offsets, the
+      // periodic bond of an unwrapped tile, the streamed v and b_{i+2}
+      T g_hi[NH - NHL > 0 ? NH - NHL : 1][2], vv[2], bt[2];
+#pragma unroll
+      for (int b = NHL; b < NH; ++b) {
+        if (cur.dh[b] != 0)
+          bload2<T>(rb1, pair_off, (uint32_t)(cur.row0 + cur.dh[b]) * TB, g_hi[b - NHL][0],
+                    g_hi[b - NHL][1]);
+        else
+          g_hi[b - NHL][0] = g_hi[b - NHL][1] = T(0);
+      }
+      if (v)
+        bload2<T, kAuxNT>(rv, pair_off, so_row, vv[0], vv[1]);
+      else
+        vv[0] = vv[1] = T(0);
+      if (b2)
+        bload2<T, kAuxNT>(rb2, pair_off, so_row, bt[0], bt[1]);
+      else
+        bt[0] = bt[1] = T(0);
+      // the lane's rows 2 lane and 2 lane + 1 (clamped into the segment)
+      int jj[2], lo[2];
+      u4 np[2];
+      T dl[2];
+      bool act_j[2], act_p[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        jj[i] = min(2 * lane + i, cur.len - 1);
+        const int q = cur.lidx + jj[i];
+        lo[i] = s_lo[q];
+        np[i] = s_np[q];
+        dl[i] = s_dlo[q];
+      }
+      T g_p[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int l = lo[i];
+        act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
+        act_p[i] = c.periodic && ((l & 1) != hitop);
+        if (!WR) {
+          const int rp = (int)((np[i][2] >> 16) & 255u);
+          g_p[i] = act_p[i] ? bload<T>(rb1, (uint32_t)(blk0 + cur.d_pbc + rp) * TB, 0) : T(0);
+        }
+      }
+      // every LDS operand of both rows is read before any is summed (an
+      // idle in-tile high bond reads the row itself and is masked; the
+      // joining and periodic reads are clamped into the buffer and masked)
+      T bo[2], nb[2][NL > 0 ? NL : 1], th[2][NHL > 0 ? NHL : 1], tj[2], tp[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int lr = lrow0 + jj[i];
+        bo[i] = cur_buf[lr];
+#pragma unroll
+        for (int b = 0; b < NL; ++b)
+          nb[i][b] = cur_buf[lblk0 + (int)((np[i][b >> 2] >> (8 * (b & 3))) & 255u)];
+#pragma unroll
+        for (int b = 0; b < NHL; ++b) th[i][b] = cur_buf[lr + cur.dh[b]];
+        const int rj = (int)((np[i][2] >> 8) & 255u);
+        tj[i] = cur_buf[min(lblk0 + cur.d_join + rj, buf_rows - 1)];
+        if (WR) {
+          const int rp = (int)((np[i][2] >> 16) & 255u);
+          tp[i] = cur_buf[min(blk0 + cur.d_pbc + rp + pshift, buf_rows - 1)];
+        }
+      }
+      T o[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int l = lo[i];
+        T hop = 0;
+#pragma unroll
+        for (int b = 0; b < NL; ++b) hop += nb[i][b];
+        const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+        hop -= (T)(NL - __popc(xlo)) * bo[i];
+#pragma unroll
+        for (int b = 0; b < NHL; ++b) hop += cur.dh[b] != 0 ? th[i][b] : T(0);
+#pragma unroll
+        for (int b = NHL; b < NH; ++b) hop += g_hi[b - NHL][i];
+        hop += act_j[i] ? tj[i] : T(0);
+        if (WR) g_p[i] = act_p[i] ? tp[i] : T(0);
+        const int lo_top = (l >> (Lb - 1)) & 1, lo0 = l & 1;
+        const int n11x = (lo_top & hi0) + (c.periodic ? (hitop & lo0) : 0);
+        const T dg = dl[i] + (T)cur.dhi + vzz * (T)n11x;
+        const T acc = dg * bo[i] + t_in * hop + (act_p[i] ? t_pb * g_p[i] : T(0));
+        o[i] = sigma * acc + tau * bo[i] - bt[i];
+        if (v) o[i] += a * vv[i];
+      }
+      const int r0 = 2 * lane;
+      if (r0 + 1 < cur.len)
+        bstore2<kAuxNT>(o[0], o[1], rout, pair_off, so_row);
+      else if (r0 < cur.len)
+        bstore<kAuxNT>(o[0], rout, pair_off, so_row);
+    }
+  }
+}
+
+// Staged-tile configurations: tile bits (below the largest tile bits of the
+// chain), wrap, double buffer, threads per workgroup.
+struct WtConf {
+  int dkt, wrap, db, nt;
+};
+constexpr WtConf kWtConf[] = {
+    {0, 1, 0, 1024},  // 6: largest wrapped tile, one buffer, 16 waves
+    {1, 1, 1, 512},   // 7: half-size wrapped tile, two buffers, 8 waves
+    {1, 1, 0, 512},   // 8: half-size wrapped tile, one buffer, 8 waves
+    {0, 1, 1, 1024},  // 9: largest wrapped tile, two buffers (FP32 fits)
+};
+constexpr int kWtFirst = 6, kWtCount = (int)(sizeof(kWtConf) / sizeof(kWtConf[0]));
+
+// Tile bits of the staged-tile kernel's largest tile at chain length L.
+constexpr int chain_wt_bits(int L) {
+  const int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  const int Lh = L - Lb;
+  const int kt = Lh - 10 < 4 ? Lh - 10 : 4;
+  return (L >= 20 && kt >= 2) ? kt : 0;
+}
+
+static const polfed_op::WTiles* wt_tables(const polfed_op* op, int kt, int wrap) {
+  const int key = kt * 2 + wrap;
+  auto it = op->wtiles.find(key);
+  if (it != op->wtiles.end()) return it->second.n > 0 ? &it->second : nullptr;
+  polfed_op::WTiles& W = op->wtiles[key];
+  const int Lh = op->L - op->split_Lb;
+  if (kt < 1 || Lh - kt - wrap < 3 || op->split_hi_off.empty()) return nullptr;
+  const auto& ho = op->split_hi_off;
+  const auto& so = op->split_seg_of_hi;
+  const int64_t nt = (int64_t)1 << (Lh - kt - wrap);
+  TallyScope untallied(nullptr);  // the table lives as long as the operator
+  std::vector<int32_t> tab;
+  for (int64_t t = 0; t < nt; ++t) {
+    int32_t e[8] = {0};
+    int rows_tot = 0, bufr[2] = {0, 0}, slots = 0;
+    for (int r = 0; r <= wrap; ++r) {
+      const int64_t h0 = ((int64_t)r << (Lh - 1)) | (t << kt), h1 = h0 + ((int64_t)1 << kt);
+      e[4 * r] = ho[h0];
+      e[4 * r + 1] = ho[h1] - ho[h0];
+      e[4 * r + 2] = so[h0];
+      e[4 * r + 3] = so[h1] - so[h0];
+      rows_tot += e[4 * r + 1];
+      slots += ((e[4 * r + 3] + 7) / 8) * 8;
+      for (int p = 0; p < 2; ++p) {
+        const int ch = p == 0 ? 128 : 256;
+        bufr[p] += ((e[4 * r + 1] + ch - 1) / ch) * ch;
+      }
+    }
+    if (rows_tot == 0) continue;
+    tab.insert(tab.end(), e, e + 8);
+    for (int p = 0; p < 2; ++p) W.buf_rows[p] = std::max(W.buf_rows[p], bufr[p]);
+    W.rec_slots = std::max(W.rec_slots, slots);
+  }
+  W.kt = kt;
+  W.wrap = wrap;
+  W.n = (int)(tab.size() / 8);
+  upload(W.d, tab.data(), tab.size(), op->ctx->stream);
+  HIPC(hipStreamSynchronize(op->ctx->stream));
+  return W.n > 0 ? &W : nullptr;
+}
+
+bool chain_wt_exists(const polfed_op* op, int var, bool fp32) {
+  if (op->model != Model::Chain || op->split_nseg <= 0) return false;
+  if (var < kWtFirst || var >= kWtFirst + kWtCount) return false;
+  const WtConf C = kWtConf[var - kWtFirst];
+  const int KT = chain_wt_bits(op->L) - C.dkt;
+  if (chain_wt_bits(op->L) == 0 || KT < 1) return false;
+  const polfed_op::WTiles* W = wt_tables(op, KT, C.wrap);
+  if (!W) return false;
+  const size_t tb = fp32 ? 4 : 8;
+  const size_t shm = chain_blob_bytes(1 << op->split_Lb, (int)tb) +
+                     (size_t)(C.db ? 2 : 1) * ((size_t)W->buf_rows[fp32 ? 1 : 0] * tb +
+                                               (size_t)W->rec_slots * kChainRecWords * 4);
+  return shm <= kLdsPerCU;
+}
+
+template <typename T, int L, int KT, int WR, int DB, int NT>
+static bool launch_wt(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v,
+                      const T* b1, const T* b2, T* out) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  const polfed_op::WTiles* W = wt_tables(op, KT, WR);
+  if (!W) return false;
+  const int buf_rows = W->buf_rows[sizeof(T) == 8 ? 0 : 1];
+  const size_t shm = chain_blob_bytes(1 << Lb, (int)sizeof(T)) +
+                     (size_t)(DB ? 2 : 1) * ((size_t)buf_rows * sizeof(T) +
+                                              (size_t)W->rec_slots * kChainRecWords * 4);
+  if (shm > kLdsPerCU) return false;
+  const int per_cu = std::max(1, std::min((int)(kLdsPerCU / shm), 2048 / NT));
+  ChainSplitDev c = op->chain_split();
+  int64_t grid = std::min<int64_t>(W->n, (int64_t)op->ctx->n_cu * per_cu);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  hipLaunchKernelGGL((k_chain_wt<T, L, KT, WR, DB, NT>), dim3((unsigned)grid), dim3(NT), shm, s,
+                     c, sigma, tau, a, v, b1, b2, out, nxcd, W->n, buf_rows, W->rec_slots,
+                     c.rec, W->d.as<int32_t>());
+  HIPC(hipGetLastError());
+  return true;
+}
+
+template <typename T, int L, int I>
+static bool launch_wt_conf(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v,
+                           const T* b1, const T* b2, T* out) {
+  constexpr WtConf C = kWtConf[I];
+  constexpr int KT = chain_wt_bits(L) - C.dkt;
+  if constexpr (chain_wt_bits(L) == 0 || KT < 1) {
+    return false;
+  } else {
+    return launch_wt<T, L, KT, C.wrap, C.db, C.nt>(s, op, sigma, tau, a, v, b1, b2, out);
+  }
+}
+
+template <typename T, int L, int... I>
+static bool launch_wt_any(hipStream_t s, const polfed_op* op, int i, T sigma, T tau, T a,
+                          const T* v, const T* b1, const T* b2, T* out,
+                          std::integer_sequence<int, I...>) {
+  bool ok = false;
+  ((i == I ? (ok = launch_wt_conf<T, L, I>(s, op, sigma, tau, a, v, b1, b2, out), 0) : 0), ...);
+  return ok;
+}
+
 // Launch shape: persistent blocks per CU and the XCD-contiguous mapping can
 // be overridden through POLFED_CHAIN_BPC and POLFED_CHAIN_XCD (0 = off).
 
@@ -704,6 +1067,9 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
     launch_split<T, L, 2>(s, op, sigma, tau, a, v, b1, b2, out);
     return true;
   }
+  if (var >= kWtFirst && var < kWtFirst + kWtCount)
+    return launch_wt_any<T, L>(s, op, var - kWtFirst, sigma, tau, a, v, b1, b2, out,
+                               std::make_integer_sequence<int, kWtCount>{});
   if constexpr (KT >= 2) {
     constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
     if (var != 1 && var != 2 && var != 5) return false;
@@ -751,7 +1117,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
   HIPC(hipStreamSynchronize(s));  // the operator's tables and the scratch vectors
   int best = 0;
   float best_us = 1e30f;
-  for (int var = 0; var < 6; ++var) {
+  for (int var = 0; var < kWtFirst + kWtCount; ++var) {
     const bool ok = launch_variant<T, L>(s, op, var, T(0.1), T(0), T(0), bv.as<T>(),
                                          bb1.as<T>(), bb2.as<T>(), bb2.as<T>());
     if (!ok) continue;
@@ -812,6 +1178,8 @@ polfed::ChainSplitDev polfed_op::chain_split() const {
   c.vzz = vzz;
   c.blob64 = d_blob64.get();
   c.blob32 = d_blob32.get();
+  c.blobl64 = d_blobl64.get();
+  c.blobl32 = d_blobl32.get();
   c.rec = d_rec.as<int32_t>();
   c.nseg = split_nseg;
   return c;

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <stdexcept>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -223,6 +224,8 @@ struct ChainSplitDev {
   double t_in, t_pb, vzz;
   const void* blob64;  // packed LDS image, FP64 diagonal
   const void* blob32;  // same with FP32 diagonal
+  const void* blobl64;  // the same tables in low-part list order (FP64)
+  const void* blobl32;  // (FP32)
   const int32_t* rec;
   int64_t nseg;
 };
@@ -337,12 +340,26 @@ struct polfed_op {
   // split layout of the chain kernel
   int split_Lb = 0;
   int64_t split_nseg = 0;
-  polfed::DevBuf d_blob64, d_blob32, d_rec;
+  polfed::DevBuf d_blob64, d_blob32, d_blobl64, d_blobl32, d_rec;
   // tile-kernel tables for three tile sizes (bits KT, KT - 1, KT - 2)
   struct Tiles {
     int bits = 0, max_rows = 0, n = 0;
     polfed::DevBuf d;  // [n][4]: first row, rows, first segment, segments
   } tiles[3];
+  // host copies of the split layout's block offsets and first segments
+  // (2^(L - Lb) + 1 entries each), for building more tile tables
+  std::vector<int32_t> split_hi_off, split_seg_of_hi;
+  // tables of the staged-tile kernel, per (tile bits, wrap): the non-empty
+  // tiles, each [first row, rows, first segment, segments] for its low run
+  // and (wrapped tiles) its top run; LDS rows of the largest tile with every
+  // run rounded up to whole staging chunks of 128 (FP64) and 256 (FP32) rows
+  struct WTiles {
+    int kt = 0, wrap = 0, n = 0;
+    int buf_rows[2] = {0, 0};
+    int rec_slots = 0;  // segment records of the largest tile, runs padded to 8
+    polfed::DevBuf d;
+  };
+  mutable std::map<int, WTiles> wtiles;
   // step-kernel variant picked by timing on first use, per precision
   // (-1: not tuned yet, 0: segment kernel, 1 + i: tile kernel tiles[i])
   mutable int tuned[2] = {-1, -1};
@@ -417,6 +434,10 @@ template <typename T>
 bool chain_split_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
                       const T* v, const T* b1, const T* b2, T* out);
 void build_chain_split(polfed_op* op);
+// Whether staged-tile variant var of the chain step exists for op at this
+// precision (chain length, tile table and LDS footprint).
+bool chain_wt_exists(const polfed_op* op, int var, bool fp32);
+constexpr int kChainVariants = 10;  // variants 0 .. 9
 // Fused Clenshaw step of the quantum random energy model (hypercube stencil).
 template <typename T>
 void qrem_step(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, const T* v, const T* b1,

@@ -181,9 +181,10 @@ struct SolveRun {
   void setup(polfed_ctx* c, const polfed_op* o, const polfed_params& prm, const double* x0,
              double* ev, double* vecs, double* res, int* nf);
   // Largest device bytes a solve of this operator holds when its Krylov
-  // space stays within the expected size and n_want does not grow: basis,
-  // work and filter vectors, and the larger of the extraction (FP64) and
-  // the FP32 refinement with its FP64 fallback.
+  // space stays within the expected size and n_want does not grow: the
+  // bounds Lanczos (unless the bounds are given), then the basis, work and
+  // filter vectors, and the larger of the extraction (FP64) and the FP32
+  // refinement with its FP64 fallback.
   static size_t footprint(const polfed_op* op, const polfed_params& p);
   // the same for m basis columns and n wanted pairs
   static size_t bytes_at(int64_t D, int m, int n, bool fp32);

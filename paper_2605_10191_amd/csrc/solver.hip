@@ -520,7 +520,15 @@ size_t SolveRun::footprint(const polfed_op* op, const polfed_params& p) {
   const int g = (f32 ? 2 : 1) * buffer_size(n_ev);
   const int n_want = (int)std::min<int64_t>(op->D, n_ev + g);
   const int M = (int)std::min<int64_t>(op->D, expected_krylov_dim(n_want, 1, p.eta > 0 ? p.eta : 1.5));
-  return bytes_at(op->D, M, n_want, f32);
+  size_t b = bytes_at(op->D, M, n_want, f32);
+  if (!(p.E_max > p.E_min)) {
+    // the bounds Lanczos before it: its basis of up to 300 steps, w and the
+    // two recurrence buffers of its work space
+    const size_t D = (size_t)std::max<int64_t>(op->D, 1);
+    const size_t cap = (size_t)std::min<int64_t>(300, op->D);
+    b = std::max(b, (cap + 2 + 3) * D * 8 + (cap + 2) * 8 * 3 + 8192 * 8 * 2);
+  }
+  return b;
 }
 
 bool SolveRun::reserve(size_t bytes) {
@@ -919,6 +927,7 @@ polfed_status solve(polfed_ctx* ctx, const polfed_op* op, const polfed_params& p
 
 void* ctx_scratch(polfed_ctx* ctx, int slot, size_t bytes) {
   DevBuf& b = ctx->ws[slot];
+  TallyScope untallied(nullptr);  // held by the context
   if (b.bytes() < bytes) b.alloc(bytes);
   return b.get();
 }

@@ -208,22 +208,26 @@ def test_large_chain_sampled_rows(pk, ctx):
 @pytest.mark.parametrize("L,periodic", [(22, True), (23, True), (24, True), (23, False),
                                         (24, False)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", list(range(10)))
 def test_long_chain_clenshaw_step_all_rows(pk, ctx, L, periodic, prec, variant):
     """Full-size Clenshaw steps of long chains, periodic and open, with each
     step kernel (the segment kernel; the tile kernels with 8/4 (L = 22),
     16/8/4 (L = 23) and 32/16/8 (L = 24) high parts per tile; the paired-row
-    and half-segment kernels): every row of a v + 2 H~ b1 - b2 against the
+    and half-segment kernels; the staged-tile kernels whose tiles wrap
+    around the periodic bond): every row of a v + 2 H~ b1 - b2 against the
     oracle's CSR of eq. (xxz)."""
     say(f"L={L} periodic={periodic} clenshaw step {prec} variant {variant}")
     N = L // 2
     h, H, _ = xxz_case(L, N, 3.0, 1, periodic)
     op = pk.Operator.xxz(ctx, L, N, 1.0, 1.0, h, periodic)
+    p = pk.FP64 if prec == "fp64" else pk.FP32
     if variant == 5 and L == 22:
         # no tile of a quarter size at L = 22 (the largest tile has 2 bits)
         with pytest.raises(pk.PolfedError):
-            op.set_kernel(pk.FP64 if prec == "fp64" else pk.FP32, variant)
+            op.set_kernel(p, variant)
         return
+    if variant == 9 and not _has_variant(pk, op, p, variant):
+        return  # two buffers of the largest tile do not fit the LDS
     assert op.set_kernel(pk.FP64 if prec == "fp64" else pk.FP32, variant) == variant
     rng = np.random.default_rng(5)
     v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
@@ -242,7 +246,7 @@ def test_long_chain_clenshaw_step_all_rows(pk, ctx, L, periodic, prec, variant):
 
 @pytest.mark.parametrize("L,N,periodic", [(24, 12, True), (26, 13, True), (25, 12, False)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", list(range(10)))
 def test_tv_long_chain_clenshaw_step(pk, ctx, L, N, periodic, prec, variant):
     """Full-size t-V steps with every step kernel.  N = 12 makes the periodic
     hop's Jordan-Wigner sign -1, N = 13 (the L = 26 configuration) +1.  Every
@@ -254,6 +258,8 @@ def test_tv_long_chain_clenshaw_step(pk, ctx, L, N, periodic, prec, variant):
     eps = wl.tv_onsite(L, 2)
     op = pk.Operator.tv(ctx, L, N, 1.0, 1.0, eps, periodic)
     p = pk.FP64 if prec == "fp64" else pk.FP32
+    if variant == 9 and not _has_variant(pk, op, p, variant):
+        return  # two buffers of the largest tile do not fit the LDS
     assert op.set_kernel(p, variant) == variant
     rng = np.random.default_rng(6)
     v, b1, b2 = (rng.standard_normal(op.D) for _ in range(3))
@@ -276,6 +282,16 @@ def test_tv_long_chain_clenshaw_step(pk, ctx, L, N, periodic, prec, variant):
     Hb = models.tv_rows_apply(L, N, 1.0, 1.0, eps, periodic, st, rows, b1)
     ref = a_i * v[rows] + 2.0 * (Hb - E_c * b1[rows]) / dE - b2[rows]
     assert np.max(np.abs(got[rows] - ref)) <= tol * np.max(np.abs(ref))
+
+
+def _has_variant(pk, op, prec, variant):
+    """Whether the library offers this step-kernel variant for op."""
+    try:
+        op.set_kernel(prec, variant)
+    except pk.PolfedError as e:
+        assert "staged-tile" in str(e)
+        return False
+    return True
 
 
 @functools.lru_cache(maxsize=2)
