@@ -336,6 +336,32 @@ polfed_status polfed_lanczos_step(polfed_ctx* ctx, const polfed_op* op,
                                   double E_c, double dE, const double* a,
                                   int K, double* V, int k, double* alpha,
                                   double* beta, int precision);
+/* Extraction (Sec. 4.3): the Ritz vectors u_j = V t_j of the selected
+ * eigenvectors t_j of the Lanczos matrix, then Rayleigh-Ritz with H on their
+ * span (the reading of Sec. 4.3's per-vector energies for a subspace):
+ * G = U^T H U (symmetrized), G = Z diag(E) Z^T, U2 = U Z, and the residuals
+ * ||H u2_j - E_j u2_j||.  V: device D x m column-major (ld D), orthonormal
+ * columns; T: device m x n column-major (ld m), orthonormal columns.  E[n]
+ * ascending, U2 (D x n, ld D), resid[n]: device outputs, caller-owned.  The
+ * products run on the matrix cores (MFMA), the n x n eigenproblem on the
+ * host.  Synchronizes. */
+polfed_status polfed_extract(polfed_ctx* ctx, const polfed_op* op, const double* V, int m,
+                             const double* T, int n, double* E, double* U2, double* resid);
+/* The products of the extraction and of block Gram-Schmidt, exposed for
+ * parity tests and profiling (device column-major FP64 arrays with leading
+ * dimensions; D >= 0, sizes >= 0):
+ *   polfed_gemm_nn:  C (D x n) = A (D x m) B (m x n), or C -= A B when
+ *                    subtract is nonzero;
+ *   polfed_gemm_tn:  G (n1 x n2) = A^T B with A (D x n1), B (D x n2); the
+ *                    sum over D is split over workgroups and the partial
+ *                    results are added in a fixed order (deterministic).
+ * Asynchronous on the context's stream. */
+polfed_status polfed_gemm_nn(polfed_ctx* ctx, int64_t D, int m, int n, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                             int subtract);
+polfed_status polfed_gemm_tn(polfed_ctx* ctx, int64_t D, int n1, int n2, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double* G, int64_t ldg);
+
 /* One block Lanczos step on the filtered operator (Sec. 2.2, eq.
  * block_lanczos_reocurrence, with the filter of Sec. 4.3): W = P(H~) V_j
  * for the current block V_j = columns k..k+s-1 of V (one multi-column

@@ -121,6 +121,9 @@ SIGNATURES = {
                                    _P, _P, _P, _I, _I],
     "polfed_bounds": [_P, _P, _P, _D, _I, _DP, _DP],
     "polfed_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _P, _P, _I],
+    "polfed_extract": [_P, _P, _P, _I, _P, _I, _P, _P, _P],
+    "polfed_gemm_nn": [_P, _I64, _I, _I, _P, _I64, _P, _I64, _P, _I64, _I],
+    "polfed_gemm_tn": [_P, _I64, _I, _I, _P, _I64, _P, _I64, _P, _I64],
     "polfed_kpm_moments": [_P, _P, _D, _D, _I, _I, _P, ctypes.c_uint64, _DP],
     "polfed_kpm_density": [_DP, _I, _DP, _I, _DP],
     "polfed_block_lanczos_step": [_P, _P, _D, _D, _DP, _I, _P, _I, _I, _P, _P, _I],
@@ -515,6 +518,40 @@ def lanczos_step(op: Operator, E_c, dE, a, V, k, alpha, beta, precision=FP64):
     _check(_lib.polfed_lanczos_step(op.ctx.handle, op.handle, E_c, dE, _dptr(a),
                                     len(a) - 1, _ptr(V), int(k), _ptr(alpha),
                                     _ptr(beta), precision))
+
+
+def extract(op: Operator, V, T):
+    """Ritz vectors u_j = V t_j and Rayleigh-Ritz with H on their span.
+    V: (m, D) device tensor (rows = basis vectors), T: (n, m) device tensor
+    (rows = the chosen eigenvectors of the Lanczos matrix).  Returns E (n,
+    ascending), U2 ((n, D), rows = Ritz vectors) and the residual norms."""
+    import torch
+    m, n = V.shape[0], T.shape[0]
+    E = torch.empty(n, dtype=torch.float64, device=V.device)
+    U2 = torch.empty((n, op.D), dtype=torch.float64, device=V.device)
+    R = torch.empty(n, dtype=torch.float64, device=V.device)
+    _check(_lib.polfed_extract(op.ctx.handle, op.handle, _ptr(V), int(m), _ptr(T), int(n),
+                               _ptr(E), _ptr(U2), _ptr(R)))
+    return E, U2, R
+
+
+def gemm_nn(ctx: Context, A, B, C, subtract=False):
+    """C = A B (or C -= A B) for column-major matrices held as transposed
+    row-major tensors: A (m, D), B (n, m), C (n, D)."""
+    m, D = A.shape
+    n = B.shape[0]
+    _check(_lib.polfed_gemm_nn(ctx.handle, int(D), int(m), int(n), _ptr(A), int(max(D, 1)),
+                               _ptr(B), int(max(m, 1)), _ptr(C), int(max(D, 1)),
+                               int(bool(subtract))))
+
+
+def gemm_tn(ctx: Context, A, B, G):
+    """G = A^T B for column-major A (D x n1) and B (D x n2) held as (n1, D)
+    and (n2, D) tensors; G (n1 x n2 column-major) is an (n2, n1) tensor."""
+    n1, D = A.shape
+    n2 = B.shape[0]
+    _check(_lib.polfed_gemm_tn(ctx.handle, int(D), int(n1), int(n2), _ptr(A), int(max(D, 1)),
+                               _ptr(B), int(max(D, 1)), _ptr(G), int(max(n1, 1))))
 
 
 def block_lanczos_step(op: Operator, E_c, dE, a, V, k, s, A, Bn, precision=FP64):

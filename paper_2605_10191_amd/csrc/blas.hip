@@ -209,6 +209,12 @@ static void tall_pass(hipStream_t s, int64_t D, int k, const double* V, double* 
 void dev_block_gs_pass(hipStream_t s, int64_t D, int k, const double* V, double* W, int n,
                        double* partial, int64_t nseg, double* C) {
   if (k <= 0 || D == 0) return;
+  if (n >= kMfmaMinCols) {
+    // a wide block: both products on the matrix cores
+    dev_gemm_tn(s, D, k, n, V, D, W, D, C, k);
+    dev_gemm_nn(s, D, k, n, V, D, C, k, W, D, true);
+    return;
+  }
   for (int j0 = 0; j0 < n; j0 += 8) {
     const int m = std::min(8, n - j0);
     double* Wc = W + (int64_t)j0 * D;

@@ -379,27 +379,7 @@ void SolveRun::advance_block() {
   }
   const double* Blast = band_h.data() + 2 * ss * (m - 1) + ss;
   std::vector<double> th, Zt;
-  DevBuf dA;  // device path: eigenvectors of H_L, k x k col-major
-  if (k >= kDeviceEigMin) {
-    dA.alloc((size_t)k * k * sizeof(double));
-    DevBuf dw((size_t)k * sizeof(double));
-    upload(dA, H.data(), H.size(), st);
-    dev_syevd(st, k, dA.as<double>(), dw.as<double>());
-    th.resize(k);
-    std::vector<double> tail((size_t)k * s);
-    HIPC(hipMemcpyAsync(th.data(), dw.get(), (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
-                        st));
-    // the last s components of every eigenvector
-    HIPC(hipMemcpy2DAsync(tail.data(), (size_t)s * sizeof(double),
-                          dA.as<double>() + (k - s), (size_t)k * sizeof(double),
-                          (size_t)s * sizeof(double), (size_t)k, hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
-    Zt.resize((size_t)s * k);
-    for (int jj = 0; jj < k; ++jj)
-      for (int c = 0; c < s; ++c) Zt[(size_t)c * k + jj] = tail[(size_t)jj * s + c];
-  } else {
-    sym_eig_tail(k, H, s, th, Zt);
-  }
+  sym_eig_tail(k, H, s, th, Zt);
   std::vector<int> order(k);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return th[x] > th[y]; });
@@ -436,15 +416,11 @@ void SolveRun::advance_block() {
   if (conv || k >= M_max || early) {
     const bool full = conv || k >= M_max;
     const int take = full ? nw : lead;
-    if (k >= kDeviceEigMin) {
-      if (conclude(th, dA, take, !full)) return;
-    } else {
-      std::vector<double> thf, Z;
-      sym_eig(k, H, thf, Z);
-      DevBuf dZ;
-      upload(dZ, Z.data(), Z.size(), st);
-      if (conclude(thf, dZ, take, !full)) return;
-    }
+    std::vector<double> thf, Z;
+    sym_eig(k, H, thf, Z);
+    DevBuf dZ;
+    upload(dZ, Z.data(), Z.size(), st);
+    if (conclude(thf, dZ, take, !full)) return;
   }
   next_check = k + check_every;
 }

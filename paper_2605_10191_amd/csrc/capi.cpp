@@ -604,6 +604,56 @@ polfed_status polfed_clenshaw_step(polfed_ctx* ctx, const polfed_op* op, double 
   });
 }
 
+// ------------------------------------------------ extraction and products
+
+polfed_status polfed_extract(polfed_ctx* ctx, const polfed_op* op, const double* V, int m,
+                             const double* T, int n, double* E, double* U2, double* resid) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(op && op->ctx == ctx, "operator missing or from another context");
+    REQUIRE(m >= 1 && n >= 1 && n <= m && m <= op->D, "extract: need 1 <= n <= m <= D");
+    REQUIRE(V && T && E && U2 && resid, "extract: null buffer");
+    DeviceGuard g(ctx->device);
+    CtxLock lk(ctx);
+    extract_pairs(ctx, op, V, m, T, n, E, U2, resid);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_gemm_nn(polfed_ctx* ctx, int64_t D, int m, int n, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                             int subtract) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(D >= 0 && m >= 0 && n >= 0, "gemm: negative size");
+    REQUIRE(lda >= std::max<int64_t>(D, 1) && ldc >= std::max<int64_t>(D, 1) &&
+                ldb >= std::max(m, 1),
+            "gemm: leading dimension too small");
+    REQUIRE(D == 0 || n == 0 || ((m == 0 || (A && B)) && C), "gemm: null buffer");
+    REQUIRE(m > 0 || subtract || D == 0 || n == 0, "gemm: empty inner dimension");
+    DeviceGuard g(ctx->device);
+    CtxLock lk(ctx);
+    dev_gemm_nn(ctx->stream, D, m, n, A, lda, B, ldb, C, ldc, subtract != 0);
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_gemm_tn(polfed_ctx* ctx, int64_t D, int n1, int n2, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double* G, int64_t ldg) {
+  return guarded([&]() -> polfed_status {
+    CTX_OK(ctx);
+    REQUIRE(D >= 0 && n1 >= 0 && n2 >= 0, "gemm: negative size");
+    REQUIRE(lda >= std::max<int64_t>(D, 1) && ldb >= std::max<int64_t>(D, 1) &&
+                ldg >= std::max(n1, 1),
+            "gemm: leading dimension too small");
+    REQUIRE(n1 == 0 || n2 == 0 || (A && B && G), "gemm: null buffer");
+    DeviceGuard g(ctx->device);
+    CtxLock lk(ctx);
+    dev_gemm_tn(ctx->stream, D, n1, n2, A, lda, B, ldb, G, ldg);
+    return POLFED_OK;
+  });
+}
+
 // ----------------------------------------------------- multi-column filter
 
 static void check_batch_args(polfed_ctx* ctx, int B, const polfed_op* const* ops,

@@ -1,16 +1,47 @@
-// Small host eigensolvers for the Lanczos matrix and the Rayleigh-Ritz
+// Host eigensolvers for the Lanczos matrix and the Rayleigh-Ritz
 // projection.  Symmetric tridiagonal: the implicit QL algorithm with
 // Wilkinson-type shifts (Dubrulle, Martin and Wilkinson, Numer. Math. 12,
-// 1968, the procedure known as imtql2).  Dense symmetric:
-// Householder reduction to tridiagonal form (Golub and Van Loan, Sec. 8.3)
-// followed by the tridiagonal solver.  Sizes here are a few hundred at most.
+// 1968, the procedure known as imtql2).  Dense symmetric: Householder
+// reduction to tridiagonal form (Golub and Van Loan, Sec. 8.3) followed by
+// the tridiagonal solver.  Both run in O(n^3); the work on the rows of the
+// eigenvector matrix (and of the matrix being reduced) is shared among the
+// host's threads with OpenMP once n reaches the thousands that thousands of
+// wanted pairs bring (about 3,000 Lanczos vectors for 1,500 pairs).  Each
+// QL sweep first computes its rotations and then applies them row by row,
+// every row in the same order as a rotation-by-rotation update would.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <stdexcept>
 
-#include "internal.hpp"
+#include "eig.hpp"
 
 namespace polfed {
+
+namespace {
+
+// Rows updated per thread below which a loop stays serial.
+constexpr long kParWork = 1L << 16;
+
+// Applies the rotations of one QL sweep, recorded for i = i_hi down to
+// i_lo, to every row of Z: (z_i, z_{i+1}) <- (c z_i - s z_{i+1}, s z_i + c z_{i+1}).
+void apply_sweep(int n, std::vector<double>& Z, int nz, int i_hi, int i_lo,
+                 const std::vector<double>& cs, const std::vector<double>& sn) {
+  if (i_hi < i_lo) return;
+  const long work = (long)nz * (i_hi - i_lo + 1);
+#pragma omp parallel for schedule(static) if (work > kParWork)
+  for (int k = 0; k < nz; ++k) {
+    double* zk = &Z[(size_t)k * n];
+    for (int i = i_hi; i >= i_lo; --i) {
+      const double c = cs[i], s = sn[i];
+      const double zf = zk[i + 1];
+      zk[i + 1] = s * zk[i] + c * zf;
+      zk[i] = c * zk[i] - s * zf;
+    }
+  }
+}
+
+}  // namespace
 
 void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
                  std::vector<double>& Z, int nz) {
@@ -18,6 +49,7 @@ void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
   e.resize(n, 0.0);
   e[n - 1] = 0.0;
   const double eps = 2.220446049250313e-16;
+  std::vector<double> cs(n), sn(n);
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     for (;;) {
@@ -27,7 +59,7 @@ void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
         if (std::fabs(e[m]) <= eps * dd) break;
       }
       if (m == l) break;
-      if (++iter > 200) fail(POLFED_ERR_INVALID, "tridiagonal QL did not converge");
+      if (++iter > 200) throw std::runtime_error("tridiagonal QL did not converge");
       // shift from the leading 2x2 block
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
       double r = std::hypot(g, 1.0);
@@ -52,13 +84,11 @@ void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
         p = s * r;
         d[i + 1] = g + p;
         g = c * r - b;
-        for (int k = 0; k < nz; ++k) {
-          double* zk = &Z[(size_t)k * n];
-          const double zf = zk[i + 1];
-          zk[i + 1] = s * zk[i] + c * zf;
-          zk[i] = c * zk[i] - s * zf;
-        }
+        cs[i] = c;
+        sn[i] = s;
       }
+      // the rotations of this sweep: i = m - 1 down to the last one done
+      apply_sweep(n, Z, nz, m - 1, deflated ? i + 1 : l, cs, sn);
       if (deflated) continue;
       d[l] -= p;
       e[l] = g;
@@ -104,6 +134,8 @@ void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Q, int q
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
     // p = beta * A_sub v
+    const bool par = (long)m * m > kParWork;
+#pragma omp parallel for schedule(static) if (par)
     for (int i = 0; i < m; ++i) {
       double t = 0;
       const double* row = &a[(size_t)(k + 1 + i) * n + (k + 1)];
@@ -114,6 +146,7 @@ void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Q, int q
     for (int i = 0; i < m; ++i) vp += v[i] * p[i];
     const double Kc = 0.5 * beta * vp;
     for (int i = 0; i < m; ++i) q[i] = p[i] - Kc * v[i];
+#pragma omp parallel for schedule(static) if (par)
     for (int i = 0; i < m; ++i) {
       double* row = &a[(size_t)(k + 1 + i) * n + (k + 1)];
       for (int j = 0; j < m; ++j) row[j] -= v[i] * q[j] + q[i] * v[j];
@@ -125,6 +158,7 @@ void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Q, int q
       a[(size_t)k * n + (k + 1 + i)] = 0.0;
     }
     // Q <- Q H on columns k+1..n-1
+#pragma omp parallel for schedule(static) if ((long)nq * m > kParWork)
     for (int r = 0; r < nq; ++r) {
       double* qr = &Q[(size_t)r * n + (k + 1)];
       double t = 0;

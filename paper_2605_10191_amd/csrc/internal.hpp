@@ -468,53 +468,38 @@ void dev_copy_f2d(hipStream_t s, int64_t n, const float* x, double* y);
 void dev_fill(hipStream_t s, int64_t n, double v, double* y);
 void dev_fillf(hipStream_t s, int64_t n, float v, float* y);
 void dev_random(hipStream_t s, int64_t n, uint64_t seed, double* y);
+// Blocks of at least this many columns take the MFMA products.
+constexpr int kMfmaMinCols = 16;
 // One block Gram-Schmidt pass: C = V^T W (k x n, ld k), W -= V C, for the
-// D x n block W against the first k columns of V (ld D); hand-written
-// tall-skinny kernels (V read once per product).  partial: nseg * k * 8.
+// D x n block W against the first k columns of V (ld D): the vector-unit
+// tall-skinny kernels (8 columns per pass, V read once per product) below
+// kMfmaMinCols columns, the MFMA products from there on.
+// partial: nseg * k * 8.
 void dev_block_gs_pass(hipStream_t s, int64_t D, int k, const double* V, double* W, int n,
                        double* partial, int64_t nseg, double* C);
-// Dense products through rocBLAS (dense_la.cpp):
-// C (D x n) = A (D x m, ld lda) * B (m x n, device, col-major, ld m)
-void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A,
-                 int64_t lda, const double* B, double* C, int64_t ldc);
-// G (n x n) = A^T B for A, B of D x n (ld D); G on device, col-major.
-void dev_gemm_tn(hipStream_t s, int64_t D, int n, const double* A,
-                 const double* B, double* partial, int64_t nseg, double* G);
-// C (m x n) = alpha op(A) op(B) + beta C, op = transpose when ta / tb;
-// k is the inner dimension; column-major, device pointers.
-void dev_dgemm(hipStream_t s, bool ta, bool tb, int m, int n, int64_t k, double alpha,
-               const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-               double* C, int64_t ldc);
-// Device eigensolvers through rocSOLVER: symmetric A (n x n col-major, lower
-// triangle read) -> eigenvalues w ascending, eigenvectors over A; symmetric
-// tridiagonal (d[n], e[n-1], both overwritten) -> eigenvalues ascending in d,
-// eigenvectors in C (n x n col-major).  All pointers are device memory.
-void dev_syevd(hipStream_t s, int n, double* A, double* w);
-void dev_stedc(hipStream_t s, int n, double* d, double* e, double* C);
-// Sizes from which the device eigensolvers replace the host ones.
-constexpr int kDeviceEigMin = 256;
+// u_j = V t_j for the n columns of T, Rayleigh-Ritz with H on their span
+// (E ascending, U2 = U Z, residual norms); device inputs and outputs.
+void extract_pairs(polfed_ctx* ctx, const polfed_op* op, const double* V, int m,
+                   const double* T, int n, double* E, double* U2, double* resid);
+// MFMA products of tall matrices (gemm.hip).  C (D x n, ldc) = A (D x m,
+// lda) B (m x n, ldb), or C -= A B with sub.
+void dev_gemm_nn(hipStream_t s, int64_t D, int m, int n, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, double* C, int64_t ldc, bool sub);
+// G (n1 x n2, ldg) = A^T B, A: D x n1 (lda), B: D x n2 (ldb); allocates its
+// split-sum workspace of gemm_tn_workspace(D, n1, n2) bytes.
+void dev_gemm_tn(hipStream_t s, int64_t D, int n1, int n2, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, double* G, int64_t ldg);
+int gemm_tn_splits(int64_t D, int n1, int n2);
+size_t gemm_tn_workspace(int64_t D, int n1, int n2);
 // res[j] = || HU[:, j] - E[j] U[:, j] ||
 void dev_resid(hipStream_t s, int64_t D, int n, const double* U,
                const double* HU, const double* E, double* partial, int64_t nseg,
                double* res);
 
 // ------------------------------------------------------- host eigen ----
-// Symmetric tridiagonal eigenproblem by implicit QL.  d[n] diagonal, e[n-1]
-// off-diagonal.  Accumulates the rotations into the rows of Z (nz x n,
-// row-major) that the caller initializes (identity rows for eigenvectors,
-// the last unit row for last components only).  Eigenvalues ascending, Z
-// columns permuted alike.
-void tridiag_eig(int n, std::vector<double>& d, std::vector<double> e,
-                 std::vector<double>& Z, int nz);
-// Dense symmetric eigenproblem (n x n col-major A): eigenvalues ascending in
-// w, eigenvectors in the columns of Z (col-major).
-void sym_eig(int n, std::vector<double>& A, std::vector<double>& w,
-             std::vector<double>& Z);
-// The eigenvalues (ascending) and only the last r rows of the eigenvector
-// matrix: Ztail is r x n row-major, Ztail[i n + j] = component n - r + i of
-// eigenvector j.
-void sym_eig_tail(int n, const std::vector<double>& A, int r, std::vector<double>& w,
-                  std::vector<double>& Ztail);
+}  // namespace polfed
+#include "eig.hpp"
+namespace polfed {
 
 // ----------------------------------------------------------------- kpm ----
 // mu[0..N) = mean over R vectors of <r|T_n(H~)|r>; rvecs: device D x R, or

@@ -49,11 +49,9 @@ static unsigned grid_for(int64_t n) {
 }
 
 // W <- W R^{-1} with W^T W = R^T R (Cholesky); tmp: D x n scratch.
-static void cholqr(hipStream_t s, int64_t D, int n, DevBuf& W, DevBuf& tmp, int64_t nseg) {
+static void cholqr(hipStream_t s, int64_t D, int n, DevBuf& W, DevBuf& tmp) {
   DevBuf dG((size_t)n * n * sizeof(double));
-  DevBuf part((size_t)nseg * n * sizeof(double) + 8192 * sizeof(double));
-  dev_gemm_tn(s, D, n, W.as<double>(), W.as<double>(), part.as<double>(), nseg,
-              dG.as<double>());
+  dev_gemm_tn(s, D, n, n, W.as<double>(), D, W.as<double>(), D, dG.as<double>(), n);
   std::vector<double> G((size_t)n * n);
   HIPC(hipMemcpyAsync(G.data(), dG.get(), G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
@@ -83,7 +81,7 @@ static void cholqr(hipStream_t s, int64_t D, int n, DevBuf& W, DevBuf& tmp, int6
   }
   DevBuf dRi;
   upload(dRi, Ri.data(), Ri.size(), s);
-  dev_gemm_nn(s, D, n, n, W.as<double>(), D, dRi.as<double>(), tmp.as<double>(), D);
+  dev_gemm_nn(s, D, n, n, W.as<double>(), D, dRi.as<double>(), n, tmp.as<double>(), D, false);
   std::swap(W, tmp);
   HIPC(hipStreamSynchronize(s));
 }
@@ -169,8 +167,8 @@ void refine(SolveRun& run, Extracted& ex, double theta_min) {
     hipLaunchKernelGGL(k_combine, dim3(grid_for(D * na)), dim3(256), 0, s, D, na,
                        Ua.as<double>(), dP.as<double>(), z32.as<float>(), Wa);
     HIPC(hipGetLastError());
-    cholqr(s, D, n, W, tmp, run.ws.nseg);
-    cholqr(s, D, n, W, tmp, run.ws.nseg);
+    cholqr(s, D, n, W, tmp);
+    cholqr(s, D, n, W, tmp);
     for (int j = 0; j < n; ++j)
       op_step<double>(s, op, 1.0, 0.0, 0.0, nullptr, W.as<double>() + (size_t)j * D, nullptr,
                       HW.as<double>() + (size_t)j * D);

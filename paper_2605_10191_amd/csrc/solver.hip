@@ -292,34 +292,26 @@ void rayleigh_ritz(hipStream_t s, int64_t D, int n, const double* U, const doubl
                    int64_t nseg, Extracted& ex) {
   DevBuf dG((size_t)n * n * sizeof(double));
   DevBuf part((size_t)nseg * n * sizeof(double) + 8192 * sizeof(double));
-  dev_gemm_tn(s, D, n, U, HU, part.as<double>(), nseg, dG.as<double>());
+  dev_gemm_tn(s, D, n, n, U, D, HU, D, dG.as<double>(), n);
   std::vector<double> w;
   DevBuf dZ, dE((size_t)n * sizeof(double)), dR((size_t)n * sizeof(double));
-  if (n >= kDeviceEigMin) {
-    // G is symmetric up to rounding; the device solver reads its lower part
-    dev_syevd(s, n, dG.as<double>(), dE.as<double>());
-    w.resize(n);
-    dcopy_async(s, w.data(), dE.as<double>(), (size_t)n, hipMemcpyDeviceToHost);
-    dZ = std::move(dG);
-  } else {
-    std::vector<double> G((size_t)n * n);
-    dcopy_async(s, G.data(), dG.as<double>(), G.size(), hipMemcpyDeviceToHost);
-    HIPC(hipStreamSynchronize(s));
-    // symmetrize: G is symmetric up to rounding
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < i; ++j) {
-        const double m = 0.5 * (G[(size_t)i * n + j] + G[(size_t)j * n + i]);
-        G[(size_t)i * n + j] = G[(size_t)j * n + i] = m;
-      }
-    std::vector<double> Z;
-    sym_eig(n, G, w, Z);
-    dZ.alloc((size_t)n * n * sizeof(double));
-    dcopy_async(s, dZ.as<double>(), Z.data(), Z.size(), hipMemcpyHostToDevice);
-    dcopy_async(s, dE.as<double>(), w.data(), w.size(), hipMemcpyHostToDevice);
-  }
+  std::vector<double> G((size_t)n * n);
+  dcopy_async(s, G.data(), dG.as<double>(), G.size(), hipMemcpyDeviceToHost);
+  HIPC(hipStreamSynchronize(s));
+  // symmetrize: G is symmetric up to rounding
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double m = 0.5 * (G[(size_t)i * n + j] + G[(size_t)j * n + i]);
+      G[(size_t)i * n + j] = G[(size_t)j * n + i] = m;
+    }
+  std::vector<double> Z;
+  sym_eig(n, G, w, Z);
+  dZ = std::move(dG);
+  dcopy_async(s, dZ.as<double>(), Z.data(), Z.size(), hipMemcpyHostToDevice);
+  dcopy_async(s, dE.as<double>(), w.data(), w.size(), hipMemcpyHostToDevice);
   DevBuf U2((size_t)D * n * sizeof(double)), HU2((size_t)D * n * sizeof(double));
-  dev_gemm_nn(s, D, n, n, U, D, dZ.as<double>(), U2.as<double>(), D);
-  dev_gemm_nn(s, D, n, n, HU, D, dZ.as<double>(), HU2.as<double>(), D);
+  dev_gemm_nn(s, D, n, n, U, D, dZ.as<double>(), n, U2.as<double>(), D, false);
+  dev_gemm_nn(s, D, n, n, HU, D, dZ.as<double>(), n, HU2.as<double>(), D, false);
   dev_resid(s, D, n, U2.as<double>(), HU2.as<double>(), dE.as<double>(), part.as<double>(),
             nseg, dR.as<double>());
   ex.res.resize(n);
@@ -368,7 +360,7 @@ Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, 
   const int64_t D = op->D;
   Extracted ex;
   DevBuf U((size_t)D * n * sizeof(double)), HU((size_t)D * n * sizeof(double));
-  dev_gemm_nn(s, D, m, n, B.V.as<double>(), D, dY.as<double>(), U.as<double>(), D);
+  dev_gemm_nn(s, D, m, n, B.V.as<double>(), D, dY.as<double>(), m, U.as<double>(), D, false);
   for (int j = 0; j < n; ++j) apply_H(s, op, U.as<double>() + (size_t)j * D, HU.as<double>() + (size_t)j * D);
   rayleigh_ritz(s, D, n, U.as<double>(), HU.as<double>(), ws.nseg, ex);
   return ex;
@@ -376,6 +368,24 @@ Extracted extract(polfed_ctx* ctx, const polfed_op* op, const Basis& B, Ws& ws, 
 
 
 }  // namespace
+
+void extract_pairs(polfed_ctx* ctx, const polfed_op* op, const double* V, int m,
+                   const double* T, int n, double* E, double* U2, double* resid) {
+  hipStream_t s = ctx->stream;
+  const int64_t D = op->D;
+  const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(256, (D + 8191) / 8192));
+  DevBuf U((size_t)D * n * sizeof(double)), HU((size_t)D * n * sizeof(double));
+  dev_gemm_nn(s, D, m, n, V, D, T, m, U.as<double>(), D, false);
+  for (int j = 0; j < n; ++j)
+    apply_H(s, op, U.as<double>() + (size_t)j * D, HU.as<double>() + (size_t)j * D);
+  Extracted ex;
+  rayleigh_ritz(s, D, n, U.as<double>(), HU.as<double>(), nseg, ex);
+  dcopy_async(s, E, ex.E.data(), (size_t)n, hipMemcpyHostToDevice);
+  dcopy_async(s, resid, ex.res.data(), (size_t)n, hipMemcpyHostToDevice);
+  HIPC(hipMemcpyAsync(U2, ex.U2.get(), (size_t)D * n * sizeof(double), hipMemcpyDeviceToDevice,
+                      s));
+  HIPC(hipStreamSynchronize(s));
+}
 
 // ---------------------------------------------------------- SolveRun ----
 
@@ -505,8 +515,9 @@ size_t SolveRun::bytes_at(int64_t D_, int m, int n, bool f32) {
   // and the fixed graph input (FP64)
   b += vec + (f32 ? 4 * D * 4 : 3 * vec);
   // check and extraction: the tridiagonal eigenvectors (M x M), the chosen
-  // ones (M x n), the projected matrix and its eigenvectors, partial sums
-  b += (M * M + M * N + 2 * N * N + nseg * N + 8192) * 8;
+  // ones (M x n), the projected matrix and its eigenvectors, partial sums,
+  // the split sums of the projection product
+  b += (M * M + M * N + 2 * N * N + nseg * N + 8192) * 8 + gemm_tn_workspace(D_, n, n);
   // FP64: U, HU, U2, HU2.  FP32 refinement: the extracted U2, HU2, four
   // FP32 blocks, five FP64 blocks and the next Rayleigh-Ritz generation;
   // then the two FP64 recurrence buffers of the FP64 fallback.
@@ -741,17 +752,7 @@ void SolveRun::step_tail() {
   if (conv || k >= M_max || early) {
     std::vector<double> thf;
     DevBuf dC;  // eigenvectors of the tridiagonal matrix, k x k col-major
-    if (k >= kDeviceEigMin) {
-      DevBuf dd((size_t)k * sizeof(double)), de((size_t)k * sizeof(double));
-      dC.alloc((size_t)k * k * sizeof(double));
-      dcopy_async(s, dd.as<double>(), al.data(), (size_t)k, hipMemcpyHostToDevice);
-      if (k > 1)
-        dcopy_async(s, de.as<double>(), be.data() + 1, (size_t)(k - 1), hipMemcpyHostToDevice);
-      dev_stedc(s, k, dd.as<double>(), de.as<double>(), dC.as<double>());
-      thf.resize(k);
-      dcopy_async(s, thf.data(), dd.as<double>(), (size_t)k, hipMemcpyDeviceToHost);
-      HIPC(hipStreamSynchronize(s));
-    } else {
+    {
       std::vector<double> Y;
       ritz_full(k, al, be, thf, Y);
       std::vector<double> Yc((size_t)k * k);
