@@ -280,6 +280,22 @@ polfed_status polfed_filter_apply(polfed_ctx* ctx, const polfed_op* op,
                                   double E_c, double dE, const double* a,
                                   int K, const void* v, void* w,
                                   int precision);
+/* The same filter application for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the two recurrence buffers come from a static device
+ * scratch array of 48 MiB that each GPU the library runs on holds until the
+ * process ends, so D is limited to 3,145,728 rows in FP64 and 6,291,456 in
+ * FP32 (larger D gives POLFED_ERR_INVALID).  The operator's step kernel must
+ * already be chosen in this precision (by an earlier step, filter or solve,
+ * or polfed_op_set_kernel), since choosing it times launches on scratch
+ * vectors; otherwise POLFED_ERR_INVALID.  Asynchronous on the context's
+ * stream, no allocation and no synchronization.  Every call on a GPU uses
+ * that GPU's one scratch array: calls that overlap on one GPU (two contexts
+ * or streams, or threads) race and give wrong results. */
+polfed_status polfed_filter_apply_noalloc(polfed_ctx* ctx, const polfed_op* op,
+                                          double E_c, double dE, const double* a,
+                                          int K, const void* v, void* w,
+                                          int precision);
 /* One fused Clenshaw step (the hot kernel), in place on b2:
  *   b2 <- a_i v + 2 H~ b1 - b2            (final == 0)
  *   b2 <- a_i v +   H~ b1 - b2            (final != 0, the closing step)

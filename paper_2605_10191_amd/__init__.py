@@ -114,6 +114,7 @@ SIGNATURES = {
     "polfed_filter_value": [_D, _I, _DP, _I64, _DP],
     "polfed_filter_quotient": [_DP, _I, _D, _DP, _DP],
     "polfed_filter_apply": [_P, _P, _D, _D, _DP, _I, _P, _P, _I],
+    "polfed_filter_apply_noalloc": [_P, _P, _D, _D, _DP, _I, _P, _P, _I],
     "polfed_clenshaw_step": [_P, _P, _D, _D, _D, _P, _P, _P, _I, _I],
     "polfed_filter_apply_batch": [_P, _I, ctypes.POINTER(_P), _DP, _DP,
                                   ctypes.POINTER(_DP), _I32P, _P, _P, _I],
@@ -453,6 +454,15 @@ def filter_apply(op: Operator, E_c, dE, a, v, precision=FP64, w=None):
         w = torch.empty_like(v)
     _check(_lib.polfed_filter_apply(op.ctx.handle, op.handle, E_c, dE,
                                     _dptr(a), K, _ptr(v), _ptr(w), precision))
+    return w
+
+
+def filter_apply_noalloc(op: Operator, E_c, dE, a, v, w, precision=FP64):
+    """filter_apply into the caller's w with the recurrence buffers in the
+    library's static device scratch (no device allocation, asynchronous)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    _check(_lib.polfed_filter_apply_noalloc(op.ctx.handle, op.handle, E_c, dE, _dptr(a),
+                                            len(a) - 1, _ptr(v), _ptr(w), precision))
     return w
 
 

@@ -2,6 +2,7 @@
 // dispatch to the library internals.  No exception crosses this boundary.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "internal.hpp"
 #include "solve_run.hpp"
@@ -148,6 +149,35 @@ int polfed_version(void) { return 10100; }
 
 const char* polfed_last_error(void) { return g_err.c_str(); }
 
+// ----------------------------------------- allocation-free filter scratch
+//
+// The two recurrence buffers of polfed_filter_apply_noalloc live in this
+// file-scope device array.  In host code its name is only a host-side stand-in:
+// the device address is looked up once per device, with that device current,
+// when a context is created on it, and only that address is ever passed to
+// kernels and copies.  Every call on a device shares the device's array.
+constexpr size_t kNoAllocScratchBytes = (size_t)48 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The device address of the scratch array on the current device (device).
+void* resolve_scratch(int device) {
+  REQUIRE(device >= 0 && device < kMaxDevices, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    HIPC(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    REQUIRE(ptr != nullptr, "no device address for the filter scratch array");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out) {
   return guarded([&]() -> polfed_status {
     REQUIRE(out != nullptr, "null output handle");
@@ -169,6 +199,7 @@ polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out) {
     hipDeviceProp_t prop;
     HIPC(hipGetDeviceProperties(&prop, device));
     ctx->n_cu = prop.multiProcessorCount;
+    (void)resolve_scratch(device);  // device is current here
     *out = ctx.release();
     return POLFED_OK;
   });
@@ -577,6 +608,48 @@ polfed_status polfed_filter_apply(polfed_ctx* ctx, const polfed_op* op, double E
                           static_cast<float*>(w), A.as<float>(), Bb.as<float>());
       HIPC(hipStreamSynchronize(ctx->stream));
     }
+    return POLFED_OK;
+  });
+}
+
+polfed_status polfed_filter_apply_noalloc(polfed_ctx* ctx, const polfed_op* op, double E_c,
+                                          double dE, const double* a, int K, const void* v,
+                                          void* w, int precision) {
+  return guarded([&]() -> polfed_status {
+    check_step_args(ctx, op, dE, precision);
+    REQUIRE(std::isfinite(E_c), "E_c must be finite");
+    REQUIRE(K >= 0 && a, "need K >= 0 and coefficients a[K+1]");
+    REQUIRE(op->D == 0 || (v && w), "null vector");
+    REQUIRE(v != w, "v and w must not overlap");
+    const int64_t D = op->D;
+    const size_t tb = precision == POLFED_FP64 ? sizeof(double) : sizeof(float);
+    if ((size_t)std::max<int64_t>(D, 1) * tb > kNoAllocScratchBytes / 2)
+      fail(POLFED_ERR_INVALID,
+           "filter_apply_noalloc: the two recurrence vectors of D = " + std::to_string(D) +
+               " rows need " + std::to_string(2 * (size_t)D * tb) +
+               " bytes, more than the " + std::to_string(kNoAllocScratchBytes) +
+               "-byte scratch array");
+    // the step kernel must be chosen already: its timing allocates
+    const int pi = precision == POLFED_FP64 ? 0 : 1;
+    if (op->storage != POLFED_CSR &&
+        ((op->model == Model::Chain && op->split_nseg > 0 && op->tuned[pi] < 0) ||
+         (op->model == Model::Qrem && op->L >= 12 && op->tuned[pi] < 1)))
+      fail(POLFED_ERR_INVALID,
+           "filter_apply_noalloc: the operator's step kernel for this precision is not chosen "
+           "yet; run one step, filter or solve in this precision, or pick it with "
+           "polfed_op_set_kernel, first");
+    DeviceGuard g(ctx->device);
+    CtxLock lk(ctx);
+    unsigned char* base = static_cast<unsigned char*>(resolve_scratch(ctx->device));
+    const size_t half = kNoAllocScratchBytes / 2;
+    if (precision == POLFED_FP64)
+      filter_apply<double>(ctx, op, E_c, dE, a, K, static_cast<const double*>(v),
+                           static_cast<double*>(w), reinterpret_cast<double*>(base),
+                           reinterpret_cast<double*>(base + half));
+    else
+      filter_apply<float>(ctx, op, E_c, dE, a, K, static_cast<const float*>(v),
+                          static_cast<float*>(w), reinterpret_cast<float*>(base),
+                          reinterpret_cast<float*>(base + half));
     return POLFED_OK;
   });
 }
