@@ -215,6 +215,15 @@ polfed_status polfed_op_set_storage(polfed_op* op, int storage);
  * be NULL) receives the variant in use after the call (-1 while not tuned
  * yet). */
 polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, int* chosen);
+/* Multi-column step kernel of batches of B chain realizations that share the
+ * pattern of op (the batch's first operator), in one precision: -1 = pick by
+ * timing at the next batched filter (the default), 0 / 1 = column-major
+ * blocks with 16 / 8 columns per launch, 2 / 3 = interleaved blocks (the B
+ * columns of a row side by side, one 16-byte access per row and 2 FP64 or 4
+ * FP32 columns; 2 / 4 workgroups per compute unit); -2 only reports.
+ * *chosen (may be NULL) receives the variant in use (-1 while not tuned). */
+polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, int variant,
+                                         int* chosen);
 /* Dimension D of the operator's space (sector or full space). */
 polfed_status polfed_op_dim(const polfed_op* op, int64_t* D);
 /* Off-diagonal nnz of the CSR copy (-1 if there is none). */

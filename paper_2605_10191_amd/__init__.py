@@ -102,6 +102,7 @@ SIGNATURES = {
     "polfed_op_materialize_csr": [_P, _P],
     "polfed_op_set_storage": [_P, _I],
     "polfed_op_set_kernel": [_P, _I, _I, ctypes.POINTER(_I)],
+    "polfed_op_set_batch_kernel": [_P, _I, _I, _I, ctypes.POINTER(_I)],
     "polfed_op_dim": [_P, _I64P],
     "polfed_op_nnz": [_P, _I64P],
     "polfed_op_export_csr": [_P, _P, _P, _P, _P, _P],
@@ -400,6 +401,16 @@ class Operator:
         for QREM (-1 autotuned); returns the variant in use."""
         out = _I()
         _check(_lib.polfed_op_set_kernel(self.handle, precision, variant, ctypes.byref(out)))
+        return out.value
+
+    def set_batch_kernel(self, B: int, precision: int, variant: int) -> int:
+        """Multi-column step kernel for batches of B realizations of this
+        pattern (-1 autotuned, 0/1 column-major with 16/8 columns per launch,
+        2/3 interleaved with 2/4 workgroups per CU); returns the variant in
+        use (-1 while not tuned)."""
+        out = _I()
+        _check(_lib.polfed_op_set_batch_kernel(self.handle, int(B), precision, variant,
+                                               ctypes.byref(out)))
         return out.value
 
     @property

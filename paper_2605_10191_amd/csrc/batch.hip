@@ -30,6 +30,18 @@ static void scale_cols(hipStream_t s, int64_t D, int nb, const T* a, const T* v,
   HIPC(hipGetLastError());
 }
 
+// y (interleaved: element (r, c) at r nb + c) = a_c v_c, v column-major.
+template <typename T>
+__global__ void k_scale_ilv(int64_t D, int nb, const T* __restrict__ a, const T* v, T* y) {
+  const int64_t n = D * nb;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / nb;
+    const int c = (int)(i - r * nb);
+    y[i] = a[c] * v[(int64_t)c * D + r];
+  }
+}
+
 void BatchCoef::set(hipStream_t s, int nb_, const double* const* a, const int* K) {
   nb = nb_;
   Kmax = 0;
@@ -61,16 +73,28 @@ void filter_apply_batch_on(hipStream_t s, const ChainBatch& bt, const BatchCoef&
     scale_cols<T>(s, D, nb, A, v, w);
     return;
   }
-  scale_cols<T>(s, D, nb, A + (size_t)K * nb, v, bufA);
+  // the recurrence blocks take the tuned kernel's layout; v and w stay
+  // column-major
+  const int var = batch_variant<T>(s, bt);
+  const bool ilv = var >= 2;
+  if (ilv) {
+    const int64_t n = D * nb;
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256));
+    hipLaunchKernelGGL((k_scale_ilv<T>), dim3(g), dim3(256), 0, s, D, nb, A + (size_t)K * nb, v,
+                       bufA);
+    HIPC(hipGetLastError());
+  } else {
+    scale_cols<T>(s, D, nb, A + (size_t)K * nb, v, bufA);
+  }
   const T* cur = bufA;
   T* prev = nullptr;
   for (int i = K - 1; i >= 1; --i) {
     T* out = prev ? prev : bufB;
-    chain_batch_step<T>(s, bt, D, false, A + (size_t)i * nb, v, cur, prev, out);
+    chain_batch_step_var<T>(s, bt, var, false, A + (size_t)i * nb, v, true, cur, prev, out, !ilv);
     prev = const_cast<T*>(cur);
     cur = out;
   }
-  chain_batch_step<T>(s, bt, D, true, A, v, cur, prev, w);
+  chain_batch_step_var<T>(s, bt, var, true, A, v, true, cur, prev, w, true);
 }
 
 template <typename T>
@@ -136,6 +160,11 @@ void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
   bt.init(c, ops.data(), nb);
   bt.set_scale(Ec.data(), dE.data());
   co.set(c->stream, nb, a.data(), K.data());
+  // the step kernel is picked before run() records the recurrence
+  if (fp32)
+    (void)batch_variant<float>(c->stream, bt);
+  else
+    (void)batch_variant<double>(c->stream, bt);
   graph.reset();
   graph_pref = runs[0]->p.graph;
   mode = kTimeDirect;

@@ -52,6 +52,11 @@ void BlockWs::init(polfed_ctx* ctx, const polfed_op* op, int s_, bool fp32_,
     bt.init(ctx, ops.data(), s);
     bt.set_scale(Ec.data(), dE.data());
     co.set(ctx->stream, s, ap.data(), K.data());
+    // the step kernel is picked before a graph records the recurrence
+    if (fp32)
+      (void)batch_variant<float>(ctx->stream, bt);
+    else
+      (void)batch_variant<double>(ctx->stream, bt);
   }
 }
 

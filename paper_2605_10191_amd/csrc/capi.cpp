@@ -453,6 +453,32 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
   });
 }
 
+polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, int variant,
+                                         int* chosen) {
+  return guarded([&]() -> polfed_status {
+    REQUIRE(op, "null operator");
+    REQUIRE(op->model == Model::Chain && op->split_nseg > 0 && !op->pattern_key.empty(),
+            "multi-column kernels exist only for matrix-free chains");
+    REQUIRE(B >= 1, "need B >= 1");
+    REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
+    REQUIRE(variant >= -2 && variant < 4, "variant must be -2 .. 3");
+    const int key = B * 2 + (precision == POLFED_FP64 ? 0 : 1);
+    if (variant == -1) op->batch_tuned.erase(key);
+    if (variant >= 0) {
+      if (variant >= 2)
+        REQUIRE((uint64_t)op->D * (uint64_t)B * (precision == POLFED_FP64 ? 8 : 4) <
+                    (uint64_t(1) << 32) - 64,
+                "interleaved blocks of this size exceed 4 GiB");
+      op->batch_tuned[key] = variant;
+    }
+    if (chosen) {
+      const auto it = op->batch_tuned.find(key);
+      *chosen = it == op->batch_tuned.end() ? -1 : it->second;
+    }
+    return POLFED_OK;
+  });
+}
+
 polfed_status polfed_op_dim(const polfed_op* op, int64_t* D) {
   return guarded([&]() -> polfed_status {
     REQUIRE(op && D, "null argument");

@@ -16,6 +16,7 @@
 // column.
 #include <algorithm>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 
 #include "chain_dev.hpp"
@@ -180,22 +181,263 @@ __global__ __launch_bounds__(256) void k_chain_split_batch(
   }
 }
 
-static int env_int(const char* name, int dflt) {
-  const char* s = std::getenv(name);
-  return (s && *s) ? std::atoi(s) : dflt;
+// Interleaved multi-column step.  The recurrence blocks are stored with the
+// columns of a row side by side: element (row r, column c) at X[r nb + c].
+// A wavefront takes one (segment, column group) item, a group being the
+// G = 16 / sizeof(T) columns (2 FP64, 4 FP32) that one 16-byte access moves
+// for a row, and lane l holds rows l and l + 64 of the segment.  So every
+// gather (uniform-offset high-part hops, the masked joining and periodic
+// hops, the block staged in LDS for the low-part hops) serves G columns at
+// once, and the columns of a batch run side by side on different
+// wavefronts instead of one after another.  The start vectors v may be
+// column-major (VCM, column stride D: the caller's block) and the output of
+// the closing step column-major too (OCM).  A last group narrower than G
+// (nb not a multiple of G) takes element-wise accesses.
+template <typename T>
+struct Grp {
+  T x[16 / sizeof(T)];
+};
+
+template <typename T>
+__device__ __forceinline__ Grp<T> gload(rsrc_t r, uint32_t row_bytes, uint32_t so, int w) {
+  constexpr int G = 16 / sizeof(T);
+  Grp<T> g;
+  if (w == G) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    const u4 d = __builtin_amdgcn_raw_buffer_load_b128(r, row_bytes, so, 0);
+    __builtin_memcpy(&g, &d, 16);
+  } else {
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      g.x[c] = c < w ? bload<T>(r, row_bytes + (uint32_t)(c * sizeof(T)), so) : T(0);
+  }
+  return g;
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(const Grp<T>& g, rsrc_t r, uint32_t row_bytes, uint32_t so,
+                                       int w) {
+  constexpr int G = 16 / sizeof(T);
+  if (w == G) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    u4 d;
+    __builtin_memcpy(&d, &g, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(d, r, row_bytes, so, kAuxNT);
+  } else {
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      if (c < w) bstore<kAuxNT>(g.x[c], r, row_bytes + (uint32_t)(c * sizeof(T)), so);
+  }
+}
+
+template <typename T, int L, bool VCM, bool OCM>
+__global__ __launch_bounds__(256) void k_chain_ilv(
+    ChainSplitDev c, int nb, T half, const T* __restrict__ fab, const T* __restrict__ dseg,
+    const T* __restrict__ sc, const T* __restrict__ acoef, const T* __restrict__ v,
+    const T* __restrict__ b1, const T* b2, T* out, int ngrp, int nxcd,
+    const int32_t* __restrict__ recs) {
+  constexpr int G = 16 / (int)sizeof(T);
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;
+  constexpr int NL = Lb - 1;
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  for (int i = threadIdx.x; i < CHUNKS; i += 256)
+    reinterpret_cast<u4*>(smem)[i] =
+        reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blobl64 : c.blobl32)[i];
+  T* s_fab = reinterpret_cast<T*>(smem + BLOB);
+  for (int i = threadIdx.x; i < nb * 64; i += 256) s_fab[i] = fab[i];
+  // list-ordered tables: entry q describes the q-th low part of the list
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(smem + 16 * NLO + TB * NLO);
+  // this wave's staging area: the segment's block, 256 rows of G columns
+  Grp<T>* stage = reinterpret_cast<Grp<T>*>(
+      reinterpret_cast<unsigned char*>(s_fab + ((nb * 64 + 1) & ~1)) +
+      (size_t)(threadIdx.x >> 6) * kChainStageRows * 16);
+  __syncthreads();
+
+  const int xcd = blockIdx.x % nxcd;
+  const int blocks_x = gridDim.x / nxcd;
+  const int64_t nitem = c.nseg * ngrp;
+  const int64_t i_begin = nitem * xcd / nxcd, i_end = nitem * (xcd + 1) / nxcd;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wstride = (int64_t)blocks_x * wpb;
+  const int lane = threadIdx.x & 63;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t rowb = (uint32_t)nb * TB;  // bytes per row of a block
+  const uint32_t blkbytes = (uint32_t)(c.D * rowb);
+  const uint32_t cbytes = (uint32_t)(c.D * TB);  // one column-major column
+  const rsrc_t rb1 = make_rsrc(b1, blkbytes), rb2 = make_rsrc(b2, b2 ? blkbytes : 0);
+  const rsrc_t rv = make_rsrc(v, v ? (VCM ? (uint32_t)(c.D * nb * TB) : blkbytes) : 0);
+  const rsrc_t rout = make_rsrc(out, OCM ? (uint32_t)(c.D * nb * TB) : blkbytes);
+  int64_t it = i_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
+  for (; it < i_end; it += wstride) {
+    const int64_t si = it / ngrp;
+    const int g = (int)(it % ngrp);
+    const int c0 = g * G, w = min(G, nb - c0);
+    const uint32_t cb = (uint32_t)c0 * TB;  // byte offset of the group in a row
+    const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform((int)si) * kChainRecWords);
+    const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+    const int bs = (cur.flags >> 2) & 1023, st = (cur.flags >> 12) & 1023;
+    const int blk0 = cur.row0 - st;
+    // per-column scalars of the group (padding columns repeat the last)
+    T sig[G], ta[G], ac[G], dsg[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int col = min(c0 + q, nb - 1);
+      sig[q] = sc[col] * half;
+      ta[q] = sc[nb + col] * half;
+      ac[q] = acoef ? acoef[col] : T(0);
+      dsg[q] = dseg[si * nb + col];
+    }
+    // the block of b_{i+1} for the low-part hops: loads now, LDS later
+    Grp<T> sg[kChainStageRows / 64];
+#pragma unroll
+    for (int m = 0; m < kChainStageRows / 64; ++m) {
+      const int r = lane + 64 * m;
+      sg[m] = gload<T>(rb1, (uint32_t)min(r, bs - 1) * rowb + cb, (uint32_t)blk0 * rowb, w);
+    }
+    int jj[2], lo[2], gj[2], gp[2];
+    u4 np[2];
+    bool act_j[2], act_p[2];
+    T zz[2], nidle[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      jj[i] = min(lane + 64 * i, cur.len - 1);
+      const int q = cur.lidx + jj[i];
+      const int l = s_lo[q];
+      lo[i] = l;
+      np[i] = s_np[q];
+      act_j[i] = ((l >> (Lb - 1)) & 1) != hi0;
+      act_p[i] = c.periodic && ((l & 1) != hitop);
+      gj[i] = blk0 + cur.d_join + (int)((np[i][2] >> 8) & 255u);
+      gp[i] = blk0 + cur.d_pbc + (int)((np[i][2] >> 16) & 255u);
+      const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+      nidle[i] = (T)(NL - __popc(xlo));
+      const int n11x = ((l >> (Lb - 1)) & 1 & hi0) + (c.periodic ? (hitop & l & 1) : 0);
+      zz[i] = vzz * (T)(__popc(l & (l >> 1)) + n11x);
+    }
+    Grp<T> g_hi[NH > 0 ? NH : 1][2], g_j[2], g_p[2], vv[2], bt[2];
+#pragma unroll
+    for (int b = 0; b < NH; ++b)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (cur.dh[b] != 0)
+          g_hi[b][i] = gload<T>(rb1, (uint32_t)jj[i] * rowb + cb,
+                                (uint32_t)(cur.row0 + cur.dh[b]) * rowb, w);
+        else
+          g_hi[b][i] = Grp<T>{};
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      g_j[i] = act_j[i] ? gload<T>(rb1, (uint32_t)gj[i] * rowb + cb, 0, w) : Grp<T>{};
+      g_p[i] = act_p[i] ? gload<T>(rb1, (uint32_t)gp[i] * rowb + cb, 0, w) : Grp<T>{};
+      const uint32_t row = (uint32_t)(cur.row0 + jj[i]);
+      if (!v) {
+        vv[i] = Grp<T>{};
+      } else if (VCM) {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          vv[i].x[q] = q < w ? bload<T, kAuxNT>(rv, row * TB, (uint32_t)(c0 + q) * cbytes) : T(0);
+      } else {
+        vv[i] = gload<T>(rv, row * rowb + cb, 0, w);
+      }
+      bt[i] = b2 ? gload<T>(rb2, row * rowb + cb, 0, w) : Grp<T>{};
+    }
+    wave_sync();  // the previous item's LDS reads are done
+#pragma unroll
+    for (int m = 0; m < kChainStageRows / 64; ++m)
+      if (lane + 64 * m < bs) stage[lane + 64 * m] = sg[m];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int l = lo[i];
+      const Grp<T> bo = stage[st + jj[i]];
+      Grp<T> nbv[NL > 0 ? NL : 1];
+#pragma unroll
+      for (int b = 0; b < NL; ++b) nbv[b] = stage[(np[i][b >> 2] >> (8 * (b & 3))) & 255u];
+      Grp<T> o;
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        T hop = 0;
+#pragma unroll
+        for (int b = 0; b < NL; ++b) hop += nbv[b].x[q];
+#pragma unroll
+        for (int b = 0; b < NH; ++b) hop += g_hi[b][i].x[q];
+        hop -= nidle[i] * bo.x[q];
+        hop += act_j[i] ? g_j[i].x[q] : T(0);
+        const T* fa = s_fab + min(c0 + q, nb - 1) * 64;
+        const T dg = zz[i] + fa[l & 31] + fa[32 + (l >> 5)] + dsg[q];
+        const T acc = dg * bo.x[q] + t_in * hop + (act_p[i] ? t_pb * g_p[i].x[q] : T(0));
+        o.x[q] = sig[q] * acc + ta[q] * bo.x[q] - bt[i].x[q] + ac[q] * vv[i].x[q];
+      }
+      const uint32_t row = (uint32_t)(cur.row0 + jj[i]);
+      if (lane + 64 * i >= cur.len) continue;  // a clamped repeat of the last row
+      if (OCM) {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          if (q < w) bstore<kAuxNT>(o.x[q], rout, row * TB, (uint32_t)(c0 + q) * cbytes);
+      } else {
+        gstore<T>(o, rout, row * rowb + cb, 0, w);
+      }
+    }
+  }
+}
+
+static int batch_bpc_fit(size_t shm) { return std::max(1, (int)(kLdsPerCU / shm)); }
+
+template <typename T, int L>
+static void launch_ilv(hipStream_t s, const polfed_op* op0, const ChainBatch& bt, int bpc, T half,
+                       const T* acoef, const T* v, bool vcm, const T* b1, const T* b2, T* out,
+                       bool ocm) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int G = 16 / (int)sizeof(T);
+  const size_t shm = chain_blob_bytes(1 << Lb, (int)sizeof(T)) +
+                     (size_t)((bt.nb * 64 + 1) & ~1) * sizeof(T) + 4 * kChainStageRows * 16;
+  bpc = std::max(1, std::min(bpc, batch_bpc_fit(shm)));
+  ChainSplitDev c = op0->chain_split();
+  const int ngrp = (bt.nb + G - 1) / G;
+  const int64_t items = c.nseg * ngrp;
+  int64_t grid = std::min<int64_t>((items + 3) / 4, (int64_t)op0->ctx->n_cu * bpc);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  const bool f64 = sizeof(T) == 8;
+  const T* fab = (const T*)(f64 ? bt.fab64.get() : bt.fab32.get());
+  const T* dseg = (const T*)(f64 ? bt.dseg64.get() : bt.dseg32.get());
+  const T* sc = (const T*)(f64 ? bt.sc64.get() : bt.sc32.get());
+#define POLFED_ILV(VC, OC)                                                                   \
+  hipLaunchKernelGGL((k_chain_ilv<T, L, VC, OC>), dim3((unsigned)grid), dim3(256), shm, s, c, \
+                     bt.nb, half, fab, dseg, sc, acoef, v, b1, b2, out, ngrp, nxcd, c.rec)
+  if (vcm && ocm)
+    POLFED_ILV(true, true);
+  else if (vcm)
+    POLFED_ILV(true, false);
+  else if (ocm)
+    POLFED_ILV(false, true);
+  else
+    POLFED_ILV(false, false);
+#undef POLFED_ILV
+  HIPC(hipGetLastError());
 }
 
 template <typename T, int L>
 static void launch_batch(hipStream_t s, const polfed_op* op0, const ChainBatch& bt,
-                         int col0, int ncols, int64_t ld, T half, const T* acoef,
+                         int col0, int ncols, int64_t ld, int bpc, T half, const T* acoef,
                          const T* v, const T* b1, const T* b2, T* out) {
   constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
   constexpr int NLO = 1 << Lb;
-  static const int bpc_env = env_int("POLFED_BATCH_BPC", 0);
   const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) +
                      (size_t)ncols * 64 * sizeof(T) + 4 * kChainStageRows * sizeof(T);
-  const int fit = std::max(1, (int)(kLdsPerCU / shm));
-  const int bpc = bpc_env > 0 ? bpc_env : std::min(fit, kChainBlocksPerCU);
+  bpc = std::max(1, std::min(bpc, batch_bpc_fit(shm)));
   ChainSplitDev c = op0->chain_split();
   const int64_t blocks_needed = (c.nseg + 3) / 4;
   int64_t grid = std::min<int64_t>(blocks_needed, (int64_t)op0->ctx->n_cu * bpc);
@@ -263,17 +505,47 @@ void ChainBatch::set_scale(const double* E_c, const double* dE) {
   HIPC(hipStreamSynchronize(s));
 }
 
+// Multi-column step variants: 0 and 1 the column-major kernel with 16 and
+// 8 columns per launch, 2 and 3 the interleaved kernel with 2 and 4
+// workgroups per compute unit.
+constexpr int kBatchVariants = 4;
+
+static bool interleaved_fits(const ChainBatch& bt, size_t tb) {
+  return (uint64_t)bt.ops[0]->D * (uint64_t)bt.nb * tb < (uint64_t(1) << 32) - 64;
+}
+
 template <typename T>
-void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool final_step,
-                      const T* acoef, const T* v, const T* b1, const T* b2, T* out) {
+static void batch_step_var(hipStream_t s, const ChainBatch& bt, int var, bool final_step,
+                           const T* acoef, const T* v, bool vcm, const T* b1, const T* b2,
+                           T* out, bool ocm) {
   const polfed_op* op0 = bt.ops[0];
   const T half = final_step ? T(0.5) : T(1);
-  for (int col0 = 0; col0 < bt.nb; col0 += kBatchMaxCols) {
-    const int ncols = std::min(kBatchMaxCols, bt.nb - col0);
+  const int64_t ld = op0->D;
+  if (var >= 2) {
+    const int bpc = var == 2 ? 2 : 4;
     switch (op0->L) {
-#define POLFED_CASE(LL)                                                                   \
-  case LL:                                                                                \
-    launch_batch<T, LL>(s, op0, bt, col0, ncols, ld, half, acoef, v, b1, b2, out); \
+#define POLFED_CASE(LL)                                                                     \
+  case LL:                                                                                  \
+    launch_ilv<T, LL>(s, op0, bt, bpc, half, acoef, v, vcm, b1, b2, out, ocm);              \
+    break;
+      POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
+      POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
+      POLFED_CASE(14) POLFED_CASE(15) POLFED_CASE(16) POLFED_CASE(17) POLFED_CASE(18)
+      POLFED_CASE(19) POLFED_CASE(20) POLFED_CASE(21) POLFED_CASE(22) POLFED_CASE(23)
+      POLFED_CASE(24) POLFED_CASE(25) POLFED_CASE(26) POLFED_CASE(27) POLFED_CASE(28)
+#undef POLFED_CASE
+      default: fail(POLFED_ERR_INVALID, "batch: chain length outside 4..28");
+    }
+    return;
+  }
+  const int per = var == 0 ? 16 : 8;
+  for (int col0 = 0; col0 < bt.nb; col0 += per) {
+    const int ncols = std::min(per, bt.nb - col0);
+    switch (op0->L) {
+#define POLFED_CASE(LL)                                                                     \
+  case LL:                                                                                  \
+    launch_batch<T, LL>(s, op0, bt, col0, ncols, ld, kChainBlocksPerCU, half, acoef, v, b1, \
+                        b2, out);                                                           \
     break;
       POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
       POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
@@ -286,6 +558,71 @@ void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool fina
   }
 }
 
+template <typename T>
+void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool final_step,
+                      const T* acoef, const T* v, const T* b1, const T* b2, T* out) {
+  REQUIRE(ld == bt.ops[0]->D, "batch: column stride must be D");
+  batch_step_var<T>(s, bt, 0, final_step, acoef, v, true, b1, b2, out, true);
+}
+
+template <typename T>
+int batch_variant(hipStream_t s, const ChainBatch& bt) {
+  const polfed_op* op0 = bt.ops[0];
+  const int key = bt.nb * 2 + (sizeof(T) == 8 ? 0 : 1);
+  {
+    auto it = op0->batch_tuned.find(key);
+    if (it != op0->batch_tuned.end()) return it->second;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPC(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return 0;  // tuned before any capture
+  TallyScope untallied(nullptr);
+  const size_t n = (size_t)std::max<int64_t>(op0->D, 1) * bt.nb;
+  DevBuf bv(n * sizeof(T)), b1(n * sizeof(T)), b2(n * sizeof(T)), ac(bt.nb * sizeof(T));
+  HIPC(hipMemsetAsync(bv.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(b1.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(b2.get(), 0, n * sizeof(T), s));
+  HIPC(hipMemsetAsync(ac.get(), 0, bt.nb * sizeof(T), s));
+  HIPC(hipStreamSynchronize(s));
+  int best = 0;
+  float best_us = 1e30f;
+  for (int var = 0; var < kBatchVariants; ++var) {
+    if (var >= 2 && !interleaved_fits(bt, sizeof(T))) continue;
+    if (var == 1 && bt.nb <= 8) continue;  // the same launches as variant 0
+    const float us = replay_time_us(
+        [&](hipStream_t ts) {
+          batch_step_var<T>(ts, bt, var, false, ac.as<T>(), bv.as<T>(), true, b1.as<T>(),
+                            b2.as<T>(), b2.as<T>(), false);
+        },
+        10);
+    if (verbose())
+      std::fprintf(stderr, "[polfed] batch step L=%d nb=%d %s variant %d: %.2f us\n", op0->L,
+                   bt.nb, sizeof(T) == 8 ? "fp64" : "fp32", var, us);
+    if (us < best_us) {
+      best_us = us;
+      best = var;
+    }
+  }
+  HIPC(hipStreamSynchronize(s));
+  op0->batch_tuned[key] = best;
+  return best;
+}
+
+template <typename T>
+void chain_batch_step_var(hipStream_t s, const ChainBatch& bt, int var, bool final_step,
+                          const T* acoef, const T* v, bool vcm, const T* b1, const T* b2,
+                          T* out, bool ocm) {
+  batch_step_var<T>(s, bt, var, final_step, acoef, v, vcm, b1, b2, out, ocm);
+}
+
+template int batch_variant<double>(hipStream_t, const ChainBatch&);
+template int batch_variant<float>(hipStream_t, const ChainBatch&);
+template void chain_batch_step_var<double>(hipStream_t, const ChainBatch&, int, bool,
+                                           const double*, const double*, bool, const double*,
+                                           const double*, double*, bool);
+template void chain_batch_step_var<float>(hipStream_t, const ChainBatch&, int, bool,
+                                          const float*, const float*, bool, const float*,
+                                          const float*, float*, bool);
 template void chain_batch_step<double>(hipStream_t, const ChainBatch&, int64_t, bool,
                                        const double*, const double*, const double*,
                                        const double*, double*);

@@ -360,6 +360,8 @@ struct polfed_op {
     polfed::DevBuf d;
   };
   mutable std::map<int, WTiles> wtiles;
+  // multi-column step variant per (batch width, precision), by timing
+  mutable std::map<int, int> batch_tuned;
   // step-kernel variant picked by timing on first use, per precision
   // (-1: not tuned yet, 0: segment kernel, 1 + i: tile kernel tiles[i])
   mutable int tuned[2] = {-1, -1};
@@ -414,6 +416,19 @@ struct ChainBatch {
 template <typename T>
 void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool final_step,
                       const T* acoef, const T* v, const T* b1, const T* b2, T* out);
+// The multi-column step kernel picked by timing for this batch width and
+// precision (kept per operator pattern): 0, 1 column-major blocks (16 or 8
+// columns per launch), 2, 3 interleaved blocks (element (r, c) at r nb + c;
+// 2 or 4 workgroups per compute unit).  Not while the stream is captured
+// (returns 0 then, without keeping it).
+template <typename T>
+int batch_variant(hipStream_t s, const ChainBatch& bt);
+// One step with variant var; v column-major (column stride D) when vcm,
+// else in the variant's layout; out column-major when ocm.
+template <typename T>
+void chain_batch_step_var(hipStream_t s, const ChainBatch& bt, int var, bool final_step,
+                          const T* acoef, const T* v, bool vcm, const T* b1, const T* b2,
+                          T* out, bool ocm);
 
 // ----------------------------------------------------------- operators ----
 // Fused Clenshaw step for every operator kind and precision:
