@@ -220,7 +220,9 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
  * timing at the next batched filter (the default), 0 / 1 = column-major
  * blocks with 16 / 8 columns per launch, 2 / 3 = interleaved blocks (the B
  * columns of a row side by side, one 16-byte access per row and 2 FP64 or 4
- * FP32 columns; 2 / 4 workgroups per compute unit); -2 only reports.
+ * FP32 columns; 2 / 4 workgroups per compute unit), 4 = every column
+ * stepped by its own operator's tuned single-column kernel (the staged-tile
+ * kernels, L >= 22); -2 only reports.
  * *chosen (may be NULL) receives the variant in use (-1 while not tuned). */
 polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, int variant,
                                          int* chosen);

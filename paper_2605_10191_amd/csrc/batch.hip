@@ -52,6 +52,8 @@ void BatchCoef::set(hipStream_t s, int nb_, const double* const* a, const int* K
   std::vector<double> A((size_t)(Kmax + 1) * nb, 0.0);
   for (int c = 0; c < nb; ++c)
     for (int i = 0; i <= K[c]; ++i) A[(size_t)i * nb + c] = a[c][i];
+  host = A;
+  this->K.assign(K, K + nb);
   std::vector<float> A32(A.begin(), A.end());
   upload(d64, A.data(), A.size(), s);
   upload(d32, A32.data(), A32.size(), s);
@@ -76,6 +78,18 @@ void filter_apply_batch_on(hipStream_t s, const ChainBatch& bt, const BatchCoef&
   // the recurrence blocks take the tuned kernel's layout; v and w stay
   // column-major
   const int var = batch_variant<T>(s, bt);
+  if (var == 4) {
+    // every column its own recurrence with its operator's tuned kernel
+    std::vector<double> ac;
+    for (int c = 0; c < nb; ++c) {
+      ac.resize((size_t)co.K[c] + 1);
+      for (int i = 0; i <= co.K[c]; ++i) ac[i] = co.host[(size_t)i * nb + c];
+      filter_apply_on<T>(s, bt.ops[c], bt.E_c[c], bt.dE[c], ac.data(), co.K[c],
+                         v + (size_t)c * D, w + (size_t)c * D, bufA + (size_t)c * D,
+                         bufB + (size_t)c * D);
+    }
+    return;
+  }
   const bool ilv = var >= 2;
   if (ilv) {
     const int64_t n = D * nb;

@@ -499,6 +499,8 @@ void ChainBatch::set_scale(const double* E_c, const double* dE) {
     sc[nb + i] = -2.0 * E_c[i] / dE[i];
   }
   std::vector<float> s32(sc.begin(), sc.end());
+  this->E_c.assign(E_c, E_c + nb);
+  this->dE.assign(dE, dE + nb);
   hipStream_t s = ctx->stream;
   HIPC(hipMemcpyAsync(sc64.get(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIPC(hipMemcpyAsync(sc32.get(), s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice, s));
@@ -508,7 +510,7 @@ void ChainBatch::set_scale(const double* E_c, const double* dE) {
 // Multi-column step variants: 0 and 1 the column-major kernel with 16 and
 // 8 columns per launch, 2 and 3 the interleaved kernel with 2 and 4
 // workgroups per compute unit.
-constexpr int kBatchVariants = 4;
+constexpr int kBatchVariants = 5;
 
 static bool interleaved_fits(const ChainBatch& bt, size_t tb) {
   return (uint64_t)bt.ops[0]->D * (uint64_t)bt.nb * tb < (uint64_t(1) << 32) - 64;
@@ -521,6 +523,16 @@ static void batch_step_var(hipStream_t s, const ChainBatch& bt, int var, bool fi
   const polfed_op* op0 = bt.ops[0];
   const T half = final_step ? T(0.5) : T(1);
   const int64_t ld = op0->D;
+  if (var == 4) {
+    // column by column with each operator's single-column kernel; the
+    // per-column scalars are host values (the filter passes them through
+    // batch_step_cols), here the timing step of the tuner
+    for (int c = 0; c < bt.nb; ++c)
+      op_step<T>(s, bt.ops[c], half * (T)(2.0 / bt.dE[c]), half * (T)(-2.0 * bt.E_c[c] / bt.dE[c]),
+                 T(0), v + (size_t)c * ld, b1 + (size_t)c * ld, b2 ? b2 + (size_t)c * ld : nullptr,
+                 out + (size_t)c * ld);
+    return;
+  }
   if (var >= 2) {
     const int bpc = var == 2 ? 2 : 4;
     switch (op0->L) {
@@ -587,8 +599,14 @@ int batch_variant(hipStream_t s, const ChainBatch& bt) {
   int best = 0;
   float best_us = 1e30f;
   for (int var = 0; var < kBatchVariants; ++var) {
-    if (var >= 2 && !interleaved_fits(bt, sizeof(T))) continue;
+    if ((var == 2 || var == 3) && !interleaved_fits(bt, sizeof(T))) continue;
     if (var == 1 && bt.nb <= 8) continue;  // the same launches as variant 0
+    if (var == 4) {
+      // only where a single-column tile kernel exists (L >= 22); each
+      // operator picks its own kernel first, outside any capture
+      if (op0->L < 22) continue;
+      for (int c = 0; c < bt.nb; ++c) op_tune(s, bt.ops[c], sizeof(T) == 4);
+    }
     const float us = replay_time_us(
         [&](hipStream_t ts) {
           batch_step_var<T>(ts, bt, var, false, ac.as<T>(), bv.as<T>(), true, b1.as<T>(),

@@ -407,6 +407,7 @@ struct ChainBatch {
   DevBuf fab64, fab32;    // [nb][64] low-bit field sums (bits 0-4 | 5-9)
   DevBuf dseg64, dseg32;  // [nseg][nb] uniform diagonal part per segment
   DevBuf sc64, sc32;      // [2][nb] sigma = 2/dE, tau = -2 E_c/dE
+  std::vector<double> E_c, dE;  // host copies of each column's rescaling
   void init(polfed_ctx* c, const polfed_op* const* o, int n);
   void set_scale(const double* E_c, const double* dE);
 };
@@ -419,7 +420,9 @@ void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool fina
 // The multi-column step kernel picked by timing for this batch width and
 // precision (kept per operator pattern): 0, 1 column-major blocks (16 or 8
 // columns per launch), 2, 3 interleaved blocks (element (r, c) at r nb + c;
-// 2 or 4 workgroups per compute unit).  Not while the stream is captured
+// 2 or 4 workgroups per compute unit), 4 column-major blocks with every
+// column stepped by its operator's own tuned single-column kernel (the
+// staged-tile kernels of long chains).  Not while the stream is captured
 // (returns 0 then, without keeping it).
 template <typename T>
 int batch_variant(hipStream_t s, const ChainBatch& bt);

@@ -86,6 +86,8 @@ double step_bytes(const polfed_op* op, int precision);
 struct BatchCoef {
   DevBuf d64, d32;
   int nb = 0, Kmax = 0;
+  std::vector<double> host;  // (Kmax + 1) x nb, column c of row i = a_c[i]
+  std::vector<int> K;        // each column's own order
   void set(hipStream_t s, int nb, const double* const* a, const int* K);
 };
 

@@ -212,3 +212,29 @@ def test_batch_kernel_is_tuned_and_kept(pk, ctx, prec):
     for c in range(6):
         ref = flt.apply_filter(Hs[c], 0.0, 30.0, coefs[c], V[c])
         assert np.max(np.abs(got[c] - ref)) <= filter_tol(50, prec) * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_per_column_tile_kernels_long_chain(pk, ctx, prec):
+    """Variant 4 (each column stepped by its own operator's tuned
+    single-column kernel, the staged-tile kernels of long chains) on three
+    L = 22 realizations: every column element by element against the
+    oracle's filter of its own Hamiltonian (D = 705,432, K = 20); the same
+    variant is refused below L = 22."""
+    say(f"batch variant 4, L=22, {prec}")
+    ops, Hs = batch_ops(pk, ctx, "xxz", 22, 3)
+    p = pk.FP64 if prec == "fp64" else pk.FP32
+    assert ops[0].set_batch_kernel(3, p, 4) == 4
+    D = ops[0].D
+    V = np.stack([wl.start_vector(D, 90 + c) for c in range(3)])
+    coefs = [flt.coefficients(0.05 * c, 20) for c in range(3)]
+    E_c, dE = [0.1, -0.2, 0.0], [40.0, 45.0, 50.0]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    w = pk.filter_apply_batch(ops, E_c, dE, coefs, dev(V, dt), p)
+    got = host(w).astype(np.float64)
+    for c in range(3):
+        ref = flt.apply_filter(Hs[c], E_c[c], dE[c], coefs[c], V[c])
+        assert np.max(np.abs(got[c] - ref)) <= filter_tol(20, prec) * np.max(np.abs(ref))
+    small, _ = batch_ops(pk, ctx, "xxz", 12, 2)
+    with pytest.raises(pk.PolfedError):
+        small[0].set_batch_kernel(2, p, 4)
