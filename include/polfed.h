@@ -222,7 +222,10 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
  * columns of a row side by side, one 16-byte access per row and 2 FP64 or 4
  * FP32 columns; 2 / 4 workgroups per compute unit), 4 = every column
  * stepped by its own operator's tuned single-column kernel (the staged-tile
- * kernels, L >= 22); -2 only reports.
+ * kernels, L >= 22), 5 = the LDS-resident filter (one workgroup per column
+ * runs the column's whole recurrence with both Clenshaw vectors in LDS and
+ * a barrier between steps; where two vectors fit: FP64 to L = 14, FP32 to
+ * L = 16 at half filling); -2 only reports.
  * *chosen (may be NULL) receives the variant in use (-1 while not tuned). */
 polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, int variant,
                                          int* chosen);

@@ -407,8 +407,8 @@ class Operator:
         """Multi-column step kernel for batches of B realizations of this
         pattern (-1 autotuned, 0/1 column-major with 16/8 columns per launch,
         2/3 interleaved with 2/4 workgroups per CU, 4 each column by its own
-        single-column kernel, L >= 22); returns the variant in use (-1 while
-        not tuned)."""
+        single-column kernel, L >= 22, 5 the LDS-resident whole filter for
+        short chains); returns the variant in use (-1 while not tuned)."""
         out = _I()
         _check(_lib.polfed_op_set_batch_kernel(self.handle, int(B), precision, variant,
                                                ctypes.byref(out)))

@@ -54,6 +54,7 @@ void BatchCoef::set(hipStream_t s, int nb_, const double* const* a, const int* K
     for (int i = 0; i <= K[c]; ++i) A[(size_t)i * nb + c] = a[c][i];
   host = A;
   this->K.assign(K, K + nb);
+  upload(dK, this->K.data(), this->K.size(), s);
   std::vector<float> A32(A.begin(), A.end());
   upload(d64, A.data(), A.size(), s);
   upload(d32, A32.data(), A32.size(), s);
@@ -78,6 +79,10 @@ void filter_apply_batch_on(hipStream_t s, const ChainBatch& bt, const BatchCoef&
   // the recurrence blocks take the tuned kernel's layout; v and w stay
   // column-major
   const int var = batch_variant<T>(s, bt);
+  if (var == 5) {
+    chain_lds_filter<T>(s, bt, A, co.dK.as<int>(), v, w);
+    return;
+  }
   if (var == 4) {
     // every column its own recurrence with its operator's tuned kernel
     std::vector<double> ac;

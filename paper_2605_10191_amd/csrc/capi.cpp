@@ -461,8 +461,12 @@ polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, in
             "multi-column kernels exist only for matrix-free chains");
     REQUIRE(B >= 1, "need B >= 1");
     REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
-    REQUIRE(variant >= -2 && variant < 5, "variant must be -2 .. 4");
+    REQUIRE(variant >= -2 && variant < 6, "variant must be -2 .. 5");
     if (variant == 4) REQUIRE(op->L >= 22, "variant 4 needs a chain of L >= 22");
+    if (variant == 5)
+      REQUIRE(precision == POLFED_FP64 ? chain_lds_filter_fits<double>(op)
+                                       : chain_lds_filter_fits<float>(op),
+              "variant 5: two vectors of this chain do not fit the LDS");
     const int key = B * 2 + (precision == POLFED_FP64 ? 0 : 1);
     if (variant == -1) op->batch_tuned.erase(key);
     if (variant >= 0) {

@@ -389,6 +389,193 @@ __global__ __launch_bounds__(256) void k_chain_ilv(
   }
 }
 
+// LDS-resident filter for short chains: one workgroup per column runs that
+// column's whole Clenshaw recurrence, b_K = a_K v, b_i = a_i v + 2 H~ b_{i+1}
+// - b_{i+2} (i = K_c - 1 .. 1), w = a_0 v + H~ b_1 - b_2, with b_{i+1} and
+// b_{i+2} both held in LDS (b_i overwrites b_{i+2} in place) and a
+// workgroup barrier between steps: no launch per step and no global traffic
+// but v (kept in LDS too where a third vector fits) and w.  The segment
+// records, a row-to-segment map and the column's per-segment diagonal part
+// sit in LDS as well, so the threads take rows, not segments: thread t
+// handles rows t, t + 1024, ..., and every operand of a row (its segment's
+// record, its low-part tables, the neighbours) is an LDS read, all issued
+// before any is summed.  Fits where the vectors and tables fit the LDS
+// (FP64 up to L = 14, FP32 up to L = 16 at half filling).
+template <typename T, int L, bool VLDS>
+__global__ __launch_bounds__(1024) void k_chain_lds_filter(
+    ChainSplitDev c, int nb, const T* __restrict__ fab, const T* __restrict__ dseg,
+    const T* __restrict__ sc, const T* __restrict__ A, const int* __restrict__ Kc,
+    const T* __restrict__ v, T* __restrict__ w, const int32_t* __restrict__ recs) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;
+  constexpr int NL = Lb - 1;
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr int RW = kChainRecWords;
+  static_assert(10 + NH <= 20, "five 16-byte reads cover a record's used words");
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int col = blockIdx.x;
+  const int64_t D = c.D;
+  const int nseg = (int)c.nseg;
+  for (int i = threadIdx.x; i < CHUNKS; i += 1024)
+    reinterpret_cast<u4*>(smem)[i] =
+        reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blobl64 : c.blobl32)[i];
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(smem + 16 * NLO + sizeof(T) * NLO);
+  T* s_fa = reinterpret_cast<T*>(smem + BLOB);
+  if (threadIdx.x < 64) s_fa[threadIdx.x] = fab[(int64_t)col * 64 + threadIdx.x];
+  // this column's uniform diagonal part per segment, the segment records,
+  // the row-to-segment map, then the vectors
+  T* s_dseg = s_fa + 64;
+  for (int i = threadIdx.x; i < nseg; i += 1024) s_dseg[i] = dseg[(int64_t)i * nb + col];
+  int32_t* s_rec = reinterpret_cast<int32_t*>(s_dseg + ((nseg + 1) & ~1));
+  for (int i = threadIdx.x; i < nseg * RW / 4; i += 1024)
+    reinterpret_cast<u4*>(s_rec)[i] = reinterpret_cast<const u4*>(recs)[i];
+  uint16_t* s_rowseg = reinterpret_cast<uint16_t*>(s_rec + nseg * RW);
+  T* bufX = reinterpret_cast<T*>(s_rowseg + ((D + 7) & ~int64_t(7)));
+  T* bufY = bufX + D;
+  T* s_v = bufY + D;
+  const T* vg = v + (int64_t)col * D;
+  if (VLDS)
+    for (int64_t r = threadIdx.x; r < D; r += 1024) s_v[r] = vg[r];
+  const T* vc = VLDS ? s_v : vg;
+  const int K = Kc[col];
+  const T sig = sc[col], tau = sc[nb + col];
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  __syncthreads();  // records in LDS
+  for (int si = threadIdx.x; si < nseg; si += 1024) {
+    const int row0 = s_rec[si * RW], len = s_rec[si * RW + 1];
+    for (int j = 0; j < len; ++j) s_rowseg[row0 + j] = (uint16_t)si;
+  }
+  // b_K = a_K v, b_{K+1} = 0
+  const T aK = A[(int64_t)K * nb + col];
+  for (int64_t r = threadIdx.x; r < D; r += 1024) {
+    bufX[r] = aK * vg[r];
+    bufY[r] = T(0);
+  }
+  __syncthreads();
+  T* cur = bufX;  // b_{i+1}
+  T* prv = bufY;  // b_{i+2}, overwritten by b_i
+  T a_next = K >= 1 ? A[(int64_t)(K - 1) * nb + col] : T(0);
+  for (int i = K - 1; i >= 0; --i) {
+    const bool last = i == 0;
+    const T h = last ? T(0.5) : T(1);
+    // this step's coefficient was read one step ahead
+    const T ai = a_next;
+    if (i >= 1) a_next = A[(int64_t)(i - 1) * nb + col];
+    for (int64_t r = threadIdx.x; r < D; r += 1024) {
+      const int si = s_rowseg[r];
+      const u4* rq = reinterpret_cast<const u4*>(s_rec + si * RW);
+      const u4 w0 = rq[0], w1 = rq[1], w2 = rq[2], w3 = rq[3], w4 = rq[4];
+      const int row0 = (int)w0[0], lidx = (int)w0[2], flags = (int)w0[3];
+      const int d_join = (int)w1[1], d_pbc = (int)w1[2];
+      int dh[NH > 0 ? NH : 1];
+#pragma unroll
+      for (int b = 0; b < NH; ++b) {
+        const int k = 10 + b;  // word k of the record
+        const u4 q4 = k < 12 ? w2 : (k < 16 ? w3 : w4);
+        dh[b] = (int)q4[k & 3];
+      }
+      const int hi0 = flags & 1, hitop = (flags >> 1) & 1, st = (flags >> 12) & 1023;
+      const int jj = (int)r - row0, blk0 = row0 - st;
+      const int q = lidx + jj;
+      const int l = s_lo[q];
+      const u4 np = s_np[q];
+      // every operand first, then the sums
+      const T bo = cur[r], bp = prv[r], vr = vc[r], dsg = s_dseg[si];
+      T nbv[NL > 0 ? NL : 1], hv[NH > 0 ? NH : 1];
+#pragma unroll
+      for (int b = 0; b < NL; ++b) nbv[b] = cur[blk0 + (int)((np[b >> 2] >> (8 * (b & 3))) & 255u)];
+#pragma unroll
+      for (int b = 0; b < NH; ++b) hv[b] = cur[r + dh[b]];  // an idle bond reads the row itself
+      const bool act_j = ((l >> (Lb - 1)) & 1) != hi0;
+      const bool act_p = c.periodic && ((l & 1) != hitop);
+      const T tj = cur[min(blk0 + d_join + (int)((np[2] >> 8) & 255u), (int)D - 1)];
+      const T tp = cur[min(blk0 + d_pbc + (int)((np[2] >> 16) & 255u), (int)D - 1)];
+      T hop = 0;
+#pragma unroll
+      for (int b = 0; b < NL; ++b) hop += nbv[b];
+      const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+      hop -= (T)(NL - __popc(xlo)) * bo;
+#pragma unroll
+      for (int b = 0; b < NH; ++b) hop += dh[b] != 0 ? hv[b] : T(0);
+      hop += act_j ? tj : T(0);
+      const int n11x = ((l >> (Lb - 1)) & 1 & hi0) + (c.periodic ? (hitop & l & 1) : 0);
+      const T dg =
+          vzz * (T)(__popc(l & (l >> 1)) + n11x) + s_fa[l & 31] + s_fa[32 + (l >> 5)] + dsg;
+      const T acc = dg * bo + t_in * hop + (act_p ? t_pb * tp : T(0));
+      const T o = h * (sig * acc + tau * bo) - bp + ai * vr;
+      if (last)
+        w[(int64_t)col * D + r] = o;
+      else
+        prv[r] = o;
+    }
+    __syncthreads();  // b_i complete before it is read as b_{i+1}
+    T* t = cur;
+    cur = prv;
+    prv = t;
+  }
+  if (K == 0)
+    for (int64_t r = threadIdx.x; r < D; r += 1024) w[(int64_t)col * D + r] = A[col] * vg[r];
+}
+
+// LDS bytes of the resident filter with nv vectors of D in LDS.
+template <typename T>
+size_t lds_filter_bytes(const polfed_op* op0, int nv = 2) {
+  const int Lb = std::min(kChainLoBits, op0->L / 2);
+  return chain_blob_bytes(1 << Lb, (int)sizeof(T)) + 64 * sizeof(T) +
+         (size_t)((op0->split_nseg + 1) & ~int64_t(1)) * sizeof(T) +
+         (size_t)op0->split_nseg * kChainRecWords * 4 + (size_t)((op0->D + 7) & ~int64_t(7)) * 2 +
+         (size_t)nv * op0->D * sizeof(T);
+}
+
+template <typename T>
+bool chain_lds_filter_fits(const polfed_op* op0) {
+  return op0->L <= 16 && op0->split_nseg > 0 && lds_filter_bytes<T>(op0) <= kLdsPerCU &&
+         op0->split_Lb <= 8;
+}
+
+template <typename T>
+void chain_lds_filter(hipStream_t s, const ChainBatch& bt, const T* A, const int* Kc, const T* v,
+                      T* w) {
+  const polfed_op* op0 = bt.ops[0];
+  REQUIRE(chain_lds_filter_fits<T>(op0), "batch: chain too long for the LDS-resident filter");
+  const bool f64 = sizeof(T) == 8;
+  ChainSplitDev c = op0->chain_split();
+  const T* fab = (const T*)(f64 ? bt.fab64.get() : bt.fab32.get());
+  const T* dseg = (const T*)(f64 ? bt.dseg64.get() : bt.dseg32.get());
+  const T* sc = (const T*)(f64 ? bt.sc64.get() : bt.sc32.get());
+  const bool vlds = lds_filter_bytes<T>(op0, 3) <= kLdsPerCU;
+  const size_t shm = lds_filter_bytes<T>(op0, vlds ? 3 : 2);
+  switch (op0->L) {
+#define POLFED_CASE(LL)                                                                         \
+  case LL:                                                                                      \
+    if (vlds)                                                                                   \
+      hipLaunchKernelGGL((k_chain_lds_filter<T, LL, true>), dim3((unsigned)bt.nb), dim3(1024),  \
+                         shm, s, c, bt.nb, fab, dseg, sc, A, Kc, v, w, c.rec);                  \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_chain_lds_filter<T, LL, false>), dim3((unsigned)bt.nb), dim3(1024), \
+                         shm, s, c, bt.nb, fab, dseg, sc, A, Kc, v, w, c.rec);                  \
+    break;
+    POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
+    POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
+    POLFED_CASE(14) POLFED_CASE(15) POLFED_CASE(16)
+#undef POLFED_CASE
+    default: fail(POLFED_ERR_INVALID, "batch: chain too long for the LDS-resident filter");
+  }
+  HIPC(hipGetLastError());
+}
+
+template bool chain_lds_filter_fits<double>(const polfed_op*);
+template bool chain_lds_filter_fits<float>(const polfed_op*);
+template void chain_lds_filter<double>(hipStream_t, const ChainBatch&, const double*, const int*,
+                                       const double*, double*);
+template void chain_lds_filter<float>(hipStream_t, const ChainBatch&, const float*, const int*,
+                                      const float*, float*);
+
 static int batch_bpc_fit(size_t shm) { return std::max(1, (int)(kLdsPerCU / shm)); }
 
 template <typename T, int L>
@@ -510,7 +697,7 @@ void ChainBatch::set_scale(const double* E_c, const double* dE) {
 // Multi-column step variants: 0 and 1 the column-major kernel with 16 and
 // 8 columns per launch, 2 and 3 the interleaved kernel with 2 and 4
 // workgroups per compute unit.
-constexpr int kBatchVariants = 5;
+constexpr int kBatchVariants = 6;
 
 static bool interleaved_fits(const ChainBatch& bt, size_t tb) {
   return (uint64_t)bt.ops[0]->D * (uint64_t)bt.nb * tb < (uint64_t(1) << 32) - 64;
@@ -606,6 +793,31 @@ int batch_variant(hipStream_t s, const ChainBatch& bt) {
       // operator picks its own kernel first, outside any capture
       if (op0->L < 22) continue;
       for (int c = 0; c < bt.nb; ++c) op_tune(s, bt.ops[c], sizeof(T) == 4);
+    }
+    if (var == 5) {
+      // the whole filter: time 16 steps, compare per step
+      if (!chain_lds_filter_fits<T>(op0)) continue;
+      constexpr int K5 = 16;
+      DevBuf A5((size_t)(K5 + 1) * bt.nb * sizeof(T)), K5d(bt.nb * sizeof(int));
+      HIPC(hipMemsetAsync(A5.get(), 0, A5.bytes(), s));
+      std::vector<int> kh(bt.nb, K5);
+      HIPC(hipMemcpyAsync(K5d.get(), kh.data(), kh.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      HIPC(hipStreamSynchronize(s));
+      const float us = replay_time_us(
+                           [&](hipStream_t ts) {
+                             chain_lds_filter<T>(ts, bt, A5.as<T>(), K5d.as<int>(), bv.as<T>(),
+                                                 b2.as<T>());
+                           },
+                           4) /
+                       K5;
+      if (verbose())
+        std::fprintf(stderr, "[polfed] batch step L=%d nb=%d %s variant 5: %.2f us per step\n",
+                     op0->L, bt.nb, sizeof(T) == 8 ? "fp64" : "fp32", us);
+      if (us < best_us) {
+        best_us = us;
+        best = 5;
+      }
+      continue;
     }
     const float us = replay_time_us(
         [&](hipStream_t ts) {

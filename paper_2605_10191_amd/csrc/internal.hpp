@@ -422,10 +422,19 @@ void chain_batch_step(hipStream_t s, const ChainBatch& bt, int64_t ld, bool fina
 // columns per launch), 2, 3 interleaved blocks (element (r, c) at r nb + c;
 // 2 or 4 workgroups per compute unit), 4 column-major blocks with every
 // column stepped by its operator's own tuned single-column kernel (the
-// staged-tile kernels of long chains).  Not while the stream is captured
-// (returns 0 then, without keeping it).
+// staged-tile kernels of long chains), 5 the LDS-resident whole filter
+// (one workgroup per column; short chains).  Not while the stream is
+// captured (returns 0 then, without keeping it).
 template <typename T>
 int batch_variant(hipStream_t s, const ChainBatch& bt);
+// Variant 5: the whole filter of every column in LDS (one workgroup per
+// column, a barrier between steps), for short chains.  A: (Kmax + 1) x nb
+// coefficients, Kc: device int32 orders; v, w column-major D x nb.
+template <typename T>
+bool chain_lds_filter_fits(const polfed_op* op0);
+template <typename T>
+void chain_lds_filter(hipStream_t s, const ChainBatch& bt, const T* A, const int* Kc, const T* v,
+                      T* w);
 // One step with variant var; v column-major (column stride D) when vcm,
 // else in the variant's layout; out column-major when ocm.
 template <typename T>

@@ -88,6 +88,7 @@ struct BatchCoef {
   int nb = 0, Kmax = 0;
   std::vector<double> host;  // (Kmax + 1) x nb, column c of row i = a_c[i]
   std::vector<int> K;        // each column's own order
+  DevBuf dK;                 // the same on the device (int32)
   void set(hipStream_t s, int nb, const double* const* a, const int* K);
 };
 

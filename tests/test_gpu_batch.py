@@ -76,13 +76,14 @@ def filter_tol(K, prec):
                                      (("xxz", 10, 18), list(range(40, 58)))],
                          ids=lambda c: "-".join(map(str, c[:3])) if isinstance(c[0], str) else "K")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [-1, 0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2, 3, 5])
 def test_filter_apply_batch_matches_oracle(pk, ctx, case, Ks, prec, variant):
     """Every column of the batched filter against the oracle's filter of its
     own Hamiltonian, element by element, with the tuned multi-column kernel
     and with each variant forced (column-major blocks with 16 or 8 columns
     per launch; interleaved blocks, including a last group narrower than a
-    16-byte access for odd batch widths)."""
+    16-byte access for odd batch widths; the LDS-resident whole filter with
+    each column's own order, K = 0 included)."""
     kind, L, B = case
     say(f"batch filter {case} K={Ks[:4]} {prec} variant {variant}")
     ops, Hs = batch_ops(pk, ctx, kind, L, B)
