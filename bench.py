@@ -79,11 +79,20 @@ def measured_traffic(kernel: str):
     return t.get("bytes_per_launch")
 
 
+# staged-tile variants 6-9: (tile bits below the largest, wrap, double
+# buffer, threads per workgroup), as in the library's table
+WT_CONF = {6: (0, 1, 0, 1024), 7: (1, 1, 1, 512), 8: (1, 1, 0, 512), 9: (0, 1, 1, 1024)}
+
+
 def step_kernel_name(op, prec, tname: str, L: int) -> str:
     """Name of the step-kernel variant in use for a chain operator."""
     var = op.set_kernel(prec, -2)
     Lb = min(10, L // 2)
     kt = min(5, L - Lb - 9)
+    if var in WT_CONF:
+        dkt, wr, db, nt = WT_CONF[var]
+        kw = min(4, L - Lb - 10) - dkt
+        return f"k_chain_wt<{tname}, {L}, {kw}, {wr}, {db}, {nt}>"
     if var == 3:
         return f"k_chain_pair<{tname}, {L}>"
     if var == 4:
@@ -313,6 +322,15 @@ def solve_legs(pk, wl, ctx, L, n_ev, block_sizes=(4, 8)):
     import torch
     res = {}
     op, x0, (_, _, lam, _, _) = xxz_setup(pk, wl, ctx, L, 3.0, 0, n_ev)
+    # the oracle's eigenvalues of this workload, when stored: the solves then
+    # target the oracle's lambda, and each precision's error per eigenpair is
+    # taken against them
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "xxz_L20_W3_eps05.json")
+    if L == 20 and n_ev == 100 and os.path.exists(gpath):
+        with open(gpath) as f:
+            golden = json.load(f)
+        lam = golden["lambda"]
     runs = {}
     for name, prec in (("fp64", pk.FP64), ("fp32_bulk", pk.FP32)):
         torch.cuda.synchronize()
@@ -366,6 +384,15 @@ def solve_legs(pk, wl, ctx, L, n_ev, block_sizes=(4, 8)):
         err = np.abs(np.sort(e32) - np.sort(e64)) / np.maximum(np.abs(np.sort(e64)), 1.0)
         res["fp32_vs_fp64_rel_err"] = {"max": float(err.max()), "median": float(np.median(err)),
                                        "per_pair": [float(x) for x in err]}
+    if golden is not None:
+        eg = np.asarray(golden["eigenvalues_nearest"])
+        for name, e in runs.items():
+            if len(e) == n_ev:
+                err = np.abs(e - eg) / np.maximum(np.abs(eg), 1.0)
+                res[f"{name}_vs_oracle_rel_err"] = {"max": float(err.max()),
+                                                    "median": float(np.median(err)),
+                                                    "per_pair": [float(x) for x in err]}
+        res["oracle"] = "tests/golden/xxz_L20_W3_eps05.json (CPU oracle, same workload)"
     res["workload"] = (f"XXZ L={L} W=3 seed 0 (D={op.D}), {n_ev} pairs at normalized "
                        "energy 0.5, full solve")
     return res
@@ -475,7 +502,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=1.0,
                     help="arrival rate as a multiple of the single-stream capacity")
     ap.add_argument("--profile-only", action="store_true",
-                    help="run only the step kernel and a plain copy (counter runs)")
+                    help="run only the step kernels and a plain copy (counter runs)")
+    ap.add_argument("--variants", default="",
+                    help="with --profile-only: step-kernel variants to run in turn "
+                         "(comma list; default: the autotuned one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -491,17 +521,32 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     ctx = pk.Context(0)
     if args.profile_only:
-        # counter runs: the step kernel alone, then a plain copy of known size
+        # counter runs: the tuned FP64 step kernel of the headline chain and
+        # of the t-V L=26 chain (a working set beyond the 256 MB last-level
+        # cache), then a plain copy of known size for the counters' scale
+        # (--variants: the step-kernel variants to run, each in turn, so that
+        # the counters cover every kernel the autotuner may pick)
+        variants = [int(x) for x in args.variants.split(",")] if args.variants else [-1]
         h = wl.xxz_fields(args.L, args.W, 0)
         op = pk.Operator.xxz(ctx, args.L, args.L // 2, 1.0, 1.0, h, True)
-        avg_ms, _ = pk.profile_step(op, pk.FP64, args.profile_iters)
+        op26 = pk.Operator.tv(ctx, 26, 13, 1.0, 1.0, wl.tv_onsite(26, 0), True)
+        for var in variants:
+            for o, LL, it in ((op, args.L, args.profile_iters),
+                              (op26, 26, max(20, args.profile_iters // 4))):
+                if var >= 0:
+                    o.set_kernel(pk.FP64, var)
+                avg_ms, _ = pk.profile_step(o, pk.FP64, it)
+                log(f"profile-only: {step_kernel_name(o, pk.FP64, 'double', LL)} "
+                    f"{avg_ms * 1e3:.2f} us")
+        op.close()
+        op26.close()
         n = 64 * 1024 * 1024  # 512 MiB of FP64
         x = torch.ones(n, dtype=torch.float64, device=ctx.torch_device)
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
-        log(f"profile-only: step kernel {avg_ms * 1e3:.2f} us; copied {n * 8} bytes x3")
+        log(f"profile-only: copied {n * 8} bytes x3")
         return
     t0 = time.time()
     op, x0, (E_min, E_max, lam, n_want, plan) = xxz_setup(
@@ -561,7 +606,12 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kernel_name),
                 "kernel": kernel_name,
-                "kernel_ms_avg": round(avg_ms, 5), "kernel_ms_min": round(min_ms, 5),
+                "kernel_ms_avg": round(avg_ms, 5),
+                "kernel_ms_isolated": round(min_ms, 5),
+                "timing": "kernel_ms_avg: HIP events on the kernel's stream around "
+                          f"{args.profile_iters} back-to-back launches, as the recurrence "
+                          "runs them; kernel_ms_isolated: the fastest of 20 single launches, "
+                          "each between its own event pair (includes the launch gap)",
                 "bytes_per_launch": step_bytes}
     log(f"step kernel {avg_ms * 1e3:.2f} us avg -> {achieved:.0f} GB/s")
 
