@@ -83,11 +83,15 @@ def rayleigh_ritz(H, U: np.ndarray):
 
 def select_nearest(E: np.ndarray, res: np.ndarray, lam: float, n_ev: int,
                    tol_resid: float):
-    """Indices of the n_ev accepted pairs (residual <= tol_resid) nearest to
-    lam, ordered by (|E - lam|, E)."""
-    ok = np.flatnonzero(res <= tol_resid)
-    order = ok[np.lexsort((E[ok], np.abs(E[ok] - lam)))]
-    return order[:n_ev]
+    """Indices of the accepted pairs (residual <= tol_resid) among the n_ev
+    Ritz pairs nearest to lam, ordered by (|E - lam|, E), up to the first
+    nearest pair that is not accepted yet: an unconverged pair nearer to
+    lam than an accepted one is not skipped, so n_ev indices come back only
+    when the n_ev nearest pairs are all accepted."""
+    order = np.lexsort((E, np.abs(E - lam)))[:n_ev]
+    ok = res[order] <= tol_resid
+    run = len(order) if np.all(ok) else int(np.argmin(ok))
+    return order[:run]
 
 
 def complete(E_sel: np.ndarray, lam: float, theta_min: float, P_at, E_c: float,

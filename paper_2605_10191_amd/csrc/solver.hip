@@ -322,22 +322,30 @@ void rayleigh_ritz(hipStream_t s, int64_t D, int n, const double* U, const doubl
   ex.HU2 = std::move(HU2);
 }
 
-// The n_ev accepted pairs nearest lambda, ordered by (|E - lambda|, E), and
-// the check that no nearer eigenvalue can be missing: the filter at the
-// farthest selected energy must not fall below the smallest converged
-// P-Ritz value theta_min.
+// The n_ev pairs nearest lambda, ordered by (|E - lambda|, E), once they are
+// all accepted, and the check that no nearer eigenvalue can be missing: the
+// filter at the farthest selected energy must not fall below the smallest
+// converged P-Ritz value theta_min.
 void select_pairs(Extracted& ex, double lam, int n_ev, double tol_resid, double theta_min,
                   const polfed_plan& pl) {
   const int n = (int)ex.E.size();
-  std::vector<int> ok;
-  for (int j = 0; j < n; ++j)
-    if (ex.res[j] <= tol_resid) ok.push_back(j);
-  std::stable_sort(ok.begin(), ok.end(), [&](int a, int b) {
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     const double da = std::fabs(ex.E[a] - lam), db = std::fabs(ex.E[b] - lam);
     if (da != db) return da < db;
     return ex.E[a] < ex.E[b];
   });
-  if ((int)ok.size() > n_ev) ok.resize(n_ev);
+  // the leading accepted run of the n_ev nearest Ritz pairs: a pair nearer
+  // to lambda than an accepted one but not converged yet is not skipped (the
+  // selection would otherwise take a farther pair in its place, and the
+  // completeness test, which argues only about the extracted values, would
+  // not notice)
+  std::vector<int> ok;
+  for (int q = 0; q < std::min(n_ev, n); ++q) {
+    if (ex.res[order[q]] > tol_resid) break;
+    ok.push_back(order[q]);
+  }
   ex.sel = ok;
   ex.complete = false;
   if ((int)ok.size() == n_ev && n_ev > 0) {

@@ -72,6 +72,7 @@ def filter_tol(K, prec):
 
 @pytest.mark.parametrize("case,Ks", [(("xxz", 12, 3), [300, 281, 150]),
                                      (("xxz", 14, 4), [700, 0, 1, 2]),
+                                     (("xxz", 14, 1), [573]),
                                      (("tv", 12, 2), [400, 400]),
                                      (("xxz", 10, 18), list(range(40, 58)))],
                          ids=lambda c: "-".join(map(str, c[:3])) if isinstance(c[0], str) else "K")

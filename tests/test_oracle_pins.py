@@ -380,3 +380,20 @@ def test_planted_boundary_sign_mistake_is_caught(monkeypatch):
                         lambda s, a, b: np.ones(len(s)))
     with pytest.raises(AssertionError):
         test_tv_without_interaction_is_free_fermions(10, 4)
+
+
+def test_select_nearest_does_not_skip_an_unconverged_nearer_pair():
+    """The selection takes the n_ev Ritz pairs nearest lambda and returns only
+    their leading accepted run: a nearer pair that has not converged yet
+    stops it (a farther accepted pair never takes its place); equal
+    distances are ordered by E."""
+    from oracle import lanczos
+    E = np.array([0.1, -0.05, 0.3, 0.2, -0.1])
+    res = np.array([1e-9, 1e-6, 1e-9, 1e-9, 1e-9])
+    assert lanczos.select_nearest(E, res, 0.0, 3, 1e-8).tolist() == []
+    res[1] = 1e-9
+    assert lanczos.select_nearest(E, res, 0.0, 3, 1e-8).tolist() == [1, 4, 0]
+    res[0] = 1e-7  # the third nearest (0.1) unconverged: the run stops there
+    assert lanczos.select_nearest(E, res, 0.0, 4, 1e-8).tolist() == [1, 4]
+    res[0] = 1e-9
+    assert lanczos.select_nearest(E, res, 0.0, 10, 1e-8).tolist() == [1, 4, 0, 3, 2]
