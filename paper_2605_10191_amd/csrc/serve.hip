@@ -7,8 +7,10 @@
 //      at submission), running their bounds and plan;
 //   2. groups the running solves by operator pattern and precision; each
 //      group filters the current Lanczos vector of all its members as one
-//      multi-column recurrence, then every member takes its own Lanczos step
-//      (reorthogonalization, convergence check, extraction);
+//      multi-column recurrence on the group's stream, then every member takes
+//      its own Lanczos step (reorthogonalization, convergence check,
+//      extraction) on its own stream, the members of the round side by side
+//      on a pool of host threads;
 //   3. retires the members that finished, which frees their slots and bytes
 //      for the next admissions.
 // Requests thus join and leave a running batch between Lanczos iterations,
@@ -19,6 +21,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -37,6 +40,8 @@ struct polfed_req {
   size_t held = 0;          // bytes reserved now (admission plus grants)
   size_t held_max = 0;      // the most ever reserved
   size_t prepaid = 0;       // part of footprint learned from an eviction
+  polfed_ctx* own = nullptr;  // the request's context (own stream) while admitted
+  hipEvent_t ready = nullptr;  // on own's stream: v_k written, w free
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::mutex m;
   std::condition_variable cv;
@@ -64,10 +69,19 @@ struct Server {
     BatchFilter bf;
   };
   std::map<std::string, Group> groups;
-  // one child context (own stream) per chain pattern, so that groups of
-  // different patterns overlap on the device
+  // one child context (own stream) per chain pattern for the groups' filter
+  // recurrences, so that groups of different patterns overlap on the device
   std::map<std::string, polfed_ctx*> children;
   polfed_ctx* child_for(const polfed_req* r);
+  // host threads that advance the members of a round side by side
+  std::vector<std::thread> pool;
+  std::mutex pm;
+  std::condition_variable pcv, pdone;
+  std::deque<std::function<void()>> jobs;
+  int busy = 0;
+  bool pool_stop = false;
+  void start_pool(int n);
+  void run_all(std::vector<std::function<void()>>& work);
   ~Server();
   void loop();
   void admit();
@@ -83,27 +97,73 @@ static std::string pattern_of(const polfed_op* op) {
   return batchable ? op->pattern_key : std::string("other");
 }
 
+static polfed_ctx* new_child(const polfed_ctx* parent) {
+  auto c = std::make_unique<polfed_ctx>();
+  c->device = parent->device;
+  c->n_cu = parent->n_cu;
+  HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  c->own_stream = true;
+  HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  return c.release();
+}
+
+static void delete_child(polfed_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamDestroy(c->stream);
+  (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
 polfed_ctx* Server::child_for(const polfed_req* r) {
   const std::string key = pattern_of(r->op);
   auto it = children.find(key);
   if (it != children.end()) return it->second;
-  auto c = std::make_unique<polfed_ctx>();
-  c->device = ctx->device;
-  c->n_cu = ctx->n_cu;
-  HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-  c->own_stream = true;
-  HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  return children[key] = c.release();
+  return children[key] = new_child(ctx);
+}
+
+void Server::start_pool(int n) {
+  for (int i = 0; i < n; ++i)
+    pool.emplace_back([this] {
+      (void)hipSetDevice(ctx->device);
+      for (;;) {
+        std::function<void()> job;
+        {
+          std::unique_lock<std::mutex> lk(pm);
+          pcv.wait(lk, [&] { return pool_stop || !jobs.empty(); });
+          if (pool_stop && jobs.empty()) return;
+          job = std::move(jobs.front());
+          jobs.pop_front();
+        }
+        job();  // catches its own errors
+        std::lock_guard<std::mutex> lk(pm);
+        if (--busy == 0) pdone.notify_all();
+      }
+    });
+}
+
+// Runs the jobs on the pool and waits for all of them.
+void Server::run_all(std::vector<std::function<void()>>& work) {
+  if (work.empty()) return;
+  if (pool.empty() || work.size() == 1) {
+    for (auto& f : work) f();
+    return;
+  }
+  std::unique_lock<std::mutex> lk(pm);
+  busy += (int)work.size();
+  for (auto& f : work) jobs.push_back(std::move(f));
+  pcv.notify_all();
+  pdone.wait(lk, [&] { return busy == 0; });
 }
 
 Server::~Server() {
-  for (auto& kv : children) {
-    polfed_ctx* c = kv.second;
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipStreamDestroy(c->stream);
-    (void)hipStreamDestroy(c->cap_stream);
-    delete c;
+  {
+    std::lock_guard<std::mutex> lk(pm);
+    pool_stop = true;
   }
+  pcv.notify_all();
+  for (auto& t : pool) t.join();
+  for (auto& kv : children) delete_child(kv.second);
 }
 
 static std::string group_key(const polfed_req* r) {
@@ -114,6 +174,16 @@ static std::string group_key(const polfed_req* r) {
   std::string k = batchable ? op->pattern_key : "op:" + std::to_string((uintptr_t)op) + ":" +
                                                     std::to_string((uintptr_t)r);
   return k + (r->run->fp32 ? "|f32" : "|f64");
+}
+
+// The request's own context and event, after its solve is gone.
+static void release_own(polfed_req* r) {
+  if (r->ready) {
+    (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
+  }
+  delete_child(r->own);
+  r->own = nullptr;
 }
 
 // Hands an admitted request back to its caller.  Everything the server keeps
@@ -128,6 +198,7 @@ void Server::complete(polfed_req* r, polfed_status st, const std::string& err) {
   if (run) rep.mem_peak = (double)run->tally.peak;
   rep.mem_reserved = (double)r->held_max;
   run.reset();
+  release_own(r);
   {
     std::lock_guard<std::mutex> lk(m);
     active.erase(std::remove(active.begin(), active.end(), r), active.end());
@@ -170,6 +241,7 @@ void Server::give(polfed_req* r, size_t bytes) {
 void Server::evict(polfed_req* r) {
   const size_t need = r->held + r->run->want;
   r->run.reset();
+  release_own(r);
   {
     std::lock_guard<std::mutex> lk(m);
     active.erase(std::remove(active.begin(), active.end(), r), active.end());
@@ -205,7 +277,10 @@ void Server::admit() {
     }
     r->t_admit = now_seconds();
     try {
-      polfed_ctx* cc = child_for(r);
+      (void)child_for(r);  // the pattern's stream for its group filter
+      r->own = new_child(ctx);
+      HIPC(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+      polfed_ctx* cc = r->own;
       // the start vector was written on the caller's stream
       hipEvent_t ready;
       HIPC(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
@@ -218,6 +293,7 @@ void Server::admit() {
       r->run->give = [this, r](size_t b) { give(r, b); };
       TallyScope ts(&r->run->tally);
       r->run->setup(cc, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
+      HIPC(hipEventRecord(r->ready, cc->stream));  // v_0 written
       std::lock_guard<std::mutex> lk(m);
       active.push_back(r);
     } catch (const Error& e) {
@@ -263,13 +339,24 @@ void Server::loop() {
       Group& g = groups[kv.first];
       try {
         if (runs.size() == 1 && kv.first.rfind("op:", 0) == 0) {
+          // a solve of its own: the filter on the request's stream
           TallyScope ts(&runs[0]->tally);
           runs[0]->filter_self();
         } else {
+          // the group's recurrence on the pattern's stream, after every
+          // member's v_k is written (on its own stream), and every member's
+          // Lanczos step after the recurrence has written its w
+          polfed_ctx* gc = child_for(kv.second[0]);
+          for (auto* r : kv.second) HIPC(hipStreamWaitEvent(gc->stream, r->ready, 0));
           // rebuilt whenever a member joined or left (a new solve may reuse
           // a finished one's address, so members are compared by uid)
-          if (!g.bf.same_members(runs)) g.bf.form(runs[0]->ctx, runs);
+          if (!g.bf.same_members(runs)) g.bf.form(gc, runs);
           g.bf.run();
+          hipEvent_t fe;
+          HIPC(hipEventCreateWithFlags(&fe, hipEventDisableTiming));
+          HIPC(hipEventRecord(fe, gc->stream));
+          for (auto* r : kv.second) HIPC(hipStreamWaitEvent(r->own->stream, fe, 0));
+          HIPC(hipEventDestroy(fe));
         }
       } catch (const Error& e) {
         g.bf.forget();
@@ -278,26 +365,48 @@ void Server::loop() {
       }
       launched.push_back({&g, &kv.second});
     }
-    for (auto& gm : launched) {
-      Group& g = *gm.first;
-      std::vector<std::pair<polfed_req*, std::pair<polfed_status, std::string>>> fin;
-      for (auto* r : *gm.second) {
+    // every member of the launched groups takes its Lanczos step
+    // (reorthogonalization on its own stream, then the periodic check and
+    // extraction, which wait for that stream only) on the host thread pool
+    std::vector<polfed_req*> adv;
+    for (auto& gm : launched) adv.insert(adv.end(), gm.second->begin(), gm.second->end());
+    std::vector<std::pair<polfed_status, std::string>> outcome(adv.size());
+    std::vector<char> finished(adv.size(), 0);
+    std::vector<std::function<void()>> work;
+    for (size_t i = 0; i < adv.size(); ++i)
+      work.push_back([&, i] {
+        polfed_req* r = adv[i];
         try {
           TallyScope ts(&r->run->tally);
           r->run->advance();
-          if (r->run->done) fin.push_back({r, {r->run->status, ""}});
+          HIPC(hipEventRecord(r->ready, r->own->stream));  // v_{k+1} written
+          if (r->run->done) {
+            finished[i] = 1;
+            outcome[i] = {r->run->status, ""};
+          }
         } catch (const Error& e) {
-          fin.push_back({r, {e.code, e.what()}});
+          finished[i] = 1;
+          outcome[i] = {e.code, e.what()};
         } catch (const std::exception& e) {
-          fin.push_back({r, {POLFED_ERR_INVALID, e.what()}});
+          finished[i] = 1;
+          outcome[i] = {POLFED_ERR_INVALID, e.what()};
         }
-      }
-      if (!fin.empty()) {
-        g.bf.drain();  // the filter timings of the leaving members
-        for (auto& f : fin) {
-          polfed_report& R = f.first->run->R;
+      });
+    run_all(work);
+    {
+      size_t i = 0;
+      for (auto& gm : launched) {
+        Group& g = *gm.first;
+        bool drained = false;
+        for (size_t q = 0; q < gm.second->size(); ++q, ++i) {
+          if (!finished[i]) continue;
+          if (!drained) {
+            g.bf.drain();  // the filter timings of the leaving members
+            drained = true;
+          }
+          polfed_report& R = adv[i]->run->R;
           R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
-          complete(f.first, f.second.first, f.second.second);
+          complete(adv[i], outcome[i].first, outcome[i].second);
         }
       }
     }
@@ -335,6 +444,7 @@ polfed_status serve_start(polfed_ctx* ctx, size_t budget, int max_cols) {
   s->budget = budget;
   s->max_cols = max_cols;
   ctx->server = s;
+  s->start_pool(std::min(8, std::max(1, max_cols)));
   s->th = std::thread([s] { s->loop(); });
   return POLFED_OK;
 }

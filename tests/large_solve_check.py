@@ -52,7 +52,7 @@ def main():
     print(f"solve done in {dt:.1f}s status={status} K={rep['K']} iters={rep['iters']}",
           flush=True)
     E = ev.cpu().numpy()
-    Uh = U.cpu().numpy().T  # D x n_ev
+    Uh = U.cpu().numpy()  # D x n_ev (column-major pairs)
     del U
     H, _ = models.xxz(L, N, 1.0, 1.0, h)
     res = np.linalg.norm(H @ Uh - Uh * E, axis=0)

@@ -218,3 +218,21 @@ def test_serve_memory_stays_within_reservation(pk, ctx):
         assert 0 < rep["mem_peak"] <= rep["mem_reserved"] <= budget
     # the eta = 0.6 requests outgrew their expected Krylov size
     assert any(results[i][3]["iters"] > results[i][3]["M_alloc"] for i in (1, 3, 4))
+
+
+@pytest.mark.parametrize("variant", [0, 3, 5])
+def test_served_fp32_request_alone_with_each_batch_kernel(pk, ctx, variant):
+    """An FP32-bulk request served alone (a one-column group) with each
+    multi-column kernel forced for its recurrence: the result is the dense
+    oracle's 20 nearest pairs.  (With one of them a refinement sweep once
+    accepted the 21st-nearest pair in place of a nearer one that had not
+    converged yet; the selection now takes the nearest pairs only once they
+    are all accepted.)"""
+    say(f"served FP32 alone, batch kernel {variant}")
+    op, H = make(pk, ctx, "xxz", 14, 1.0, 0)
+    op.set_batch_kernel(1, pk.FP32, variant)
+    x0 = dev(wl.start_vector(op.D, 0))
+    with pk.Server(ctx, 8 << 30, max_cols=2) as srv:
+        res = srv.submit(op, x0, 20, 0.5, "normalized", precision=pk.FP32).wait()
+    check(H, 20, res)
+    say(f"   sweeps {res[3]['refine_sweeps']} iters {res[3]['iters']}")
