@@ -398,9 +398,11 @@ def solve_legs(pk, wl, ctx, L, n_ev, block_sizes=(4, 8)):
     return res
 
 
-def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate=1.0):
+def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate=1.0,
+                arrival=None):
     """A Poisson stream through the server; arrival rate = `rate` times the
-    measured single-stream capacity (mean service time of one request per L).
+    measured single-stream capacity (mean service time of one request per L),
+    or `arrival` requests per second when given (inf: all at once).
     Latency runs from each request's planned arrival to its result."""
     import torch
     n_ev = 50
@@ -422,7 +424,10 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
         svc.append(time.perf_counter() - t0)
         log(f"serving capacity: L={L} alone {svc[-1]:.2f}s {st} K={rep['K']} iters={rep['iters']}")
     mean_svc = float(np.mean(svc))
-    stream = wl.serving_stream(n_req, seed, mean_svc / rate)
+    rate_given = arrival is None
+    if arrival is None:
+        arrival = rate / mean_svc
+    stream = wl.serving_stream(n_req, seed, 1.0 / arrival)
     reqs = []
     with pk.Server(ctx, int(budget_gb * (1 << 30)), max_cols=max_cols) as srv:
         t_start = time.perf_counter()
@@ -455,6 +460,27 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
     used = {}
     for (r, _, _, _), res in zip(reqs, results):
         used.setdefault(f"L={r['L']}", set()).add(label[res[3]["precision"]])
+    by_L = {}
+    for L in (14, 16, 18):
+        idx = [i for i, (r, _, _, _) in enumerate(reqs) if r["L"] == L]
+        if idx:
+            lz = [lat[i] for i in idx]
+            # device seconds of the requests' filter applications (a batched
+            # application's time split over its columns) and reorthogonalization
+            by_L[f"L={L}"] = {"n": len(idx),
+                              "p50_ms": round(1e3 * float(np.percentile(lz, 50)), 1),
+                              "p99_ms": round(1e3 * float(np.percentile(lz, 99)), 1),
+                              "filter_gpu_s": round(sum(results[i][3]["t_filter"]
+                                                        for i in idx), 2),
+                              "reorth_gpu_s": round(sum(results[i][3]["t_reorth"]
+                                                        for i in idx), 2),
+                              "iters": int(sum(results[i][3]["iters"] for i in idx))}
+    if math.isinf(arrival):
+        desc = "all requests submitted at once (saturation)"
+    elif rate_given:
+        desc = f"Poisson arrivals at {rate:g}x the single-stream capacity"
+    else:
+        desc = f"Poisson arrivals at {arrival:g} requests/s"
     return {"requests": n_req, "ok": int(ok), "n_ev": n_ev,
             "precision": label[precision],
             "precision_used": {k: sorted(v) for k, v in sorted(used.items())},
@@ -463,13 +489,16 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
             "mean_ms": round(1e3 * float(lat.mean()), 1),
             "throughput_req_per_s": round(n_req / (t_end - t_start), 3),
             "single_stream_service_s": [round(x, 3) for x in svc],
-            "arrival_rate_per_s": round(rate / mean_svc, 3),
+            "arrival_rate_per_s": None if math.isinf(arrival) else round(arrival, 3),
+            "latency_by_L": by_L,
+            "max_resid": float(max((float(res[2].max().item()) for res in results
+                                    if len(res[2])), default=float("nan"))),
+            "wall_s": round(t_end - t_start, 2),
             "max_queue_s": round(max(res[3]["t_queue"] for res in results), 3),
             "max_submit_delay_s": round(float(delay.max()), 3),
             "fp32_fallbacks": int(sum(res[3]["fp32_fallback"] for res in results)),
             "hbm_budget_GiB": budget_gb, "max_cols": max_cols,
-            "stream": "L in {14,16,18}, W in {1,3,5} uniform, Poisson arrivals at "
-                      f"{rate:g}x the single-stream capacity"}
+            "stream": "L in {14,16,18}, W in {1,3,5} uniform, " + desc}
 
 
 def main():
@@ -501,6 +530,14 @@ def main():
                     help="serve the stream with the automatic precision only")
     ap.add_argument("--serve-rate", type=float, default=1.0,
                     help="arrival rate as a multiple of the single-stream capacity")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream(s) and print their results")
+    ap.add_argument("--serve-precision", default="auto,fp32",
+                    help="with --serve-only: precisions to serve the stream with "
+                         "(comma list of auto, fp32, fp64)")
+    ap.add_argument("--serve-arrival", type=float, default=None,
+                    help="with --serve-only: arrival rate in requests/s (inf: all at "
+                         "once), in place of --serve-rate")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the step kernels and a plain copy (counter runs)")
     ap.add_argument("--variants", default="",
@@ -520,6 +557,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     ctx = pk.Context(0)
+    if args.serve_only:
+        names = {"auto": pk.AUTO, "fp32": pk.FP32, "fp64": pk.FP64}
+        out = {"mode": "serve-only", "serving": {}}
+        for name in args.serve_precision.split(","):
+            sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
+                             args.serve_cols, names[name], rate=args.serve_rate,
+                             arrival=args.serve_arrival)
+            out["serving"][name] = sv
+            log(f"serving {name}: {sv}")
+        print(json.dumps(out))
+        return
     if args.profile_only:
         # counter runs: the tuned FP64 step kernel of the headline chain and
         # of the t-V L=26 chain (a working set beyond the 256 MB last-level

@@ -92,9 +92,12 @@ int polfed_version(void);
 const char* polfed_last_error(void);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is the hipStream_t
- * the context borrows for all its work; NULL is the device's null stream, so
- * that library work is ordered with other work queued there (e.g. torch's
- * default stream).  Fails with POLFED_ERR_NODEVICE when no GPU is visible. */
+ * the context borrows for all its work.  NULL asks for ordering with the
+ * device's null stream (e.g. torch's default stream): the context then
+ * creates a blocking stream of its own, which the null stream and it wait on
+ * each other through (the library queues nothing on the null stream itself,
+ * which would break the graph captures its server runs beside it).  Fails
+ * with POLFED_ERR_NODEVICE when no GPU is visible. */
 polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out);
 /* Stops a running server, waits for the context's work and frees the
  * context; its operators must not be used afterwards (NULL is a no-op). */
@@ -225,7 +228,12 @@ polfed_status polfed_op_set_kernel(polfed_op* op, int precision, int variant, in
  * kernels, L >= 22), 5 = the LDS-resident filter (one workgroup per column
  * runs the column's whole recurrence with both Clenshaw vectors in LDS and
  * a barrier between steps; where two vectors fit: FP64 to L = 14, FP32 to
- * L = 16 at half filling); -2 only reports.
+ * L = 16 at half filling), 6 / 7 = row-group kernel on the interleaved
+ * blocks (the 16-byte column groups of a row on neighbouring lanes, so a
+ * wavefront reads whole rows; up to 32 FP64 or 64 FP32 columns; 4 / 8
+ * workgroups per compute unit); -2 only reports.  A batch whose pattern was
+ * timed before (any operator of it, same width and precision) takes that
+ * pick without timing again.
  * *chosen (may be NULL) receives the variant in use (-1 while not tuned). */
 polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, int variant,
                                          int* chosen);
@@ -452,8 +460,10 @@ typedef struct {
   double E_min, E_max; /* both 0: compute the bounds */
   int graph;           /* filter recurrence as one HIP graph: 0 = pick the
                           faster of direct launches and graph replay on the
-                          first two filter applications, 1 = always graph,
-                          2 = never */
+                          first two filter applications (a multi-column
+                          filter reuses the pick of an earlier batch of the
+                          same chain pattern, width, precision and order to a
+                          factor of two), 1 = always graph, 2 = never */
   int refine_max;      /* FP32 bulk: at most this many refinement sweeps
                           (0: 16; -1: none); a refinement that stalls or
                           runs out hands the solve to the FP64 filter */
@@ -522,8 +532,10 @@ polfed_status polfed_solve_batch(polfed_ctx* ctx, int B,
 /* --------------------------------------------------------------- serving
  * Continuous batching: requests are admitted while the HBM their Krylov
  * bases need fits the budget and a column slot is free; admitted requests of
- * the same operator class (same chain pattern) share one multi-column
- * filter recurrence, and each leaves the batch as soon as it converges. */
+ * the same operator class (same chain pattern and precision) share one
+ * multi-column filter recurrence, and each leaves the batch as soon as it
+ * converges.  Each class runs its rounds (recurrence, then every member's
+ * Lanczos step) on its own stream at its own pace. */
 polfed_status polfed_serve_start(polfed_ctx* ctx, size_t hbm_budget_bytes,
                                  int max_cols);
 /* Queues a solve; op, x0 and the output buffers must stay alive until
@@ -531,8 +543,10 @@ polfed_status polfed_serve_start(polfed_ctx* ctx, size_t hbm_budget_bytes,
  * rejected (POLFED_ERR_REJECTED); block_size must be 0 or 1.  With
  * POLFED_PRECISION_AUTO the precision is chosen at admission and the request
  * reserves the larger of the two footprints.  Calls on ctx from other
- * threads while the server runs wait for at most the server's current round
- * of work. */
+ * threads while the server runs: those that only build new objects (basis
+ * calls, operator constructors, polfed_gemm_nn/tn) run beside the server's
+ * rounds; the others wait until the rounds in flight have ended (at most one
+ * round of each group) and run before the next ones start. */
 polfed_status polfed_submit(polfed_ctx* ctx, const polfed_op* op,
                             const polfed_params* params, const double* x0,
                             double* evals, double* evecs, double* resid,

@@ -156,6 +156,12 @@ void BatchFilter::forget() {
 
 BatchFilter::~BatchFilter() { forget(); }
 
+std::string BatchFilter::graph_choice_key() const {
+  int lg = 0;
+  while ((2 << lg) <= std::max(co.Kmax, 1)) ++lg;
+  return "bgraph" + std::to_string(co.nb) + (fp32 ? "|32|" : "|64|") + std::to_string(lg);
+}
+
 void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
   drain();
   ctx = c;
@@ -189,6 +195,12 @@ void BatchFilter::form(polfed_ctx* c, const std::vector<SolveRun*>& runs) {
   mode = kTimeDirect;
   if (graph_pref == 2 || co.Kmax < 8 || co.Kmax > kGraphMaxSteps) mode = kDirect;
   if (graph_pref == 1 && mode == kTimeDirect) mode = kGraph;
+  if (mode == kTimeDirect) {
+    // the way an earlier batch of this pattern, width, precision and order
+    // (to a factor of two) chose
+    const int v = pattern_choice(ops[0], graph_choice_key());
+    if (v >= 0) mode = v == 1 ? kGraph : kDirect;
+  }
   const int64_t D = ops[0]->D;
   const size_t tb = fp32 ? sizeof(float) : sizeof(double);
   const size_t need = (size_t)D * nb * tb;
@@ -265,6 +277,7 @@ void BatchFilter::run() {
   } else if (mode == kTimeGraph) {
     mode = ms < t_direct_ms ? kGraph : kDirect;
     if (mode == kDirect) graph.reset();
+    pattern_choice_set(bt.ops[0], graph_choice_key(), mode == kGraph ? 1 : 0);
     if (verbose())
       std::fprintf(stderr, "[polfed] batch filter nb=%d K=%d: direct %.3f ms, graph %.3f ms -> %s\n",
                    nb, co.Kmax, t_direct_ms, ms, mode == kGraph ? "graph" : "direct");

@@ -1,7 +1,9 @@
 // extern "C" entry points of polfed.h: argument checks, error capture and
 // dispatch to the library internals.  No exception crosses this boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "internal.hpp"
@@ -44,18 +46,167 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 
 thread_local MemTally* g_mem_tally = nullptr;
 
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) HIPC(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// ------------------------------------------------------ device memory ----
+// hipFree waits until everything queued on the device has finished, so a
+// buffer released in the middle of other streams' work (a server round, a
+// retiring request) would stall all of them.  Released blocks are therefore
+// kept per device and handed out again once the device has passed the
+// release: at release an event is recorded on every stream the library
+// queues work on, and a cached block is reused only when all its events have
+// completed.  Blocks go back to hipFree only when the cache would exceed its
+// cap, or to make room when an allocation fails.  Sizes are rounded to
+// buckets (powers of two up to 1 MiB, then 2 MiB multiples) so that blocks
+// of a repeating workload fit each other.
+namespace {
+struct CachedBlock {
+  void* p;
+  std::vector<hipEvent_t> fence;
+};
+struct DevicePool {
+  std::mutex mu;
+  std::vector<hipStream_t> streams;  // work streams (one entry per registration)
+  std::multimap<size_t, CachedBlock> blocks;  // by bucket size
+  std::vector<hipEvent_t> spare;             // events of reused blocks
+  size_t cached = 0, cap = 0;
+};
+
+DevicePool& device_pool(int dev) {
+  static std::mutex m;
+  // never destroyed: blocks cached at exit are returned with the process
+  static auto* pools = new std::map<int, DevicePool*>();
+  std::lock_guard<std::mutex> lk(m);
+  DevicePool*& p = (*pools)[dev];
+  if (!p) {
+    p = new DevicePool();
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      tot = (size_t)16 << 30;
+    }
+    p->cap = std::min<size_t>(tot / 8, (size_t)32 << 30);
+  }
+  return *p;
+}
+
+size_t bucket_of(size_t b) {
+  if (b <= 256) return 256;
+  if (b <= ((size_t)1 << 20)) {
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t g = (size_t)2 << 20;
+  return (b + g - 1) / g * g;
+}
+
+// Makes dev current for the scope without throwing (release paths run in
+// destructors).
+struct QuietDevice {
+  int prev = -1;
+  explicit QuietDevice(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+    (void)hipGetLastError();
+  }
+  ~QuietDevice() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool fence_passed(const CachedBlock& c) {
+  for (hipEvent_t e : c.fence) {
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipSuccess) continue;
+    (void)hipGetLastError();  // a pending event is no error of a later call
+    return false;
+  }
+  return true;
+}
+
+// Waits for the device and frees every cached block (pool lock held).
+void flush_pool(DevicePool& P) {
+  (void)hipDeviceSynchronize();
+  for (auto& kv : P.blocks) {
+    (void)hipFree(kv.second.p);
+    for (hipEvent_t e : kv.second.fence) P.spare.push_back(e);
+  }
+  P.blocks.clear();
+  P.cached = 0;
+  (void)hipGetLastError();
+}
+}  // namespace
+
+void register_stream(int dev, hipStream_t s) {
+  QuietDevice g(dev);
+  DevicePool& P = device_pool(dev);
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.streams.push_back(s);
+}
+
+void unregister_stream(int dev, hipStream_t s) {
+  QuietDevice g(dev);
+  DevicePool& P = device_pool(dev);
+  std::lock_guard<std::mutex> lk(P.mu);
+  auto it = std::find(P.streams.begin(), P.streams.end(), s);
+  if (it != P.streams.end()) P.streams.erase(it);
+  // the last stream gone: nothing of the library runs on the device any
+  // more, so the cached blocks go back to the device
+  if (P.streams.empty()) flush_pool(P);
+}
+
 void DevBuf::alloc(size_t bytes) {
   release();
   if (bytes == 0) bytes = 16;
+  const size_t cap = bucket_of(bytes);
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  DevicePool& P = device_pool(dev);
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error(POLFED_ERR_OOM, "device allocation of " + std::to_string(bytes) +
-                                    " bytes failed: " + hipGetErrorString(e));
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto range = P.blocks.equal_range(cap);
+    for (auto it = range.first; it != range.second; ++it)
+      if (fence_passed(it->second)) {
+        p = it->second.p;
+        for (hipEvent_t e : it->second.fence) P.spare.push_back(e);
+        P.blocks.erase(it);
+        P.cached -= cap;
+        break;
+      }
+  }
+  if (!p) {
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      {
+        std::lock_guard<std::mutex> lk(P.mu);
+        flush_pool(P);
+      }
+      e = hipMalloc(&p, cap);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(POLFED_ERR_OOM, "device allocation of " + std::to_string(bytes) +
+                                      " bytes failed: " + hipGetErrorString(e));
+    }
   }
   p_ = p;
   n_ = bytes;
+  cap_ = cap;
+  dev_ = dev;
   t_ = g_mem_tally;
   if (t_) {
     t_->cur += bytes;
@@ -64,10 +215,58 @@ void DevBuf::alloc(size_t bytes) {
 }
 
 void DevBuf::release() {
-  if (p_) (void)hipFree(p_);
-  if (p_ && t_) t_->cur -= n_;
+  if (p_) {
+    if (t_) t_->cur -= n_;
+    QuietDevice g(dev_);
+    DevicePool& P = device_pool(dev_);
+    bool cached = false;
+    {
+      std::lock_guard<std::mutex> lk(P.mu);
+      if (P.cached + cap_ <= P.cap) {
+        CachedBlock c{p_, {}};
+        bool ok = true;
+        std::vector<hipStream_t> seen;
+        for (hipStream_t s : P.streams) {
+          if (std::find(seen.begin(), seen.end(), s) != seen.end()) continue;
+          seen.push_back(s);
+          // a stream being captured takes no event: its work is a graph
+          // that can run later, so the block goes back to hipFree
+          hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+          if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+            (void)hipGetLastError();
+            ok = false;
+            break;
+          }
+          hipEvent_t e = nullptr;
+          if (!P.spare.empty()) {
+            e = P.spare.back();
+            P.spare.pop_back();
+          } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ok = false;
+            break;
+          }
+          c.fence.push_back(e);
+          if (hipEventRecord(e, s) != hipSuccess) {
+            (void)hipGetLastError();
+            ok = false;
+            break;
+          }
+        }
+        if (ok) {
+          P.blocks.emplace(cap_, std::move(c));
+          P.cached += cap_;
+          cached = true;
+        } else {
+          for (hipEvent_t e : c.fence) P.spare.push_back(e);
+        }
+      }
+    }
+    if (!cached) (void)hipFree(p_);
+  }
   p_ = nullptr;
   n_ = 0;
+  cap_ = 0;
   t_ = nullptr;
 }
 
@@ -125,17 +324,6 @@ polfed_status guarded(F&& f) {
   }
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) HIPC(hipSetDevice(dev));
-  }
-  ~DeviceGuard() {
-    int cur;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
 
 }  // namespace polfed
 
@@ -192,10 +380,17 @@ polfed_status polfed_create(int device, void* hip_stream, polfed_ctx** out) {
     DeviceGuard g(device);
     auto ctx = std::make_unique<polfed_ctx>();
     ctx->device = device;
-    // NULL is the device's null stream: library work is then ordered with
-    // everything else the caller queues there (torch's default stream)
+    // NULL: ordered with the device's null stream (torch's default stream)
+    // through a blocking stream of the context's own; work queued on the
+    // null stream itself while another thread captures a graph can
+    // invalidate that capture
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    if (!ctx->stream) {
+      HIPC(hipStreamCreateWithFlags(&ctx->stream, hipStreamDefault));
+      ctx->own_stream = true;
+    }
     HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    register_stream(device, ctx->stream);
     hipDeviceProp_t prop;
     HIPC(hipGetDeviceProperties(&prop, device));
     ctx->n_cu = prop.multiProcessorCount;
@@ -215,6 +410,8 @@ polfed_status polfed_destroy(polfed_ctx* ctx) {
       ctx->scratch_red.release();
       ctx->scratch_scalar.release();
       ctx->binom.release();
+      for (auto& b : ctx->ws) b.release();
+      unregister_stream(ctx->device, ctx->stream);
       if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
       if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     }
@@ -261,7 +458,7 @@ polfed_status polfed_basis_enumerate(polfed_ctx* ctx, int L, int N, uint32_t* st
     REQUIRE(D < (int64_t(1) << 31), "sector too large");
     REQUIRE(states != nullptr || D == 0, "null states");
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     basis_enumerate(ctx->stream, L, N, D, states, ctx_binom(ctx));
     return POLFED_OK;
   });
@@ -276,7 +473,7 @@ polfed_status polfed_basis_rank(polfed_ctx* ctx, int L, int N, const uint32_t* s
     REQUIRE(n == 0 || (states && ranks), "null array");
     REQUIRE(binom64(L, N) < (int64_t(1) << 31), "sector too large");
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     basis_rank(ctx->stream, L, N, states, n, ranks, ctx_binom(ctx));
     return POLFED_OK;
   });
@@ -292,7 +489,7 @@ polfed_status polfed_basis_unrank(polfed_ctx* ctx, int L, int N, const int64_t* 
     const int64_t D = binom64(L, N);
     REQUIRE(D < (int64_t(1) << 31), "sector too large");
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     basis_unrank(ctx->stream, L, N, D, ranks, n, states, ctx_binom(ctx));
     return POLFED_OK;
   });
@@ -307,7 +504,7 @@ polfed_status polfed_op_xxz(polfed_ctx* ctx, int L, int n_up, double J, double D
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     *out = make_xxz(ctx, L, n_up, J, Delta, h, periodic);
     return POLFED_OK;
   });
@@ -320,7 +517,7 @@ polfed_status polfed_op_tv(polfed_ctx* ctx, int L, int n_part, double t, double 
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     *out = make_tv(ctx, L, n_part, t, V, eps, periodic);
     return POLFED_OK;
   });
@@ -336,7 +533,7 @@ polfed_status polfed_op_qsun(polfed_ctx* ctx, int N_dot, int L, const double* A,
     REQUIRE(std::isfinite(gamma) && std::isfinite(g0) && std::isfinite(alpha) && alpha > 0,
             "qsun: need finite gamma, g0 and alpha > 0");
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     *out = make_qsun(ctx, N_dot, L, A, gamma, g0, alpha, u, n_of_j, h);
     return POLFED_OK;
   });
@@ -349,7 +546,7 @@ polfed_status polfed_op_qrem(polfed_ctx* ctx, int L, const double* E, double Gam
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     *out = make_qrem(ctx, L, E, Gamma);
     return POLFED_OK;
   });
@@ -363,7 +560,7 @@ polfed_status polfed_op_spin_chain(polfed_ctx* ctx, int L, int N, int R, const d
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     *out = make_spin_chain(ctx, L, N, R, J, Delta, h, periodic);
     return POLFED_OK;
   });
@@ -388,7 +585,7 @@ polfed_status polfed_op_csr(polfed_ctx* ctx, int64_t D, const int64_t* rowptr,
     REQUIRE(out, "null output handle");
     *out = nullptr;
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     *out = make_csr(ctx, D, rowptr, col, val);
     return POLFED_OK;
   });
@@ -461,7 +658,7 @@ polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, in
             "multi-column kernels exist only for matrix-free chains");
     REQUIRE(B >= 1, "need B >= 1");
     REQUIRE(precision == POLFED_FP64 || precision == POLFED_FP32, "unknown precision");
-    REQUIRE(variant >= -2 && variant < 6, "variant must be -2 .. 5");
+    REQUIRE(variant >= -2 && variant < 8, "variant must be -2 .. 7");
     if (variant == 4) REQUIRE(op->L >= 22, "variant 4 needs a chain of L >= 22");
     if (variant == 5)
       REQUIRE(precision == POLFED_FP64 ? chain_lds_filter_fits<double>(op)
@@ -474,6 +671,11 @@ polfed_status polfed_op_set_batch_kernel(polfed_op* op, int B, int precision, in
         REQUIRE((uint64_t)op->D * (uint64_t)B * (precision == POLFED_FP64 ? 8 : 4) <
                     (uint64_t(1) << 32) - 64,
                 "interleaved blocks of this size exceed 4 GiB");
+      if (variant >= 6) {
+        const int groups = (int)(((size_t)B * (precision == POLFED_FP64 ? 8 : 4) + 15) / 16);
+        REQUIRE(groups <= 16, "variants 6 and 7: at most 16 lanes per row (32 FP64 or 64 FP32 "
+                              "columns)");
+      }
       op->batch_tuned[key] = variant;
     }
     if (chosen) {
@@ -736,7 +938,7 @@ polfed_status polfed_gemm_nn(polfed_ctx* ctx, int64_t D, int m, int n, const dou
     REQUIRE(D == 0 || n == 0 || ((m == 0 || (A && B)) && C), "gemm: null buffer");
     REQUIRE(m > 0 || subtract || D == 0 || n == 0, "gemm: empty inner dimension");
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     dev_gemm_nn(ctx->stream, D, m, n, A, lda, B, ldb, C, ldc, subtract != 0);
     return POLFED_OK;
   });
@@ -752,7 +954,7 @@ polfed_status polfed_gemm_tn(polfed_ctx* ctx, int64_t D, int n1, int n2, const d
             "gemm: leading dimension too small");
     REQUIRE(n1 == 0 || n2 == 0 || (A && B && G), "gemm: null buffer");
     DeviceGuard g(ctx->device);
-    CtxLock lk(ctx);
+    CtxLock lk(ctx, CtxLock::kBuild);
     dev_gemm_tn(ctx->stream, D, n1, n2, A, lda, B, ldb, G, ldg);
     return POLFED_OK;
   });

@@ -345,11 +345,6 @@ __global__ __launch_bounds__(256) void k_chain_split(
   }
 }
 
-static int env_int(const char* name, int dflt) {
-  const char* s = std::getenv(name);
-  return (s && *s) ? std::atoi(s) : dflt;
-}
-
 // Paired variant: lane l holds the adjacent rows 2l and 2l + 1 of a segment,
 // so every coalesced access (block staging, high-part gathers, v, b_{i+2}
 // and the store) moves both rows in one 16-byte instruction, halving the
@@ -1004,22 +999,21 @@ static bool launch_wt_any(hipStream_t s, const polfed_op* op, int i, T sigma, T 
   return ok;
 }
 
-// Launch shape: persistent blocks per CU and the XCD-contiguous mapping can
-// be overridden through POLFED_CHAIN_BPC and POLFED_CHAIN_XCD (0 = off).
+// Launch shape: kChainBlocksPerCU persistent blocks per CU, the blocks of a
+// launch mapped XCD-contiguously once there are enough of them.
 
 template <typename T, int L, int HALVES = 1>
 static void launch_split(hipStream_t s, const polfed_op* op, T sigma, T tau, T a,
                          const T* v, const T* b1, const T* b2, T* out) {
   constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
   constexpr int NLO = 1 << Lb;
-  static const int bpc = std::max(1, env_int("POLFED_CHAIN_BPC", kChainBlocksPerCU));
-  static const int xcd_map = env_int("POLFED_CHAIN_XCD", 1);
+  constexpr int bpc = kChainBlocksPerCU;
   const size_t shm = chain_blob_bytes(NLO, (int)sizeof(T)) + 4 * kChainStageRows * sizeof(T);
   ChainSplitDev c = op->chain_split();
   const int64_t blocks_needed = (c.nseg * HALVES + 3) / 4;
   int64_t grid = std::min<int64_t>(blocks_needed, (int64_t)op->ctx->n_cu * bpc);
   int nxcd = 1;
-  if (xcd_map && grid >= 64) {
+  if (grid >= 64) {
     grid -= grid % 8;
     nxcd = 8;
   }
@@ -1098,14 +1092,18 @@ static bool launch_variant(hipStream_t s, const polfed_op* op, int var, T sigma,
 }
 
 // Picks the fastest variant for (op, precision) by replaying 20 launches of
-// each on scratch vectors; not while the stream is being captured.
+// each on scratch vectors; not while the stream is being captured.  The
+// choice is shared by the context's operators of the same chain pattern
+// (same kernels and tables, other diagonals).
 template <typename T, int L>
 static int tuned_variant(hipStream_t s, const polfed_op* op) {
   const int pi = sizeof(T) == 8 ? 0 : 1;
   if (op->tuned[pi] >= 0) return op->tuned[pi];
-  static const int allow_tile = env_int("POLFED_CHAIN_TILE", -1);
-  if (allow_tile == 0) return op->tuned[pi] = 0;
-  if (allow_tile >= 1 && allow_tile <= 5) return op->tuned[pi] = allow_tile;
+  const std::string pkey = std::string(sizeof(T) == 8 ? "step64" : "step32");
+  {
+    const int v = pattern_choice(op, pkey);
+    if (v >= 0) return op->tuned[pi] = v;
+  }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return 0;
@@ -1137,6 +1135,7 @@ static int tuned_variant(hipStream_t s, const polfed_op* op) {
     }
   }
   HIPC(hipStreamSynchronize(s));
+  pattern_choice_set(op, pkey, best);
   return op->tuned[pi] = best;
 }
 

@@ -389,6 +389,149 @@ __global__ __launch_bounds__(256) void k_chain_ilv(
   }
 }
 
+// Row-group multi-column step, on the interleaved layout (element (row r,
+// column c) at X[r nb + c]).  The lpr = 2^lg_lpr lanes of a row group share
+// one row, lane k of the group holding the row's columns kG .. kG + G - 1
+// (one 16-byte access), so a wavefront reads 64 / lpr whole rows per access:
+// every gather is contiguous, the row's own work (its low part, neighbour
+// positions and diagonal) is done once per row group instead of once per
+// column group, and the low-part neighbours, which lie in the row's block of
+// at most 256 rows, are read from the L1 cache instead of an LDS stage.  A
+// wavefront takes one (segment, chunk of 64 / lpr rows) item.  Lanes past
+// the last column (nb below lpr G) load nothing and store nothing.  v may be
+// column-major (vcm) and the output too (ocm), as in the interleaved kernel.
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_chain_rows(
+    ChainSplitDev c, int nb, int lg_lpr, T half, const T* __restrict__ fab,
+    const T* __restrict__ dseg, const T* __restrict__ sc, const T* __restrict__ acoef,
+    const T* __restrict__ v, bool vcm, const T* __restrict__ b1, const T* b2, T* out, bool ocm,
+    int nxcd, const int32_t* __restrict__ recs) {
+  constexpr int G = 16 / (int)sizeof(T);
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  constexpr int Lh = L - Lb;
+  constexpr int NLO = 1 << Lb;
+  constexpr int NH = Lh - 1;
+  constexpr int NL = Lb - 1;
+  constexpr int BLOB = chain_blob_bytes(NLO, (int)sizeof(T));
+  constexpr int CHUNKS = BLOB / 16;
+  constexpr uint32_t TB = sizeof(T);
+  using u4 = __attribute__((ext_vector_type(4))) uint32_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  for (int i = threadIdx.x; i < CHUNKS; i += 256)
+    reinterpret_cast<u4*>(smem)[i] =
+        reinterpret_cast<const u4*>(sizeof(T) == 8 ? c.blobl64 : c.blobl32)[i];
+  T* s_fab = reinterpret_cast<T*>(smem + BLOB);
+  for (int i = threadIdx.x; i < nb * 64; i += 256) s_fab[i] = fab[i];
+  const u4* s_np = reinterpret_cast<const u4*>(smem);
+  const uint16_t* s_lo = reinterpret_cast<const uint16_t*>(smem + 16 * NLO + TB * NLO);
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int rpw = 64 >> lg_lpr;          // rows per wavefront access
+  const int nch = (kChainSegRows + rpw - 1) / rpw;  // chunks of a segment
+  const int rl = lane >> lg_lpr;
+  const int c0 = (lane & ((1 << lg_lpr) - 1)) * G;
+  const int w = max(0, min(G, nb - c0));
+  const uint32_t cb = (uint32_t)c0 * TB;
+  T sig[G], ta[G], ac[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int col = min(c0 + q, nb - 1);
+    sig[q] = sc[col] * half;
+    ta[q] = sc[nb + col] * half;
+    ac[q] = acoef ? acoef[col] : T(0);
+  }
+  const int xcd = blockIdx.x % nxcd;
+  const int blocks_x = gridDim.x / nxcd;
+  const int64_t nitem = c.nseg * nch;
+  const int64_t i_begin = nitem * xcd / nxcd, i_end = nitem * (xcd + 1) / nxcd;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wstride = (int64_t)blocks_x * wpb;
+  const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
+  const uint32_t rowb = (uint32_t)nb * TB;
+  const uint32_t blkbytes = (uint32_t)(c.D * rowb);
+  const uint32_t cbytes = (uint32_t)(c.D * TB);
+  const rsrc_t rb1 = make_rsrc(b1, blkbytes), rb2 = make_rsrc(b2, b2 ? blkbytes : 0);
+  const rsrc_t rv = make_rsrc(v, v ? blkbytes : 0);
+  const rsrc_t rout = make_rsrc(out, blkbytes);
+  int64_t it = i_begin + (int64_t)(blockIdx.x / nxcd) * wpb + uniform(threadIdx.x >> 6);
+  for (; it < i_end; it += wstride) {
+    const int64_t si = it / nch;
+    const int ch = (int)(it % nch);
+    const SegRec<NH> cur = load_rec<NH>(recs + (int64_t)uniform((int)si) * kChainRecWords);
+    if (ch * rpw >= cur.len) continue;  // wave-uniform: the segment is shorter
+    const int hi0 = cur.flags & 1, hitop = (cur.flags >> 1) & 1;
+    const int st = (cur.flags >> 12) & 1023;
+    const int blk0 = cur.row0 - st;
+    const int jr = ch * rpw + rl;
+    const bool valid = jr < cur.len && w > 0;
+    const int jj = min(jr, cur.len - 1);
+    const int qd = cur.lidx + jj;
+    const int l = s_lo[qd];
+    const u4 np = s_np[qd];
+    const bool act_j = ((l >> (Lb - 1)) & 1) != hi0;
+    const bool act_p = c.periodic && ((l & 1) != hitop);
+    const int xlo = (l ^ (l >> 1)) & ((1 << NL) - 1);
+    const T nidle = (T)(NL - __popc(xlo));
+    const int n11x = ((l >> (Lb - 1)) & 1 & hi0) + (c.periodic ? (hitop & l & 1) : 0);
+    const T zz = vzz * (T)(__popc(l & (l >> 1)) + n11x);
+    const uint32_t row = (uint32_t)(cur.row0 + jj);
+    const int ww = valid ? w : 0;  // rows past the segment's end load nothing
+    T dsg[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) dsg[q] = dseg[si * nb + min(c0 + q, nb - 1)];
+    Grp<T> bo = gload<T>(rb1, row * rowb + cb, 0, ww);
+    Grp<T> nbv[NL > 0 ? NL : 1], g_hi[NH > 0 ? NH : 1];
+#pragma unroll
+    for (int b = 0; b < NL; ++b)
+      nbv[b] = gload<T>(rb1, (uint32_t)(blk0 + (int)((np[b >> 2] >> (8 * (b & 3))) & 255u)) * rowb + cb,
+                        0, ww);
+#pragma unroll
+    for (int b = 0; b < NH; ++b)
+      g_hi[b] = cur.dh[b] != 0 ? gload<T>(rb1, (uint32_t)jj * rowb + cb,
+                                          (uint32_t)(cur.row0 + cur.dh[b]) * rowb, ww)
+                               : Grp<T>{};
+    const int gj = blk0 + cur.d_join + (int)((np[2] >> 8) & 255u);
+    const int gp = blk0 + cur.d_pbc + (int)((np[2] >> 16) & 255u);
+    const Grp<T> g_j = act_j ? gload<T>(rb1, (uint32_t)gj * rowb + cb, 0, ww) : Grp<T>{};
+    const Grp<T> g_p = act_p ? gload<T>(rb1, (uint32_t)gp * rowb + cb, 0, ww) : Grp<T>{};
+    Grp<T> vv{}, bt{};
+    if (v) {
+      if (vcm) {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          vv.x[q] = q < ww ? bload<T, kAuxNT>(rv, row * TB, (uint32_t)(c0 + q) * cbytes) : T(0);
+      } else {
+        vv = gload<T>(rv, row * rowb + cb, 0, ww);
+      }
+    }
+    if (b2) bt = gload<T>(rb2, row * rowb + cb, 0, ww);
+    Grp<T> o;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      T hop = 0;
+#pragma unroll
+      for (int b = 0; b < NL; ++b) hop += nbv[b].x[q];
+#pragma unroll
+      for (int b = 0; b < NH; ++b) hop += g_hi[b].x[q];
+      hop -= nidle * bo.x[q];
+      hop += act_j ? g_j.x[q] : T(0);
+      const T* fa = s_fab + min(c0 + q, nb - 1) * 64;
+      const T dg = zz + fa[l & 31] + fa[32 + (l >> 5)] + dsg[q];
+      const T acc = dg * bo.x[q] + t_in * hop + (act_p ? t_pb * g_p.x[q] : T(0));
+      o.x[q] = sig[q] * acc + ta[q] * bo.x[q] - bt.x[q] + ac[q] * vv.x[q];
+    }
+    if (!valid) continue;
+    if (ocm) {
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+        if (q < w) bstore<kAuxNT>(o.x[q], rout, row * TB, (uint32_t)(c0 + q) * cbytes);
+    } else {
+      gstore<T>(o, rout, row * rowb + cb, 0, w);
+    }
+  }
+}
+
 // LDS-resident filter for short chains: one workgroup per column runs that
 // column's whole Clenshaw recurrence, b_K = a_K v, b_i = a_i v + 2 H~ b_{i+1}
 // - b_{i+2} (i = K_c - 1 .. 1), w = a_0 v + H~ b_1 - b_2, with b_{i+1} and
@@ -616,6 +759,42 @@ static void launch_ilv(hipStream_t s, const polfed_op* op0, const ChainBatch& bt
   HIPC(hipGetLastError());
 }
 
+// lanes per row: the columns' 16-byte groups rounded up to a power of two
+static int rows_lg_lpr(int nb, size_t tb) {
+  const int groups = (int)((nb * tb + 15) / 16);
+  int lg = 0;
+  while ((1 << lg) < groups) ++lg;
+  return lg;
+}
+constexpr int kRowsMaxLgLpr = 4;  // at most 16 lanes per row
+
+template <typename T, int L>
+static void launch_rows(hipStream_t s, const polfed_op* op0, const ChainBatch& bt, int bpc, T half,
+                        const T* acoef, const T* v, bool vcm, const T* b1, const T* b2, T* out,
+                        bool ocm) {
+  constexpr int Lb = (L / 2 < kChainLoBits) ? L / 2 : kChainLoBits;
+  const size_t shm = chain_blob_bytes(1 << Lb, (int)sizeof(T)) + (size_t)bt.nb * 64 * sizeof(T);
+  bpc = std::max(1, std::min(bpc, batch_bpc_fit(shm)));
+  const int lg = rows_lg_lpr(bt.nb, sizeof(T));
+  ChainSplitDev c = op0->chain_split();
+  const int rpw = 64 >> lg;
+  const int64_t items = c.nseg * ((kChainSegRows + rpw - 1) / rpw);
+  int64_t grid = std::min<int64_t>((items + 3) / 4, (int64_t)op0->ctx->n_cu * bpc);
+  int nxcd = 1;
+  if (grid >= 64) {
+    grid -= grid % 8;
+    nxcd = 8;
+  }
+  grid = std::max<int64_t>(grid, 1);
+  const bool f64 = sizeof(T) == 8;
+  hipLaunchKernelGGL((k_chain_rows<T, L>), dim3((unsigned)grid), dim3(256), shm, s, c, bt.nb, lg,
+                     half, (const T*)(f64 ? bt.fab64.get() : bt.fab32.get()),
+                     (const T*)(f64 ? bt.dseg64.get() : bt.dseg32.get()),
+                     (const T*)(f64 ? bt.sc64.get() : bt.sc32.get()), acoef, v, vcm, b1, b2, out,
+                     ocm, nxcd, c.rec);
+  HIPC(hipGetLastError());
+}
+
 template <typename T, int L>
 static void launch_batch(hipStream_t s, const polfed_op* op0, const ChainBatch& bt,
                          int col0, int ncols, int64_t ld, int bpc, T half, const T* acoef,
@@ -696,11 +875,17 @@ void ChainBatch::set_scale(const double* E_c, const double* dE) {
 
 // Multi-column step variants: 0 and 1 the column-major kernel with 16 and
 // 8 columns per launch, 2 and 3 the interleaved kernel with 2 and 4
-// workgroups per compute unit.
-constexpr int kBatchVariants = 6;
+// workgroups per compute unit, 4 each column by its operator's own kernel,
+// 5 the LDS-resident whole filter, 6 and 7 the row-group kernel with 4 and
+// 8 workgroups per compute unit.
+constexpr int kBatchVariants = 8;
 
 static bool interleaved_fits(const ChainBatch& bt, size_t tb) {
   return (uint64_t)bt.ops[0]->D * (uint64_t)bt.nb * tb < (uint64_t(1) << 32) - 64;
+}
+
+static bool rows_fit(const ChainBatch& bt, size_t tb) {
+  return interleaved_fits(bt, tb) && rows_lg_lpr(bt.nb, tb) <= kRowsMaxLgLpr;
 }
 
 template <typename T>
@@ -718,6 +903,23 @@ static void batch_step_var(hipStream_t s, const ChainBatch& bt, int var, bool fi
       op_step<T>(s, bt.ops[c], half * (T)(2.0 / bt.dE[c]), half * (T)(-2.0 * bt.E_c[c] / bt.dE[c]),
                  T(0), v + (size_t)c * ld, b1 + (size_t)c * ld, b2 ? b2 + (size_t)c * ld : nullptr,
                  out + (size_t)c * ld);
+    return;
+  }
+  if (var == 6 || var == 7) {
+    const int bpc = var == 6 ? 4 : 8;
+    switch (op0->L) {
+#define POLFED_CASE(LL)                                                                     \
+  case LL:                                                                                  \
+    launch_rows<T, LL>(s, op0, bt, bpc, half, acoef, v, vcm, b1, b2, out, ocm);             \
+    break;
+      POLFED_CASE(4) POLFED_CASE(5) POLFED_CASE(6) POLFED_CASE(7) POLFED_CASE(8)
+      POLFED_CASE(9) POLFED_CASE(10) POLFED_CASE(11) POLFED_CASE(12) POLFED_CASE(13)
+      POLFED_CASE(14) POLFED_CASE(15) POLFED_CASE(16) POLFED_CASE(17) POLFED_CASE(18)
+      POLFED_CASE(19) POLFED_CASE(20) POLFED_CASE(21) POLFED_CASE(22) POLFED_CASE(23)
+      POLFED_CASE(24) POLFED_CASE(25) POLFED_CASE(26) POLFED_CASE(27) POLFED_CASE(28)
+#undef POLFED_CASE
+      default: fail(POLFED_ERR_INVALID, "batch: chain length outside 4..28");
+    }
     return;
   }
   if (var >= 2) {
@@ -772,6 +974,12 @@ int batch_variant(hipStream_t s, const ChainBatch& bt) {
     auto it = op0->batch_tuned.find(key);
     if (it != op0->batch_tuned.end()) return it->second;
   }
+  // an earlier choice for this chain pattern (any operator of it)
+  const std::string pkey = "batch" + std::to_string(bt.nb) + (sizeof(T) == 8 ? "|64" : "|32");
+  {
+    const int v = pattern_choice(op0, pkey);
+    if (v >= 0) return op0->batch_tuned[key] = v;
+  }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return 0;  // tuned before any capture
@@ -787,6 +995,7 @@ int batch_variant(hipStream_t s, const ChainBatch& bt) {
   float best_us = 1e30f;
   for (int var = 0; var < kBatchVariants; ++var) {
     if ((var == 2 || var == 3) && !interleaved_fits(bt, sizeof(T))) continue;
+    if ((var == 6 || var == 7) && !rows_fit(bt, sizeof(T))) continue;
     if (var == 1 && bt.nb <= 8) continue;  // the same launches as variant 0
     if (var == 4) {
       // only where a single-column tile kernel exists (L >= 22); each
@@ -834,6 +1043,7 @@ int batch_variant(hipStream_t s, const ChainBatch& bt) {
     }
   }
   HIPC(hipStreamSynchronize(s));
+  pattern_choice_set(op0, pkey, best);
   op0->batch_tuned[key] = best;
   return best;
 }

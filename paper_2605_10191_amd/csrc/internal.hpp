@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <stdexcept>
 #include <map>
 #include <string>
@@ -58,9 +59,10 @@ class DevBuf {
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), t_(o.t_) {
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), cap_(o.cap_), dev_(o.dev_), t_(o.t_) {
     o.p_ = nullptr;
     o.n_ = 0;
+    o.cap_ = 0;
     o.t_ = nullptr;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
@@ -68,9 +70,12 @@ class DevBuf {
       release();
       p_ = o.p_;
       n_ = o.n_;
+      cap_ = o.cap_;
+      dev_ = o.dev_;
       t_ = o.t_;
       o.p_ = nullptr;
       o.n_ = 0;
+      o.cap_ = 0;
       o.t_ = nullptr;
     }
     return *this;
@@ -82,9 +87,16 @@ class DevBuf {
   size_t bytes() const { return n_; }
  private:
   void* p_ = nullptr;
-  size_t n_ = 0;
+  size_t n_ = 0;    // bytes asked for
+  size_t cap_ = 0;  // bytes of the block (its cache bucket)
+  int dev_ = 0;
   MemTally* t_ = nullptr;
 };
+
+// Streams the library queues work on, per device: a released device block
+// is reused only after every registered stream has passed the release.
+void register_stream(int dev, hipStream_t s);
+void unregister_stream(int dev, hipStream_t s);
 
 // A sequence of launches recorded once on a capture stream and replayed as
 // one HIP graph on any stream.  The recorded launches keep their arguments,
@@ -282,6 +294,14 @@ struct polfed_ctx {
   std::mutex mu;  // serializes calls that use the shared workspaces
   // API calls waiting for mu (the server thread lets them in between rounds)
   std::atomic<int> api_waiting{0};
+  // held shared by the server's rounds in flight, exclusively by calls that
+  // may use or change operators those rounds use
+  std::shared_mutex serve_mu;
+  // the autotuners' choices, shared by the operators of one chain pattern
+  // (same kernels and tables, only the diagonal differs): key
+  // "<pattern>|<what>"; guarded by tune_mu
+  std::mutex tune_mu;
+  std::map<std::string, int> pattern_tuned;
   // reusable workspaces
   polfed::DevBuf scratch_red;  // reduction partials
   polfed::DevBuf scratch_scalar;
@@ -292,13 +312,16 @@ struct polfed_ctx {
 
 namespace polfed {
 // Lock of a context for an API call.  The call announces itself before it
-// blocks: the server thread holds the lock for a whole round of filter work
-// and, as std::mutex is not fair, would otherwise take it again at once and
-// keep a caller (say, one building the next request's operator) waiting for
-// many rounds.
+// blocks: the server thread takes the lock between its rounds and, as
+// std::mutex is not fair, would otherwise take it again at once and keep a
+// caller (say, one building the next request's operator) waiting.  A call
+// that may use or change existing operators (kOps) also waits for the
+// server's rounds in flight; one that only builds new objects (kBuild) does
+// not.
 class CtxLock {
  public:
-  explicit CtxLock(polfed_ctx* c) : c_(c) {
+  enum Kind { kOps, kBuild };
+  explicit CtxLock(polfed_ctx* c, Kind kind = kOps) : c_(c) {
     c_->api_waiting.fetch_add(1);
     try {
       c_->mu.lock();
@@ -307,12 +330,25 @@ class CtxLock {
       throw;
     }
     c_->api_waiting.fetch_sub(1);
+    if (kind == kOps) {
+      try {
+        c_->serve_mu.lock();
+      } catch (...) {
+        c_->mu.unlock();
+        throw;
+      }
+      ops_ = true;
+    }
   }
-  ~CtxLock() { c_->mu.unlock(); }
+  ~CtxLock() {
+    if (ops_) c_->serve_mu.unlock();
+    c_->mu.unlock();
+  }
   CtxLock(const CtxLock&) = delete;
   CtxLock& operator=(const CtxLock&) = delete;
  private:
   polfed_ctx* c_;
+  bool ops_ = false;
 };
 }  // namespace polfed
 
@@ -570,6 +606,10 @@ polfed_status solve_batch(polfed_ctx* ctx, int B, const polfed_op* const* ops,
                           polfed_report* rep);
 double now_seconds();
 bool verbose();  // POLFED_VERBOSE set: solver diagnostics on stderr
+// A tuner's choice `what` for the operator's chain pattern on its context
+// (-1: none yet, or the operator has no pattern), and its record.
+int pattern_choice(const polfed_op* op, const std::string& what);
+void pattern_choice_set(const polfed_op* op, const std::string& what, int v);
 void* ctx_scratch(polfed_ctx* ctx, int slot, size_t bytes);
 void lanczos_step(polfed_ctx* ctx, const polfed_op* op, double E_c, double dE,
                   const double* a, int K, double* V, int k, double* alpha,

@@ -1,21 +1,34 @@
 // Continuous-batching solve server.
 //
-// A scheduler thread owns the context's stream while serving.  Each cycle it
-//   1. admits queued requests in arrival order while a column slot is free
-//      and the device bytes their Krylov bases need fit the budget (a request
-//      that does not fit waits; one larger than the whole budget is refused
-//      at submission), running their bounds and plan;
-//   2. groups the running solves by operator pattern and precision; each
-//      group filters the current Lanczos vector of all its members as one
-//      multi-column recurrence on the group's stream, then every member takes
-//      its own Lanczos step (reorthogonalization, convergence check,
-//      extraction) on its own stream, the members of the round side by side
-//      on a pool of host threads;
-//   3. retires the members that finished, which frees their slots and bytes
-//      for the next admissions.
+// A scheduler thread admits requests and hands out rounds of work:
+//   1. it admits queued requests in arrival order while a column slot is
+//      free and the device bytes their Krylov bases need fit the budget (a
+//      request that does not fit waits; one larger than the whole budget is
+//      refused at submission), running their bounds and plan;
+//   2. it groups the running solves by operator pattern and precision; a
+//      round of a group filters the current Lanczos vector of all its
+//      members as one multi-column recurrence, then every member takes its
+//      Lanczos step (reorthogonalization, convergence check, extraction),
+//      all on the group's one stream.  Rounds run as jobs on a pool of host
+//      threads, each group's next round as soon as its last one ended, so
+//      groups proceed at their own pace: a group of short chains (short
+//      filters, many rounds per second) is not held to the pace of a group
+//      of long chains.  One stream per group keeps the groups on separate
+//      hardware queues where the device has enough of them;
+//   3. it retires the members that finished, which frees their slots and
+//      bytes for the next admissions.
 // Requests thus join and leave a running batch between Lanczos iterations,
 // and a request's result does not depend on which others share its batch
 // beyond the rounding of the batched filter.
+//
+// Locking: the scheduler thread takes the context lock (ctx->mu) for
+// admissions and the start of rounds only.  Rounds hold ctx->serve_mu
+// shared; library calls that may use or change an operator take it
+// exclusively (after ctx->mu, so no new round starts meanwhile) and so run
+// between rounds, while calls that only build new objects do not wait for
+// rounds at all.  Two rounds in flight never share an operator (an
+// operator's lazily tuned kernel choices are not guarded otherwise), and a
+// request whose operator is in a round in flight waits to be admitted.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -25,6 +38,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
+#include <shared_mutex>
 #include <thread>
 
 #include "internal.hpp"
@@ -40,8 +55,9 @@ struct polfed_req {
   size_t held = 0;          // bytes reserved now (admission plus grants)
   size_t held_max = 0;      // the most ever reserved
   size_t prepaid = 0;       // part of footprint learned from an eviction
-  polfed_ctx* own = nullptr;  // the request's context (own stream) while admitted
-  hipEvent_t ready = nullptr;  // on own's stream: v_k written, w free
+  // on the stream of the request's last work (its set-up or its group's
+  // last round): v_k written, w free
+  hipEvent_t ready = nullptr;
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::mutex m;
   std::condition_variable cv;
@@ -59,43 +75,57 @@ struct Server {
   polfed_ctx* ctx = nullptr;
   size_t budget = 0, used = 0;
   int max_cols = 0;
-  std::mutex m;
+  std::mutex m;  // pending, active, used, done_rounds, kick, stop
   std::condition_variable cv;
   std::deque<polfed_req*> pending;
   std::vector<polfed_req*> active;
   bool stop = false;
+  bool kick = false;  // a request arrived
   std::thread th;
+  // The solves of one operator pattern and precision; its recurrence runs on
+  // the group's own stream.  Touched by the scheduler thread while no round
+  // of the group is in flight, and by the round's job while one is.
   struct Group {
     BatchFilter bf;
+    polfed_ctx* gc = nullptr;
+    bool busy = false;
   };
-  std::map<std::string, Group> groups;
-  // one child context (own stream) per chain pattern for the groups' filter
-  // recurrences, so that groups of different patterns overlap on the device
-  std::map<std::string, polfed_ctx*> children;
-  polfed_ctx* child_for(const polfed_req* r);
-  // host threads that advance the members of a round side by side
+  std::map<std::string, std::unique_ptr<Group>> groups;
+  // a round that ended, with the members that finished in it
+  struct Done {
+    Group* g = nullptr;
+    std::vector<polfed_req*> members;
+    std::vector<char> finished;
+    std::vector<std::pair<polfed_status, std::string>> outcome;
+  };
+  std::deque<Done> done_rounds;
+  // scheduler thread only
+  int in_flight = 0;                             // rounds
+  std::set<const polfed_req*> busy_reqs;         // members of rounds in flight
+  std::map<const polfed_op*, int> busy_ops;      // their operators
+  // host seconds spent in the server's phases (printed at the end with
+  // POLFED_VERBOSE): admission set-up, group formation, filter launch,
+  // member steps; and counts of rounds and formations
+  std::atomic<int64_t> t_setup_us{0}, t_form_us{0}, t_run_us{0}, t_adv_us{0};
+  std::atomic<int64_t> n_rounds{0}, n_forms{0};
+  // host threads that run the rounds
   std::vector<std::thread> pool;
   std::mutex pm;
-  std::condition_variable pcv, pdone;
+  std::condition_variable pcv;
   std::deque<std::function<void()>> jobs;
-  int busy = 0;
   bool pool_stop = false;
   void start_pool(int n);
-  void run_all(std::vector<std::function<void()>>& work);
+  void post(std::function<void()> job);
   ~Server();
   void loop();
   void admit();
+  void round(Group* g, const std::string& key, std::vector<polfed_req*> members);
+  void settle(Done& d);
   void complete(polfed_req* r, polfed_status st, const std::string& err);
   void evict(polfed_req* r);
   bool take(polfed_req* r, size_t bytes);
   void give(polfed_req* r, size_t bytes);
 };
-
-static std::string pattern_of(const polfed_op* op) {
-  const bool batchable = op->model == Model::Chain && !op->pattern_key.empty() &&
-                         op->split_nseg > 0;
-  return batchable ? op->pattern_key : std::string("other");
-}
 
 static polfed_ctx* new_child(const polfed_ctx* parent) {
   auto c = std::make_unique<polfed_ctx>();
@@ -104,22 +134,18 @@ static polfed_ctx* new_child(const polfed_ctx* parent) {
   HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   c->own_stream = true;
   HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  register_stream(c->device, c->stream);
   return c.release();
 }
 
 static void delete_child(polfed_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->ws) b.release();
+  unregister_stream(c->device, c->stream);
   (void)hipStreamDestroy(c->stream);
   (void)hipStreamDestroy(c->cap_stream);
   delete c;
-}
-
-polfed_ctx* Server::child_for(const polfed_req* r) {
-  const std::string key = pattern_of(r->op);
-  auto it = children.find(key);
-  if (it != children.end()) return it->second;
-  return children[key] = new_child(ctx);
 }
 
 void Server::start_pool(int n) {
@@ -136,34 +162,32 @@ void Server::start_pool(int n) {
           jobs.pop_front();
         }
         job();  // catches its own errors
-        std::lock_guard<std::mutex> lk(pm);
-        if (--busy == 0) pdone.notify_all();
       }
     });
 }
 
-// Runs the jobs on the pool and waits for all of them.
-void Server::run_all(std::vector<std::function<void()>>& work) {
-  if (work.empty()) return;
-  if (pool.empty() || work.size() == 1) {
-    for (auto& f : work) f();
-    return;
+void Server::post(std::function<void()> job) {
+  {
+    std::lock_guard<std::mutex> lk(pm);
+    jobs.push_back(std::move(job));
   }
-  std::unique_lock<std::mutex> lk(pm);
-  busy += (int)work.size();
-  for (auto& f : work) jobs.push_back(std::move(f));
-  pcv.notify_all();
-  pdone.wait(lk, [&] { return busy == 0; });
+  pcv.notify_one();
 }
 
 Server::~Server() {
+  if (verbose())
+    std::fprintf(stderr,
+                 "[polfed] server: %lld rounds, %lld formations; host s: set-up %.2f, "
+                 "formation %.2f, filter launch %.2f, member steps %.2f\n",
+                 (long long)n_rounds.load(), (long long)n_forms.load(), 1e-6 * t_setup_us.load(),
+                 1e-6 * t_form_us.load(), 1e-6 * t_run_us.load(), 1e-6 * t_adv_us.load());
   {
     std::lock_guard<std::mutex> lk(pm);
     pool_stop = true;
   }
   pcv.notify_all();
   for (auto& t : pool) t.join();
-  for (auto& kv : children) delete_child(kv.second);
+  for (auto& kv : groups) delete_child(kv.second->gc);
 }
 
 static std::string group_key(const polfed_req* r) {
@@ -176,14 +200,12 @@ static std::string group_key(const polfed_req* r) {
   return k + (r->run->fp32 ? "|f32" : "|f64");
 }
 
-// The request's own context and event, after its solve is gone.
+// The request's event, after its solve is gone.
 static void release_own(polfed_req* r) {
   if (r->ready) {
     (void)hipEventDestroy(r->ready);
     r->ready = nullptr;
   }
-  delete_child(r->own);
-  r->own = nullptr;
 }
 
 // Hands an admitted request back to its caller.  Everything the server keeps
@@ -260,8 +282,10 @@ void Server::evict(polfed_req* r) {
                std::to_string(budget));
 }
 
+
 // Admission in arrival order: stop at the first request that does not fit,
-// so a large request is not overtaken for ever by smaller ones.
+// so a large request is not overtaken for ever by smaller ones (nor while
+// its operator is in a round in flight: setting up a solve may tune it).
 void Server::admit() {
   for (;;) {
     polfed_req* r = nullptr;
@@ -269,6 +293,7 @@ void Server::admit() {
       std::lock_guard<std::mutex> lk(m);
       if (pending.empty() || (int)active.size() >= max_cols) return;
       if (used + pending.front()->footprint > budget) return;
+      if (busy_ops.count(pending.front()->op)) return;
       r = pending.front();
       pending.pop_front();
       used += r->footprint;
@@ -277,23 +302,19 @@ void Server::admit() {
     }
     r->t_admit = now_seconds();
     try {
-      (void)child_for(r);  // the pattern's stream for its group filter
-      r->own = new_child(ctx);
       HIPC(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
-      polfed_ctx* cc = r->own;
-      // the start vector was written on the caller's stream
-      hipEvent_t ready;
-      HIPC(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-      HIPC(hipEventRecord(ready, ctx->stream));
-      HIPC(hipStreamWaitEvent(cc->stream, ready, 0));
-      HIPC(hipEventDestroy(ready));
+      // the set-up (bounds, plan, v_0) on the context's stream, where the
+      // caller wrote the start vector; the rounds run on the group's stream
+      polfed_ctx* cc = ctx;
       r->run.reset(new SolveRun());
       r->run->granted = r->prepaid;
       r->run->take = [this, r](size_t b) { return take(r, b); };
       r->run->give = [this, r](size_t b) { give(r, b); };
       TallyScope ts(&r->run->tally);
+      const double t0 = now_seconds();
       r->run->setup(cc, r->op, r->p, r->x0, r->evals, r->evecs, r->resid, &r->n_found);
       HIPC(hipEventRecord(r->ready, cc->stream));  // v_0 written
+      t_setup_us += (int64_t)(1e6 * (now_seconds() - t0));
       std::lock_guard<std::mutex> lk(m);
       active.push_back(r);
     } catch (const Error& e) {
@@ -304,114 +325,190 @@ void Server::admit() {
   }
 }
 
+// One round of a group, on a pool thread: the filter application for every
+// member, then each member's Lanczos step.  Members that finish are handed
+// to the scheduler thread, which retires them.
+void Server::round(Group* g, const std::string& key, std::vector<polfed_req*> members) {
+  Done d;
+  d.g = g;
+  d.members = std::move(members);
+  const size_t n = d.members.size();
+  d.finished.assign(n, 0);
+  d.outcome.resize(n);
+  {
+    std::shared_lock<std::shared_mutex> sl(ctx->serve_mu);
+    std::vector<SolveRun*> runs;
+    for (auto* r : d.members) runs.push_back(r->run.get());
+    bool filtered = false;
+    try {
+      // every member's work runs on the group's stream (one hardware queue
+      // per group, so the groups do not wait for each other), after its
+      // last work elsewhere (set-up, or a round of another group)
+      for (auto* r : d.members) {
+        HIPC(hipStreamWaitEvent(g->gc->stream, r->ready, 0));
+        r->run->ctx = g->gc;
+      }
+      if (n == 1 && key.rfind("op:", 0) == 0) {
+        // a solve of its own: the single-column filter
+        TallyScope ts(&runs[0]->tally);
+        runs[0]->filter_self();
+      } else {
+        // rebuilt whenever a member joined or left (a new solve may reuse a
+        // finished one's address, so members are compared by uid)
+        const double t0 = now_seconds();
+        if (!g->bf.same_members(runs)) {
+          g->bf.form(g->gc, runs);
+          ++n_forms;
+        }
+        const double t1 = now_seconds();
+        g->bf.run();
+        t_form_us += (int64_t)(1e6 * (t1 - t0));
+        t_run_us += (int64_t)(1e6 * (now_seconds() - t1));
+      }
+      filtered = true;
+    } catch (const Error& e) {
+      g->bf.forget();
+      for (size_t i = 0; i < n; ++i) d.outcome[i] = {e.code, e.what()};
+    } catch (const std::exception& e) {
+      g->bf.forget();
+      for (size_t i = 0; i < n; ++i) d.outcome[i] = {POLFED_ERR_INVALID, e.what()};
+    }
+    if (!filtered) {
+      d.finished.assign(n, 1);
+    } else {
+      bool leaving = false;
+      const double t0 = now_seconds();
+      for (size_t i = 0; i < n; ++i) {
+        polfed_req* r = d.members[i];
+        try {
+          TallyScope ts(&r->run->tally);
+          r->run->advance();
+          HIPC(hipEventRecord(r->ready, g->gc->stream));  // v_{k+1} written
+          if (r->run->done) {
+            d.finished[i] = 1;
+            d.outcome[i] = {r->run->status, ""};
+          }
+        } catch (const Error& e) {
+          d.finished[i] = 1;
+          d.outcome[i] = {e.code, e.what()};
+        } catch (const std::exception& e) {
+          d.finished[i] = 1;
+          d.outcome[i] = {POLFED_ERR_INVALID, e.what()};
+        }
+        // a member leaves the group when it finished, waits for bytes, or
+        // changed precision (an FP32 run restarted in FP64)
+        if (d.finished[i] || r->run->blocked() || group_key(r) != key) leaving = true;
+      }
+      t_adv_us += (int64_t)(1e6 * (now_seconds() - t0));
+      ++n_rounds;
+      if (leaving) {
+        // the filter timings of this group's past rounds, while every
+        // member they name is alive
+        try {
+          g->bf.drain();
+        } catch (const std::exception&) {
+          g->bf.forget();
+        }
+      }
+      for (size_t i = 0; i < n; ++i)
+        if (d.finished[i]) {
+          polfed_report& R = d.members[i]->run->R;
+          R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
+        }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(m);
+    done_rounds.push_back(std::move(d));
+  }
+  cv.notify_all();
+}
+
+// A round that ended: its group and operators are free again, and its
+// finished members are retired.
+void Server::settle(Done& d) {
+  d.g->busy = false;
+  --in_flight;
+  for (auto* r : d.members) {
+    busy_reqs.erase(r);
+    auto it = busy_ops.find(r->op);
+    if (--it->second == 0) busy_ops.erase(it);
+  }
+  for (size_t i = 0; i < d.members.size(); ++i)
+    if (d.finished[i]) complete(d.members[i], d.outcome[i].first, d.outcome[i].second);
+}
+
 void Server::loop() {
   (void)hipSetDevice(ctx->device);
   for (;;) {
+    std::deque<Done> ended;
     {
       std::unique_lock<std::mutex> lk(m);
-      cv.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
-      if (stop && pending.empty() && active.empty()) return;
+      // wakes when a round ends or a request arrives; with no round in
+      // flight, at once while there is work to decide on
+      cv.wait(lk, [&] {
+        return !done_rounds.empty() || kick ||
+               (in_flight == 0 && (stop || !pending.empty() || !active.empty()));
+      });
+      if (stop && pending.empty() && active.empty() && in_flight == 0 && done_rounds.empty())
+        return;
+      ended.swap(done_rounds);
+      kick = false;
     }
+    for (auto& d : ended) settle(d);
     // API calls waiting for the context go first
     while (ctx->api_waiting.load() > 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
     std::lock_guard<std::mutex> ctx_lk(ctx->mu);
     admit();
-    // current groups
-    // a solve waiting for budget takes no filter step this round
+    // the solves not in a round in flight, by group; a solve waiting for
+    // budget takes no filter step
+    std::vector<polfed_req*> act;
+    {
+      std::lock_guard<std::mutex> lk(m);
+      act = active;
+    }
     std::map<std::string, std::vector<polfed_req*>> by_key;
     std::vector<polfed_req*> waiting;
-    for (auto* r : active) {
+    for (auto* r : act) {
+      if (busy_reqs.count(r)) continue;
       if (r->run->blocked())
         waiting.push_back(r);
       else
         by_key[group_key(r)].push_back(r);
     }
-    for (auto it = groups.begin(); it != groups.end();)
-      it = by_key.count(it->first) ? std::next(it) : groups.erase(it);
-    // every group's filter application is launched before any member is
-    // advanced: advancing reads a member's Lanczos coefficients back and so
-    // waits for its group's filter, which would otherwise keep the groups'
-    // recurrences from running side by side on their streams
-    std::vector<std::pair<Group*, const std::vector<polfed_req*>*>> launched;
-    for (auto& kv : by_key) {
-      std::vector<SolveRun*> runs;
-      for (auto* r : kv.second) runs.push_back(r->run.get());
-      Group& g = groups[kv.first];
-      try {
-        if (runs.size() == 1 && kv.first.rfind("op:", 0) == 0) {
-          // a solve of its own: the filter on the request's stream
-          TallyScope ts(&runs[0]->tally);
-          runs[0]->filter_self();
-        } else {
-          // the group's recurrence on the pattern's stream, after every
-          // member's v_k is written (on its own stream), and every member's
-          // Lanczos step after the recurrence has written its w
-          polfed_ctx* gc = child_for(kv.second[0]);
-          for (auto* r : kv.second) HIPC(hipStreamWaitEvent(gc->stream, r->ready, 0));
-          // rebuilt whenever a member joined or left (a new solve may reuse
-          // a finished one's address, so members are compared by uid)
-          if (!g.bf.same_members(runs)) g.bf.form(gc, runs);
-          g.bf.run();
-          hipEvent_t fe;
-          HIPC(hipEventCreateWithFlags(&fe, hipEventDisableTiming));
-          HIPC(hipEventRecord(fe, gc->stream));
-          for (auto* r : kv.second) HIPC(hipStreamWaitEvent(r->own->stream, fe, 0));
-          HIPC(hipEventDestroy(fe));
-        }
-      } catch (const Error& e) {
-        g.bf.forget();
-        for (auto* r : kv.second) complete(r, e.code, e.what());
-        continue;
+    for (auto it = groups.begin(); it != groups.end();) {
+      if (!it->second->busy && !by_key.count(it->first)) {
+        delete_child(it->second->gc);
+        it = groups.erase(it);
+      } else {
+        ++it;
       }
-      launched.push_back({&g, &kv.second});
     }
-    // every member of the launched groups takes its Lanczos step
-    // (reorthogonalization on its own stream, then the periodic check and
-    // extraction, which wait for that stream only) on the host thread pool
-    std::vector<polfed_req*> adv;
-    for (auto& gm : launched) adv.insert(adv.end(), gm.second->begin(), gm.second->end());
-    std::vector<std::pair<polfed_status, std::string>> outcome(adv.size());
-    std::vector<char> finished(adv.size(), 0);
-    std::vector<std::function<void()>> work;
-    for (size_t i = 0; i < adv.size(); ++i)
-      work.push_back([&, i] {
-        polfed_req* r = adv[i];
-        try {
-          TallyScope ts(&r->run->tally);
-          r->run->advance();
-          HIPC(hipEventRecord(r->ready, r->own->stream));  // v_{k+1} written
-          if (r->run->done) {
-            finished[i] = 1;
-            outcome[i] = {r->run->status, ""};
-          }
-        } catch (const Error& e) {
-          finished[i] = 1;
-          outcome[i] = {e.code, e.what()};
-        } catch (const std::exception& e) {
-          finished[i] = 1;
-          outcome[i] = {POLFED_ERR_INVALID, e.what()};
-        }
-      });
-    run_all(work);
-    {
-      size_t i = 0;
-      for (auto& gm : launched) {
-        Group& g = *gm.first;
-        bool drained = false;
-        for (size_t q = 0; q < gm.second->size(); ++q, ++i) {
-          if (!finished[i]) continue;
-          if (!drained) {
-            g.bf.drain();  // the filter timings of the leaving members
-            drained = true;
-          }
-          polfed_report& R = adv[i]->run->R;
-          R.filter_GBps = R.t_filter > 0 ? R.filter_bytes / R.t_filter / 1e9 : 0;
-          complete(adv[i], outcome[i].first, outcome[i].second);
-        }
+    bool launched = false;
+    for (auto& kv : by_key) {
+      std::unique_ptr<Group>& gp = groups[kv.first];
+      if (!gp) {
+        gp.reset(new Group());
+        gp->gc = new_child(ctx);
       }
+      if (gp->busy) continue;  // the new members join its next round
+      bool clash = false;
+      for (auto* r : kv.second) clash = clash || busy_ops.count(r->op) > 0;
+      if (clash) continue;  // after the round that uses the operator
+      gp->busy = true;
+      ++in_flight;
+      for (auto* r : kv.second) {
+        busy_reqs.insert(r);
+        ++busy_ops[r->op];
+      }
+      Group* g = gp.get();
+      std::string key = kv.first;
+      std::vector<polfed_req*> mem = kv.second;
+      post([this, g, key, mem]() { round(g, key, mem); });
+      launched = true;
     }
     // solves waiting for budget: granted now if others have released bytes
-    bool progress = !launched.empty();
+    bool progress = launched || in_flight > 0;
     for (auto* r : waiting) {
       try {
         TallyScope ts(&r->run->tally);
@@ -426,6 +523,7 @@ void Server::loop() {
         progress = true;
       }
     }
+    // every running solve waits for bytes that no round in flight can free
     if (!progress && !waiting.empty()) {
       polfed_req* last = nullptr;
       for (auto* r : waiting)
@@ -484,14 +582,12 @@ polfed_status serve_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_pa
   r->evecs = evecs;
   r->resid = resid;
   r->footprint = fp;
-  // the server's loop enqueues for many groups: a filter application is one
-  // graph replay unless the caller asked for direct launches
-  if (r->p.graph == 0) r->p.graph = 1;
   r->t_submit = now_seconds();
   {
     std::lock_guard<std::mutex> lk(s->m);
     REQUIRE(!s->stop, "serve: server is stopping");
     s->pending.push_back(r);
+    s->kick = true;
   }
   s->cv.notify_all();
   *out = r;

@@ -250,6 +250,7 @@ struct BatchFilter {
   std::vector<uint64_t> ids;  // uid of each member when the batch was formed
   // true when runs are exactly the members the tables were built for
   bool same_members(const std::vector<SolveRun*>& runs) const;
+  std::string graph_choice_key() const;
   bool fp32 = false;
   ChainBatch bt;
   BatchCoef co;

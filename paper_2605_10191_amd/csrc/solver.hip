@@ -31,6 +31,19 @@ bool verbose() {
   return v;
 }
 
+int pattern_choice(const polfed_op* op, const std::string& what) {
+  if (!op || op->pattern_key.empty()) return -1;
+  std::lock_guard<std::mutex> lk(op->ctx->tune_mu);
+  auto it = op->ctx->pattern_tuned.find(op->pattern_key + "|" + what);
+  return it == op->ctx->pattern_tuned.end() ? -1 : it->second;
+}
+
+void pattern_choice_set(const polfed_op* op, const std::string& what, int v) {
+  if (!op || op->pattern_key.empty()) return;
+  std::lock_guard<std::mutex> lk(op->ctx->tune_mu);
+  op->ctx->pattern_tuned[op->pattern_key + "|" + what] = v;
+}
+
 double now_seconds() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();

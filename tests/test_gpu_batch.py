@@ -74,21 +74,33 @@ def filter_tol(K, prec):
                                      (("xxz", 14, 4), [700, 0, 1, 2]),
                                      (("xxz", 14, 1), [573]),
                                      (("tv", 12, 2), [400, 400]),
-                                     (("xxz", 10, 18), list(range(40, 58)))],
+                                     (("xxz", 10, 18), list(range(40, 58))),
+                                     (("xxz", 12, 21), [90 + 3 * c for c in range(21)]),
+                                     (("xxz", 16, 32), [60 - (c % 7) for c in range(32)])],
                          ids=lambda c: "-".join(map(str, c[:3])) if isinstance(c[0], str) else "K")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [-1, 0, 1, 2, 3, 5])
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2, 3, 5, 6, 7])
 def test_filter_apply_batch_matches_oracle(pk, ctx, case, Ks, prec, variant):
     """Every column of the batched filter against the oracle's filter of its
     own Hamiltonian, element by element, with the tuned multi-column kernel
     and with each variant forced (column-major blocks with 16 or 8 columns
     per launch; interleaved blocks, including a last group narrower than a
     16-byte access for odd batch widths; the LDS-resident whole filter with
-    each column's own order, K = 0 included)."""
+    each column's own order, K = 0 included; the row-group kernel, with
+    lanes past the last column for widths that do not fill a power of two of
+    16-byte groups, up to 32 columns)."""
     kind, L, B = case
     say(f"batch filter {case} K={Ks[:4]} {prec} variant {variant}")
     ops, Hs = batch_ops(pk, ctx, kind, L, B)
     p = pk.FP64 if prec == "fp64" else pk.FP32
+    if variant == 5 and L > 14:
+        # the LDS-resident filter where two vectors and the tables fit the
+        # LDS (FP64 to L = 14; FP32 beyond only for some chains), else refused
+        try:
+            ops[0].set_batch_kernel(B, p, variant)
+        except pk.PolfedError as e:
+            assert "LDS" in str(e)
+            return
     assert ops[0].set_batch_kernel(B, p, variant) == variant
     D = ops[0].D
     E_c, dE, coefs, refs = [], [], [], []
@@ -209,7 +221,7 @@ def test_batch_kernel_is_tuned_and_kept(pk, ctx, prec):
     w = pk.filter_apply_batch(ops, [0.0] * 6, [30.0] * 6, coefs, dev(V, dt), p)
     chosen = ops[0].set_batch_kernel(6, p, -2)
     say(f"   chosen variant {chosen}")
-    assert chosen in (0, 1, 2, 3)
+    assert chosen in (0, 1, 2, 3, 5, 6, 7)
     got = host(w).astype(np.float64)
     for c in range(6):
         ref = flt.apply_filter(Hs[c], 0.0, 30.0, coefs[c], V[c])

@@ -220,7 +220,7 @@ def test_serve_memory_stays_within_reservation(pk, ctx):
     assert any(results[i][3]["iters"] > results[i][3]["M_alloc"] for i in (1, 3, 4))
 
 
-@pytest.mark.parametrize("variant", [0, 3, 5])
+@pytest.mark.parametrize("variant", [0, 3, 5, 6])
 def test_served_fp32_request_alone_with_each_batch_kernel(pk, ctx, variant):
     """An FP32-bulk request served alone (a one-column group) with each
     multi-column kernel forced for its recurrence: the result is the dense
