@@ -524,8 +524,8 @@ def main():
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-budget-gb", type=float, default=2.0)
-    ap.add_argument("--serve-cols", type=int, default=16)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-cols", type=int, default=32)
     ap.add_argument("--serve-one-leg", action="store_true",
                     help="serve the stream with the automatic precision only")
     ap.add_argument("--serve-rate", type=float, default=1.0,

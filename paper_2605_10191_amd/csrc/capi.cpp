@@ -45,6 +45,7 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 }
 
 thread_local MemTally* g_mem_tally = nullptr;
+thread_local bool g_no_capture = false;
 
 struct DeviceGuard {
   int prev = -1;
@@ -136,12 +137,16 @@ bool fence_passed(const CachedBlock& c) {
   return true;
 }
 
-// Waits for the device and frees every cached block (pool lock held).
+// Frees every cached block once its fence has passed (pool lock held).  No
+// device-wide synchronization: on another thread, that would invalidate a
+// graph capture in progress (and fail itself).
 void flush_pool(DevicePool& P) {
-  (void)hipDeviceSynchronize();
   for (auto& kv : P.blocks) {
+    for (hipEvent_t e : kv.second.fence) {
+      (void)hipEventSynchronize(e);
+      P.spare.push_back(e);
+    }
     (void)hipFree(kv.second.p);
-    for (hipEvent_t e : kv.second.fence) P.spare.push_back(e);
   }
   P.blocks.clear();
   P.cached = 0;
@@ -276,6 +281,7 @@ void GraphExec::reset() {
 }
 
 void GraphExec::begin(hipStream_t cap) {
+  REQUIRE(!g_no_capture, "graph capture on a thread that captures no graphs (a server thread)");
   HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
 }
 

@@ -131,8 +131,15 @@ class GraphExec {
   hipGraphExec_t exec_ = nullptr;
 };
 
+// Set on the server's threads: they capture no graphs.  A stream capture on
+// one thread can be invalidated by HIP calls other threads make meanwhile,
+// and the server's rounds run side by side on several threads.
+extern thread_local bool g_no_capture;
+
 // Average run time in microseconds of one call of launch(stream), taken from
-// a replay of a graph of `reps` calls on a private stream.  Between eager
+// a replay of a graph of `reps` calls on a private stream (on a thread that
+// captures no graphs: from `reps` eager launches, which at small kernel sizes
+// also time the host's launch gaps).  Between eager
 // launches the host leaves gaps longer than a small kernel's own run time, so
 // an eager timing would not tell kernel variants apart at small sizes; a
 // replay runs the kernels back to back, as the filter's graphs do.  The caller
@@ -155,6 +162,15 @@ float replay_time_us(F&& launch, int reps) {
   HIPC(hipEventCreate(&t.e0));
   HIPC(hipEventCreate(&t.e1));
   launch(t.s);  // any first-call work outside the capture
+  if (g_no_capture) {
+    HIPC(hipEventRecord(t.e0, t.s));
+    for (int i = 0; i < reps; ++i) launch(t.s);
+    HIPC(hipEventRecord(t.e1, t.s));
+    HIPC(hipEventSynchronize(t.e1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, t.e0, t.e1));
+    return 1e3f * ms / (float)reps;
+  }
   g.capture(t.s, [&](hipStream_t c) {
     for (int i = 0; i < reps; ++i) launch(c);
   });

@@ -152,6 +152,7 @@ void Server::start_pool(int n) {
   for (int i = 0; i < n; ++i)
     pool.emplace_back([this] {
       (void)hipSetDevice(ctx->device);
+      g_no_capture = true;
       for (;;) {
         std::function<void()> job;
         {
@@ -440,6 +441,7 @@ void Server::settle(Done& d) {
 
 void Server::loop() {
   (void)hipSetDevice(ctx->device);
+  g_no_capture = true;
   for (;;) {
     std::deque<Done> ended;
     {
@@ -582,6 +584,8 @@ polfed_status serve_submit(polfed_ctx* ctx, const polfed_op* op, const polfed_pa
   r->evecs = evecs;
   r->resid = resid;
   r->footprint = fp;
+  // the server's threads capture no graphs: filter steps launch directly
+  r->p.graph = 2;
   r->t_submit = now_seconds();
   {
     std::lock_guard<std::mutex> lk(s->m);
