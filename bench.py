@@ -74,9 +74,10 @@ def measured_traffic(kernel: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_src_sha") != kernel_source_sha() or t.get("kernel") != kernel:
+    if t.get("kernel_src_sha") != kernel_source_sha():
         return None
-    return t.get("bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    return k.get("bytes_per_launch") if k else None
 
 
 # staged-tile variants 6-9: (tile bits below the largest, wrap, double
