@@ -502,6 +502,42 @@ def serving_leg(pk, wl, ctx, n_req, budget_gb, max_cols, precision, seed=7, rate
             "stream": "L in {14,16,18}, W in {1,3,5} uniform, " + desc}
 
 
+def batch_variant_leg(pk, wl, ctx, K=400):
+    """Per-step time of every multi-column variant, each forced in turn, in
+    a K-step batched filter of XXZ realizations at serving sizes."""
+    import torch
+    out = {}
+    for L, B in ((18, 8), (18, 16), (18, 32), (16, 16), (16, 32), (14, 16)):
+        ops = [pk.Operator.xxz(ctx, L, L // 2, 1.0, 1.0, wl.xxz_fields(L, 3.0, c), True)
+               for c in range(B)]
+        D = ops[0].D
+        for prec, dt, w in ((pk.FP64, torch.float64, 8), (pk.FP32, torch.float32, 4)):
+            V = torch.randn((B, D), dtype=dt, device=ctx.torch_device)
+            a = [np.full(K + 1, 0.01) for _ in range(B)]
+            row = {}
+            for var in (0, 2, 3, 5, 6, 7):
+                try:
+                    ops[0].set_batch_kernel(B, prec, var)
+                except pk.PolfedError:
+                    continue  # variant 5 where two vectors do not fit the LDS
+                pk.filter_apply_batch(ops, [0.0] * B, [40.0] * B, a, V, prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    pk.filter_apply_batch(ops, [0.0] * B, [40.0] * B, a, V, prec)
+                torch.cuda.synchronize()
+                us = (time.perf_counter() - t0) / (3 * K) * 1e6
+                row[f"v{var}"] = {"us_per_step": round(us, 2),
+                                  "GBps": round(4 * w * D * B / us / 1e3, 1)}
+            ops[0].set_batch_kernel(B, prec, -1)
+            key = f"L={L} B={B} {'fp64' if prec == pk.FP64 else 'fp32'}"
+            out[key] = row
+            log(f"batch variants {key}: {row}")
+        for o in ops:
+            o.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -539,6 +575,8 @@ def main():
     ap.add_argument("--serve-arrival", type=float, default=None,
                     help="with --serve-only: arrival rate in requests/s (inf: all at "
                          "once), in place of --serve-rate")
+    ap.add_argument("--batch-variants", action="store_true",
+                    help="run only the per-step timing of every multi-column variant")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the step kernels and a plain copy (counter runs)")
     ap.add_argument("--variants", default="",
@@ -558,6 +596,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     ctx = pk.Context(0)
+    if args.batch_variants:
+        print(json.dumps({"mode": "batch-variants",
+                          "batch_variants": batch_variant_leg(pk, wl, ctx)}))
+        return
     if args.serve_only:
         names = {"auto": pk.AUTO, "fp32": pk.FP32, "fp64": pk.FP64}
         out = {"mode": "serve-only", "serving": {}}
