@@ -538,6 +538,39 @@ def batch_variant_leg(pk, wl, ctx, K=400):
     return out
 
 
+def gemm_leg(pk, ctx, reps=3):
+    """The library's FP64 MFMA products at the extraction shapes of the QREM
+    L = 20, 1500-pair solve (D = 2^20 rows, Krylov dimension 2,955, 1,800
+    wanted pairs): u = V t, U^T (H U) and the Rayleigh-Ritz rotation."""
+    import torch
+    D = 1 << 20
+    out = {}
+    for name, m, n in (("nn_VY", 2955, 1800), ("tn_UtHU", 1800, 1800), ("nn_rotate", 1800, 1800)):
+        A = torch.randn((m, D), dtype=torch.float64, device=ctx.torch_device)
+        if name.startswith("nn"):
+            B = torch.randn((n, m), dtype=torch.float64, device=ctx.torch_device)
+            C = torch.empty((n, D), dtype=torch.float64, device=ctx.torch_device)
+            f = lambda: pk.gemm_nn(ctx, A, B, C)
+        else:
+            B = torch.randn((n, D), dtype=torch.float64, device=ctx.torch_device)
+            C = torch.empty((n, m), dtype=torch.float64, device=ctx.torch_device)
+            f = lambda: pk.gemm_tn(ctx, A, B, C)
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        tf = 2.0 * D * m * n / dt / 1e12
+        out[name] = {"D": D, "m": m, "n": n, "ms": round(dt * 1e3, 2), "TFLOPs": round(tf, 1),
+                     "frac_of_78.6": round(tf / 78.6, 3)}
+        log(f"gemm {name}: {out[name]}")
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -575,6 +608,8 @@ def main():
     ap.add_argument("--serve-arrival", type=float, default=None,
                     help="with --serve-only: arrival rate in requests/s (inf: all at "
                          "once), in place of --serve-rate")
+    ap.add_argument("--gemm-shapes", action="store_true",
+                    help="run only the MFMA products at the QREM 1500-pair extraction shapes")
     ap.add_argument("--batch-variants", action="store_true",
                     help="run only the per-step timing of every multi-column variant")
     ap.add_argument("--profile-only", action="store_true",
@@ -596,6 +631,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     ctx = pk.Context(0)
+    if args.gemm_shapes:
+        print(json.dumps({"mode": "gemm-shapes", "gemm": gemm_leg(pk, ctx)}))
+        return
     if args.batch_variants:
         print(json.dumps({"mode": "batch-variants",
                           "batch_variants": batch_variant_leg(pk, wl, ctx)}))
