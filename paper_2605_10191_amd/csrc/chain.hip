@@ -35,6 +35,8 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
+#include <tuple>
 #include <utility>
 
 #include "chain_dev.hpp"
@@ -659,6 +661,9 @@ __global__ __launch_bounds__(kTileThreads) void k_chain_tile(
   }
 }
 
+// XCDs of the device: the staged-tile table carries this many ranges.
+constexpr int kWtXcds = 8;
+
 // Staged-tile kernel.  A tile is the set of rows whose state bits outside
 // [0, Lb + KT) (and, for a wrapped tile, outside the top bit L - 1) are
 // fixed: 2^WR runs of 2^KT consecutive high parts, each run a contiguous
@@ -711,8 +716,10 @@ __global__ __launch_bounds__(NT) void k_chain_wt(
 
   const int xcd = blockIdx.x % nxcd;
   const int wg = blockIdx.x / nxcd, nwg = gridDim.x / nxcd;
-  const int t_begin = (int)((int64_t)ntiles * xcd / nxcd);
-  const int t_end = (int)((int64_t)ntiles * (xcd + 1) / nxcd);
+  // the XCD's range of the tile table (row-balanced bounds after the
+  // entries; one XCD takes them all)
+  const int t_begin = nxcd == kWtXcds ? uniform(tiles[8 * ntiles + xcd]) : 0;
+  const int t_end = nxcd == kWtXcds ? uniform(tiles[8 * ntiles + xcd + 1]) : ntiles;
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const T vzz = (T)c.vzz, t_in = (T)c.t_in, t_pb = (T)c.t_pb;
@@ -907,6 +914,8 @@ static const polfed_op::WTiles* wt_tables(const polfed_op* op, int kt, int wrap)
   const int64_t nt = (int64_t)1 << (Lh - kt - wrap);
   TallyScope untallied(nullptr);  // the table lives as long as the operator
   std::vector<int32_t> tab;
+  std::vector<int64_t> tid;   // the tile index t of each entry
+  std::vector<int> trows;     // its rows
   for (int64_t t = 0; t < nt; ++t) {
     int32_t e[8] = {0};
     int rows_tot = 0, bufr[2] = {0, 0}, slots = 0;
@@ -925,12 +934,59 @@ static const polfed_op::WTiles* wt_tables(const polfed_op* op, int kt, int wrap)
     }
     if (rows_tot == 0) continue;
     tab.insert(tab.end(), e, e + 8);
+    tid.push_back(t);
+    trows.push_back(rows_tot);
     for (int p = 0; p < 2; ++p) W.buf_rows[p] = std::max(W.buf_rows[p], bufr[p]);
     W.rec_slots = std::max(W.rec_slots, slots);
   }
   W.kt = kt;
   W.wrap = wrap;
   W.n = (int)(tab.size() / 8);
+  // Order of the tiles and their split over the XCDs.  A hop across a bond
+  // between two fixed bits of a tile swaps them, which keeps the popcount of
+  // the fixed bits t; only the bonds at the ends of the fixed range change
+  // it.  Tiles sorted by popcount(t), then by the popcount of the upper half
+  // of t (swaps inside either half keep it), then by t, therefore keep most
+  // of their global gathers inside a contiguous range of the table, and each
+  // XCD takes such a range, cut where the rows (not the tiles) are balanced.
+  // Hopping gathers sent to another XCD's range, counted over the sector:
+  // 26.6% instead of 39.9% in plain t order at L = 24, 22.1% instead of
+  // 33.2% at L = 26, 38.8% instead of 50.3% at L = 22.
+  const int tbits = Lh - kt - wrap, thalf = (tbits + 1) / 2;
+  std::vector<int> ord(W.n);
+  std::iota(ord.begin(), ord.end(), 0);
+  auto order_key = [&](int x) {
+    const unsigned long long t = (unsigned long long)tid[x];
+    return std::make_tuple(__builtin_popcountll(t), __builtin_popcountll(t >> (tbits - thalf)),
+                           tid[x]);
+  };
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int x, int y) { return order_key(x) < order_key(y); });
+  std::vector<int32_t> sorted;
+  sorted.reserve(tab.size() + kWtXcds + 1);
+  int64_t rows_all = 0;
+  for (int i : ord) {
+    sorted.insert(sorted.end(), tab.begin() + 8 * (size_t)i, tab.begin() + 8 * (size_t)i + 8);
+    rows_all += trows[i];
+  }
+  // XCD x takes entries [bound[x], bound[x + 1]): bound[x] is the first
+  // entry whose rows before it reach x/8 of all rows
+  int64_t cum = 0;
+  int x = 1;
+  sorted.push_back(0);
+  for (int k = 0; k < W.n && x < kWtXcds; ++k) {
+    while (x < kWtXcds && cum >= rows_all * x / kWtXcds) {
+      sorted.push_back(k);
+      ++x;
+    }
+    cum += trows[ord[k]];
+  }
+  while (x < kWtXcds) {
+    sorted.push_back(W.n);
+    ++x;
+  }
+  sorted.push_back(W.n);
+  tab.swap(sorted);
   upload(W.d, tab.data(), tab.size(), op->ctx->stream);
   HIPC(hipStreamSynchronize(op->ctx->stream));
   return W.n > 0 ? &W : nullptr;
@@ -967,8 +1023,8 @@ static bool launch_wt(hipStream_t s, const polfed_op* op, T sigma, T tau, T a, c
   int64_t grid = std::min<int64_t>(W->n, (int64_t)op->ctx->n_cu * per_cu);
   int nxcd = 1;
   if (grid >= 64) {
-    grid -= grid % 8;
-    nxcd = 8;
+    grid -= grid % kWtXcds;
+    nxcd = kWtXcds;
   }
   grid = std::max<int64_t>(grid, 1);
   hipLaunchKernelGGL((k_chain_wt<T, L, KT, WR, DB, NT>), dim3((unsigned)grid), dim3(NT), shm, s,
