@@ -571,6 +571,26 @@ def gemm_leg(pk, ctx, reps=3):
     return out
 
 
+def serving_child(args, precision: str) -> dict:
+    """One serving stream run by `bench.py --serve-only` in a child process
+    (its progress on this process's stderr); its result, or what ended it."""
+    import subprocess
+    cmd = [sys.executable, "-X", "faulthandler", os.path.abspath(__file__), "--serve-only",
+           "--serve-precision", precision, "--serve-requests", str(args.serve_requests),
+           "--serve-budget-gb", str(args.serve_budget_gb), "--serve-cols", str(args.serve_cols),
+           "--serve-rate", str(args.serve_rate)]
+    if args.serve_arrival is not None:
+        cmd += ["--serve-arrival", str(args.serve_arrival)]
+    try:
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    except OSError as e:
+        return {"error": f"serving process not started: {e}", "precision": precision}
+    lines = [ln for ln in p.stdout.splitlines() if ln.startswith("{")]
+    if p.returncode == 0 and lines:
+        return json.loads(lines[-1])["serving"][precision]
+    return {"error": f"serving process ended with status {p.returncode}", "precision": precision}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -773,14 +793,15 @@ def main():
         out["qrem_paper_shape"] = qrem_leg(pk, wl, ctx, args.qrem_L, args.qrem_pairs,
                                            args.qrem_block)
     if not args.no_serve:
-        sv = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
-                         args.serve_cols, pk.AUTO, rate=args.serve_rate)
-        out["p50_p99_batched_solve_ms"] = [sv["p50_ms"], sv["p99_ms"]]
+        # each serving stream in a process of its own: its result, or the
+        # failure of that process, without ending this one
+        sv = serving_child(args, "auto")
+        out["p50_p99_batched_solve_ms"] = ([sv["p50_ms"], sv["p99_ms"]] if "p50_ms" in sv
+                                           else None)
         out["serving"] = sv
         log(f"serving: {sv}")
         if not args.serve_one_leg:
-            sv32 = serving_leg(pk, wl, ctx, args.serve_requests, args.serve_budget_gb,
-                               args.serve_cols, pk.FP32, rate=args.serve_rate)
+            sv32 = serving_child(args, "fp32")
             out["serving_fp32_bulk"] = sv32
             log(f"serving fp32 bulk: {sv32}")
     else:
