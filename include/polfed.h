@@ -57,8 +57,9 @@ enum { POLFED_FP64 = 0, POLFED_FP32 = 1 };        /* Clenshaw precision */
 /* polfed_params.precision only (solves, batches, served requests): FP32 bulk
  * filtering with FP64 refinement when the operator's FP32 Clenshaw step runs
  * in less than 0.7 of the FP64 step's time, else FP64.  The two steps are
- * timed (graph replays of 20 launches on scratch vectors, about 3 D-vectors
- * of device memory for the duration) at the first such solve of an operator,
+ * timed (graph replays of 20 launches on scratch vectors, eager launches on
+ * the server's threads; about 3 D-vectors of device memory for the
+ * duration) at the first such solve of an operator,
  * or of any chain operator with the same off-diagonal pattern and storage on
  * the device, and the choice is kept; polfed_report.precision says which
  * ran.  The refinement costs about 40% of the FP32 filter time, so FP32 bulk
@@ -463,7 +464,11 @@ typedef struct {
                           first two filter applications (a multi-column
                           filter reuses the pick of an earlier batch of the
                           same chain pattern, width, precision and order to a
-                          factor of two), 1 = always graph, 2 = never */
+                          factor of two), 1 = always graph, 2 = never.
+                          Served requests always launch directly (the
+                          server's threads capture no graphs: a device
+                          synchronization or synchronous copy on another
+                          thread would invalidate the capture). */
   int refine_max;      /* FP32 bulk: at most this many refinement sweeps
                           (0: 16; -1: none); a refinement that stalls or
                           runs out hands the solve to the FP64 filter */
