@@ -71,15 +71,22 @@ struct DeviceGuard {
 // buckets (powers of two up to 1 MiB, then 2 MiB multiples) so that blocks
 // of a repeating workload fit each other.
 namespace {
+// A fence event and the stream it was recorded on.  Events never outlive
+// their stream: when a stream is unregistered (after its work has drained,
+// before it is destroyed), the events recorded on it are destroyed.
+struct Fence {
+  hipStream_t s;
+  hipEvent_t e;
+};
 struct CachedBlock {
   void* p;
-  std::vector<hipEvent_t> fence;
+  std::vector<Fence> fence;
 };
 struct DevicePool {
   std::mutex mu;
   std::vector<hipStream_t> streams;  // work streams (one entry per registration)
   std::multimap<size_t, CachedBlock> blocks;  // by bucket size
-  std::vector<hipEvent_t> spare;             // events of reused blocks
+  std::vector<Fence> spare;                  // events of reused blocks (s: last stream)
   size_t cached = 0, cap = 0;
 };
 
@@ -128,8 +135,8 @@ struct QuietDevice {
 };
 
 bool fence_passed(const CachedBlock& c) {
-  for (hipEvent_t e : c.fence) {
-    const hipError_t q = hipEventQuery(e);
+  for (const Fence& f : c.fence) {
+    const hipError_t q = hipEventQuery(f.e);
     if (q == hipSuccess) continue;
     (void)hipGetLastError();  // a pending event is no error of a later call
     return false;
@@ -142,9 +149,9 @@ bool fence_passed(const CachedBlock& c) {
 // graph capture in progress (and fail itself).
 void flush_pool(DevicePool& P) {
   for (auto& kv : P.blocks) {
-    for (hipEvent_t e : kv.second.fence) {
-      (void)hipEventSynchronize(e);
-      P.spare.push_back(e);
+    for (const Fence& f : kv.second.fence) {
+      (void)hipEventSynchronize(f.e);
+      P.spare.push_back(f);
     }
     (void)hipFree(kv.second.p);
   }
@@ -167,6 +174,23 @@ void unregister_stream(int dev, hipStream_t s) {
   std::lock_guard<std::mutex> lk(P.mu);
   auto it = std::find(P.streams.begin(), P.streams.end(), s);
   if (it != P.streams.end()) P.streams.erase(it);
+  if (std::find(P.streams.begin(), P.streams.end(), s) == P.streams.end()) {
+    // the stream's work has drained (callers synchronize it first): its
+    // fence events have completed and are destroyed while it still exists
+    for (auto& kv : P.blocks) {
+      auto& fv = kv.second.fence;
+      for (const Fence& f : fv)
+        if (f.s == s) (void)hipEventDestroy(f.e);
+      fv.erase(std::remove_if(fv.begin(), fv.end(), [&](const Fence& f) { return f.s == s; }),
+               fv.end());
+    }
+    for (const Fence& f : P.spare)
+      if (f.s == s) (void)hipEventDestroy(f.e);
+    P.spare.erase(std::remove_if(P.spare.begin(), P.spare.end(),
+                                 [&](const Fence& f) { return f.s == s; }),
+                  P.spare.end());
+    (void)hipGetLastError();
+  }
   // the last stream gone: nothing of the library runs on the device any
   // more, so the cached blocks go back to the device
   if (P.streams.empty()) flush_pool(P);
@@ -186,7 +210,7 @@ void DevBuf::alloc(size_t bytes) {
     for (auto it = range.first; it != range.second; ++it)
       if (fence_passed(it->second)) {
         p = it->second.p;
-        for (hipEvent_t e : it->second.fence) P.spare.push_back(e);
+        for (const Fence& f : it->second.fence) P.spare.push_back(f);
         P.blocks.erase(it);
         P.cached -= cap;
         break;
@@ -244,14 +268,14 @@ void DevBuf::release() {
           }
           hipEvent_t e = nullptr;
           if (!P.spare.empty()) {
-            e = P.spare.back();
+            e = P.spare.back().e;
             P.spare.pop_back();
           } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
             ok = false;
             break;
           }
-          c.fence.push_back(e);
+          c.fence.push_back({s, e});
           if (hipEventRecord(e, s) != hipSuccess) {
             (void)hipGetLastError();
             ok = false;
@@ -263,7 +287,7 @@ void DevBuf::release() {
           P.cached += cap_;
           cached = true;
         } else {
-          for (hipEvent_t e : c.fence) P.spare.push_back(e);
+          for (const Fence& f : c.fence) P.spare.push_back(f);
         }
       }
     }

@@ -91,6 +91,11 @@ struct Server {
     bool busy = false;
   };
   std::map<std::string, std::unique_ptr<Group>> groups;
+  // streams of groups that ended, for the next new group: a group's stream
+  // lives until the server stops, since events recorded on it (a member's
+  // ready event, its timing events) can outlive the group when the member
+  // moves on to another group
+  std::vector<polfed_ctx*> spare_ctx;
   // a round that ended, with the members that finished in it
   struct Done {
     Group* g = nullptr;
@@ -188,7 +193,12 @@ Server::~Server() {
   }
   pcv.notify_all();
   for (auto& t : pool) t.join();
-  for (auto& kv : groups) delete_child(kv.second->gc);
+  // every request has finished: the groups' events go before their streams
+  for (auto& kv : groups) {
+    kv.second->bf.forget();
+    delete_child(kv.second->gc);
+  }
+  for (polfed_ctx* c : spare_ctx) delete_child(c);
 }
 
 static std::string group_key(const polfed_req* r) {
@@ -480,7 +490,8 @@ void Server::loop() {
     }
     for (auto it = groups.begin(); it != groups.end();) {
       if (!it->second->busy && !by_key.count(it->first)) {
-        delete_child(it->second->gc);
+        it->second->bf.forget();
+        spare_ctx.push_back(it->second->gc);
         it = groups.erase(it);
       } else {
         ++it;
@@ -491,7 +502,12 @@ void Server::loop() {
       std::unique_ptr<Group>& gp = groups[kv.first];
       if (!gp) {
         gp.reset(new Group());
-        gp->gc = new_child(ctx);
+        if (!spare_ctx.empty()) {
+          gp->gc = spare_ctx.back();
+          spare_ctx.pop_back();
+        } else {
+          gp->gc = new_child(ctx);
+        }
       }
       if (gp->busy) continue;  // the new members join its next round
       bool clash = false;
