@@ -530,7 +530,13 @@ void Server::loop() {
     for (auto* r : waiting) {
       try {
         TallyScope ts(&r->run->tally);
+        // on this thread's stream, after the solve's last work (its group
+        // may have ended and handed its stream to another group); the next
+        // round of the solve waits for what resume queues here
+        HIPC(hipStreamWaitEvent(ctx->stream, r->ready, 0));
+        r->run->ctx = ctx;
         r->run->resume();
+        HIPC(hipEventRecord(r->ready, ctx->stream));
         if (!r->run->blocked()) progress = true;
         if (r->run->done) complete(r, r->run->status, "");
       } catch (const Error& e) {
